@@ -1,0 +1,176 @@
+"""Benchmark of the MV/FFC hot path on one MI355X.
+
+Headline: MotionValidation with robot-obstacle, self and robot-robot checks on
+the four-arm workload (4 seeded 7-R arms x 60 spheres, 20 boxes + 8 cylinders,
+65,536 straight-line motions at 1/32 rad max-joint step), every state evaluated
+(exhaustive mode), inputs resident in HBM.  One step = one mrv_mv_device call
+over all 65,536 motions.  ``value`` = robot-states validated per second.
+
+Also reported (``extra``): early-exit MV on the same motions, FFC on the
+4-arm + 4-rectangle decoupled-path workload (16,384 path sets), the disk
+workload, the FP32 roofline of the validation kernel and the FP64 oracle on the
+host cores (``cpu_baseline``).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# FLOP per unit of work ("Roofline and FLOP convention").
+FLOP_SPHERE_SPHERE = 10     # 3 sub, |d|^2 5, (ra+rb)^2 2
+FLOP_SPHERE_BOX = 26
+FLOP_SPHERE_CYL = 26
+FLOP_REV_JOINT = 30         # interpolation 3, translation 9, Rz composition 18
+FLOP_PRI_JOINT = 12
+FLOP_SPHERE_PLACE = 18
+PEAK_FP32_VALU = 157.3e12   # MI355X FP32 vector peak (published)
+
+
+def per_timestep_flop(team, env, check_env=True):
+    """Algorithmic FLOP to validate one timestep of the whole team."""
+    from paper_2604_23960_amd import workloads as W
+    ns = [r.n_spheres for r in team]
+    rr = sum(ns[i] * ns[j] for i in range(len(ns)) for j in range(i + 1, len(ns))) * FLOP_SPHERE_SPHERE
+    fk = 0
+    for r in team:
+        fk += sum(FLOP_REV_JOINT if jt == W.REV_Z else FLOP_PRI_JOINT for jt in r.joint_type)
+        fk += r.n_spheres * FLOP_SPHERE_PLACE
+    envf = 0
+    if check_env:
+        S = sum(ns)
+        envf = S * (len(env.boxes) * FLOP_SPHERE_BOX + len(env.cylinders) * FLOP_SPHERE_CYL +
+                    len(env.spheres) * FLOP_SPHERE_SPHERE)
+        envf += sum(len(r.self_pairs) for r in team) * FLOP_SPHERE_SPHERE
+    return rr + fk + envf
+
+
+def run_device(ctx, team, env, dp, kind, flags, out, steps, warmup):
+    import torch
+    call = (lambda: ctx.mv_device(team, env, dp, flags, out.data_ptr())) if kind == 0 else \
+        (lambda: ctx.ffc_device(team, dp, flags, out.data_ptr()))
+    for _ in range(warmup):
+        call()
+    ctx.sync()
+    torch.cuda.synchronize()
+    kernel_ms = []
+    stats = None
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        call()
+        stats = ctx.last_stats()          # waits for the step; reads the kernel's HIP-event time
+        kernel_ms.append(stats["kernel_ms"])
+    ctx.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, kernel_ms, stats
+
+
+def cpu_baseline(w, max_queries):
+    import oracle
+    n = w.paths.n_queries
+    sub = w.paths.subset(np.arange(min(n, max_queries)))
+    ot, oe, op = oracle.Team(w.team), oracle.Env(w.env), oracle.Paths(sub)
+    oracle.mv(ot, oe, oracle.Paths(sub.subset(np.arange(min(8, sub.n_queries)))))   # warm the library
+    t0 = time.perf_counter()
+    valid, fh = oracle.mv(ot, oe, op, first_hit=True)
+    dt = time.perf_counter() - t0
+    T = sub.horizon()
+    covered = float(np.sum(T) * len(w.team))
+    evaluated = float(np.sum(np.where(fh < 0, T, fh + 1)) * len(w.team))
+    return dict(value=covered / dt, unit="robot-states/s", cores=int(oracle.threads()), kind="oracle",
+                sample=(f"MV (env on, early exit as the oracle scans) over the first {sub.n_queries} motions of the "
+                        f"same workload; {dt:.2f} s wall; covered states/s shown; states scanned before exit/s = "
+                        f"{evaluated / dt:.3g}; {valid.mean() * 100:.1f}% valid"))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--queries", type=int, default=65536)
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-queries", type=int, default=65536)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2604_23960_amd import mrv
+    from paper_2604_23960_amd import workloads as W
+
+    def log(*a):
+        print("[bench]", *a, file=sys.stderr, flush=True)
+
+    log("generating the four-arm workload")
+    w = W.arms_workload(args.queries)
+    ctx = mrv.Context(0)
+    team, env = ctx.load_team(w.team), ctx.load_env(w.env)
+    dp = mrv.DevicePaths(w.paths)
+    out = torch.zeros(w.paths.n_queries, dtype=torch.uint8, device="cuda")
+    flags = mrv.CHECK_ENV | mrv.EXHAUSTIVE
+    log("timing exhaustive MV")
+    wall, kms, st = run_device(ctx, team, env, dp, 0, flags, out, args.steps, args.warmup)
+    states = st["states_evaluated"]
+    value = states * args.steps / wall
+    ms_per_step = wall / args.steps * 1e3
+    kernel_ms = float(np.mean(kms))
+    ts = states / len(w.team)
+    flop = ts * per_timestep_flop(w.team, w.env, True)
+    achieved = flop / (kernel_ms * 1e-3)
+    roofline = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_FP32_VALU / 1e12, unit="TFLOP/s",
+                    frac=achieved / PEAK_FP32_VALU, traffic=None, kernel="k_validate<MV>",
+                    kernel_ms=kernel_ms, flop_per_launch=flop)
+    extra = dict(states_covered=st["states_covered"], rr_tests=st["rr_tests"], env_tests=st["env_tests"],
+                 self_tests=st["self_tests"], near_rechecks=st["near_rechecks"],
+                 pair_tests_per_s=(st["rr_tests"] + st["env_tests"] + st["self_tests"]) / (kernel_ms * 1e-3),
+                 valid_fraction=float(out.float().mean().item()))
+    if not args.no_extra:
+        log("timing early-exit MV")
+        wall2, kms2, st2 = run_device(ctx, team, env, dp, 0, mrv.CHECK_ENV, out, 5, 1)
+        extra["mv_early_exit"] = dict(covered_states_per_s=st2["states_covered"] * 5 / wall2,
+                                      evaluated_states_per_s=st2["states_evaluated"] * 5 / wall2,
+                                      ms_per_call=wall2 / 5 * 1e3, effort=st2["states_evaluated"] / st2["states_covered"])
+        log("timing FFC on the arm + rectangle workload")
+        wf = W.ffc_workload(16384)
+        tf = ctx.load_team(wf.team)
+        dpf = mrv.DevicePaths(wf.paths)
+        cf = torch.zeros((wf.paths.n_queries, 3), dtype=torch.int32, device="cuda")
+        wall3, kms3, st3 = run_device(ctx, tf, -1, dpf, 1, 0, cf, 5, 1)
+        extra["ffc_hetero"] = dict(queries=wf.paths.n_queries, ms_per_call=wall3 / 5 * 1e3,
+                                   covered_states_per_s=st3["states_covered"] * 5 / wall3,
+                                   evaluated_states_per_s=st3["states_evaluated"] * 5 / wall3,
+                                   null_fraction=float((cf[:, 0] < 0).float().mean().item()))
+        wall4, kms4, st4 = run_device(ctx, tf, -1, dpf, 1, mrv.EXHAUSTIVE, cf, 3, 1)
+        extra["ffc_hetero_exhaustive"] = dict(ms_per_call=wall4 / 3 * 1e3,
+                                              states_per_s=st4["states_evaluated"] * 3 / wall4)
+    cpu = None
+    if not args.no_cpu:
+        log("timing the FP64 oracle on the host")
+        cpu = cpu_baseline(w, args.cpu_queries)
+        extra["gpu_covered_states_per_s_early_exit_same_metric"] = extra.get("mv_early_exit", {}).get(
+            "covered_states_per_s")
+    line = dict(metric="robot-states validated/s", value=value, unit="robot-states/s", n_gpus=1,
+                steps=args.steps, warmup=args.warmup, ms_per_step=ms_per_step, higher_is_better=True,
+                scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
+                config=dict(workload="arms-4x7R-60sph-20box-8cyl MV exhaustive (env+self+robot-robot)",
+                            motions=w.paths.n_queries, robots=len(w.team), spheres_per_robot=60,
+                            boxes=20, cylinders=8, step="1/32 rad Linf", precision="fp32 + fp64 near-contact recheck"),
+                roofline=roofline, cpu_baseline=cpu, extra=extra)
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,226 @@
+/*
+ * mrv.h -- C ABI of libmrv: multi-robot MotionValidation (MV) and
+ * FindFirstConflict (FFC) on an AMD Instinct MI355X (gfx950).
+ *
+ * The problem (paper §III-A, Alg. 1 input; §III-B, Alg. 2 input): a team of
+ * robots, each a set of spheres attached to a kinematic chain (paper §II-B:
+ * sphere-based robot representation), an obstacle set, and one timed path per
+ * robot.  The state of robot i at integer timestep t is the linear
+ * interpolation of its waypoints around t, and its last waypoint for every t at
+ * or after the last waypoint time (padding, §III-A).  T = max_i L_i with
+ * L_i = last waypoint time + 1.
+ *
+ *   MV  = true iff at every t in [0, T) no robot collides with an obstacle or
+ *         itself (only with MRV_CHECK_ENV) and no two robots collide (§III-A).
+ *   FFC = the lexicographically smallest (t, i, j), i < j, such that robots i
+ *         and j collide at t; (-1, -1, -1) when there is none (§III-B).
+ *
+ * A pair of spheres collides iff its signed clearance is < 0 (touching is
+ * free).  Arithmetic is FP32 with an FP64 re-evaluation of every test whose FP32
+ * clearance lies within `near_eps` metres of zero, so the booleans and
+ * (t, i, j) equal those of an FP64 evaluation.
+ *
+ * Conventions for every entry point:
+ *  - Return value: MRV_OK (0) or a negative mrv_status.  On error nothing is
+ *    written to any output and mrv_last_error() describes the failure.  No
+ *    C++ exception crosses this boundary.
+ *  - Ownership: the caller owns every array it passes.  Host arrays are read
+ *    (and copied where needed) before the call returns.  Device arrays passed to
+ *    the *_device entry points must stay valid until the work on the context
+ *    stream has completed (mrv_sync).
+ *  - Threading: mrv_submit, mrv_poll, mrv_wait and mrv_cancel may be called from
+ *    any thread.  Every other call on one context must come from one thread at a
+ *    time.
+ *  - Layouts: all transforms are 3x4 row-major [R | p] (12 doubles).  All
+ *    arrays are dense and C-ordered.
+ */
+#ifndef MRV_H
+#define MRV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mrv_status;
+enum {
+    MRV_OK = 0,
+    MRV_PENDING = 1,         /* mrv_poll: the request has not finished yet */
+    MRV_E_INVALID = -1,      /* malformed argument or input data */
+    MRV_E_NOMEM = -2,        /* device or host allocation failed */
+    MRV_E_DEVICE = -3,       /* a HIP runtime call failed */
+    MRV_E_BUSY = -4,         /* request queue full, or handle still in use */
+    MRV_E_HANDLE = -5,       /* unknown context, team, environment or ticket */
+    MRV_E_CANCELLED = -6,    /* the request was cancelled */
+    MRV_E_TIMEOUT = -7       /* mrv_wait ran out of time */
+};
+
+/* Limits enforced by validation. */
+#define MRV_MAX_ROBOTS 32
+#define MRV_MAX_JOINTS 8
+#define MRV_MAX_SPHERES_PER_ROBOT 256
+#define MRV_MAX_TEAM_SPHERES 2048
+#define MRV_MAX_T (1 << 20)
+
+typedef struct mrv_ctx_s* mrv_ctx;
+
+typedef struct {
+    int32_t device;        /* HIP device ordinal */
+    void* stream;          /* hipStream_t to order all work on; NULL = the library creates one */
+    double near_eps;       /* near-contact band in metres; <= 0 selects 1e-5 */
+    int32_t max_inflight;  /* serving: queue capacity in requests; <= 0 selects 1024 */
+    size_t serve_bytes;    /* serving: device bytes for admitted requests; 0 selects 256 MiB */
+    uint32_t flags;        /* reserved, must be 0 */
+} mrv_ctx_opts;
+
+/* Create a context on opts->device.  *out receives the handle. */
+mrv_status mrv_create(const mrv_ctx_opts* opts, mrv_ctx* out);
+/* Release the context, its resident teams and environments, and its device memory.
+ * Pending requests are cancelled.  NULL is accepted. */
+mrv_status mrv_destroy(mrv_ctx ctx);
+/* Message for the last failing call on this thread ("" if none).  Valid until the
+ * next call on this thread. */
+const char* mrv_last_error(void);
+
+/* ---------------------------------------------------------------- robots */
+enum { MRV_REV_Z = 0, MRV_PRI_X = 1, MRV_PRI_Y = 2, MRV_PRI_Z = 3 };
+
+/* One robot: a serial chain and the spheres on its frames (paper §II-B).
+ * Frame_0 = base, Frame_k = Frame_{k-1} F_k J_k(q_k), J a rotation about local z
+ * (MRV_REV_Z) or a translation along local x/y/z (MRV_PRI_*).  Sphere s sits at
+ * Frame_{sphere_frame[s]} c_s. */
+typedef struct {
+    int32_t n_joints;               /* 0..MRV_MAX_JOINTS; also the robot's dof */
+    const int32_t* joint_type;      /* [n_joints] */
+    const double* joint_fixed;      /* [n_joints][12] F_k */
+    int32_t n_spheres;              /* 1..MRV_MAX_SPHERES_PER_ROBOT */
+    const int32_t* sphere_frame;    /* [n_spheres] in 0..n_joints */
+    const double* sphere_xyzr;      /* [n_spheres][4] local centre and radius (> 0) */
+    int32_t n_self_pairs;           /* >= 0 */
+    const int32_t* self_pairs;      /* [n_self_pairs][2] sphere indices a != b: self-collision pairs */
+    double base[12];                /* world-from-base transform */
+} mrv_robot_desc;
+
+/* Upload a team (host arrays, copied) and keep it resident.  Robot order
+ * defines the robot indices reported by FFC.  *team_out receives the handle. */
+mrv_status mrv_load_team(mrv_ctx ctx, const mrv_robot_desc* robots, int32_t n_robots,
+                         int32_t* team_out);
+
+/* ---------------------------------------------------------- environments */
+/* Obstacles in the world frame (paper §III-A: environment geometry per robot
+ * frame; here one world-frame copy serves every robot, see DESIGN notes). */
+typedef struct {
+    int32_t n_spheres; const double* spheres;      /* [n][4] centre, radius */
+    int32_t n_boxes;   const double* boxes;        /* [n][15] centre, R (row-major 3x3), half-extents */
+    int32_t n_cyls;    const double* cylinders;    /* [n][8] centre, unit axis, half-length, radius */
+    int64_t n_points;  const double* points;       /* [n][3] point obstacles of radius point_radius */
+    double point_radius;                           /* >= 0 */
+    double grid_cell;                              /* point-grid cell size in metres; <= 0 selects 0.05 */
+} mrv_env_desc;
+
+/* Upload an environment (host arrays, copied).  *env_out receives the handle. */
+mrv_status mrv_load_env(mrv_ctx ctx, const mrv_env_desc* env, int32_t* env_out);
+
+/* Drop a team or environment handle.  MRV_E_BUSY while a served request uses it. */
+mrv_status mrv_unload(mrv_ctx ctx, int32_t handle);
+
+/* ----------------------------------------------------------------- paths */
+/* Query-major CSR over per-robot timed waypoint lists.  Path (q, r) is
+ * waypoints [wp_begin[q*n_robots + r], wp_begin[q*n_robots + r + 1]).  Its first
+ * time is 0, times strictly increase, the last time is < MRV_MAX_T, and the
+ * configurations are finite.  wp_q rows hold dof_stride doubles (the team's
+ * largest dof; a robot reads its first n_joints values). */
+typedef struct {
+    int32_t n_queries;
+    int32_t dof_stride;
+    const int64_t* wp_begin;   /* [n_queries * n_robots + 1], wp_begin[0] = 0 */
+    const int32_t* wp_t;       /* [n_wp] */
+    const double* wp_q;        /* [n_wp][dof_stride] */
+    int64_t n_wp;              /* number of waypoints = wp_begin[last] */
+} mrv_paths;
+
+typedef struct { int32_t t, ri, rj; } mrv_conflict;   /* (-1, -1, -1): no conflict */
+
+/* Per-call flags. */
+enum {
+    MRV_CHECK_ENV = 1,       /* MV: check robot-obstacle and self collision too */
+    MRV_EXHAUSTIVE = 2,      /* evaluate every test (no early termination); same answers */
+    MRV_HIERARCHICAL = 4,    /* MV: all environment tiles before robot-robot tiles (Alg. 1) */
+    MRV_ORDER_BISECT = 0,    /* MV tile order: rake tiles in golden-ratio interleave (default) */
+    MRV_ORDER_RAKE = 8,      /* MV tile order: the paper's rake, batches in index order */
+    MRV_ORDER_LINEAR = 16    /* MV tile order: consecutive timesteps (FFC always uses this) */
+};
+
+/* MV over host arrays; synchronous.  valid_out[q] = 1 valid, 0 invalid.
+ * env = -1 runs without obstacles (self checks still run with MRV_CHECK_ENV). */
+mrv_status mrv_mv(mrv_ctx ctx, int32_t team, int32_t env, const mrv_paths* paths, uint32_t flags,
+                  uint8_t* valid_out);
+/* FFC over host arrays; synchronous.  out[q] = earliest conflict of query q. */
+mrv_status mrv_ffc(mrv_ctx ctx, int32_t team, const mrv_paths* paths, uint32_t flags,
+                   mrv_conflict* out);
+
+/* Device-resident variants: every pointer in *paths and the output point to
+ * device memory of the context's device.  Work is queued on the context stream
+ * and the call returns without waiting.  Inputs are checked on the device; a
+ * query whose path data break the rules above gets valid_out = 2 (MV) or
+ * t = -2 (FFC), and the next mrv_sync returns MRV_E_INVALID.  The context
+ * keeps per-call scratch, so results are complete only after mrv_sync or an
+ * equivalent stream synchronisation. */
+mrv_status mrv_mv_device(mrv_ctx ctx, int32_t team, int32_t env, const mrv_paths* paths,
+                         uint32_t flags, uint8_t* valid_out);
+mrv_status mrv_ffc_device(mrv_ctx ctx, int32_t team, const mrv_paths* paths, uint32_t flags,
+                          mrv_conflict* out);
+/* Wait for the context stream; report device-side input errors since the last sync. */
+mrv_status mrv_sync(mrv_ctx ctx);
+
+/* Timesteps for a straight-line motion dq: ceil(|dq| / step) with the L2
+ * (metric 0) or L-infinity (metric 1) norm (paper §IV-A: bounded C-space motion
+ * per timestep).  Returns -1 on invalid arguments. */
+int64_t mrv_motion_steps(const double* dq, int32_t dof, double step, int32_t metric);
+
+/* ------------------------------------------------------------- tuning/stats */
+typedef struct {
+    int32_t chunk;           /* timesteps per tile; 0 = automatic */
+    int32_t wg_per_cu;       /* persistent workgroups per compute unit; 0 = occupancy limit */
+} mrv_tiling;
+/* Set the tiling used for (team, kind) where kind 0 = MV, 1 = FFC. */
+mrv_status mrv_set_tiling(mrv_ctx ctx, int32_t team, int32_t kind, const mrv_tiling* tiling);
+mrv_status mrv_get_tiling(mrv_ctx ctx, int32_t team, int32_t kind, mrv_tiling* tiling);
+
+typedef struct {
+    uint64_t tiles_run, tiles_skipped;
+    uint64_t states_evaluated;   /* robot-states run through FK and tests */
+    uint64_t states_covered;     /* sum over queries of n_robots * T */
+    uint64_t rr_tests, env_tests, self_tests;
+    uint64_t near_rechecks;      /* tests re-evaluated in FP64 */
+    double kernel_ms;            /* validation kernel time of the last call (device events) */
+} mrv_stats;
+/* Counters of the last MV/FFC call on this context (synchronises the stream). */
+mrv_status mrv_last_stats(mrv_ctx ctx, mrv_stats* out);
+
+/* --------------------------------------------------------------- serving */
+typedef struct {
+    int32_t kind;            /* 0 = MV, 1 = FFC */
+    int32_t team, env;       /* env = -1: none */
+    uint32_t flags;
+    mrv_paths paths;         /* host arrays, copied by mrv_submit */
+} mrv_request;
+
+/* Queue a request for the serving loop; returns once its inputs are copied.
+ * MRV_E_BUSY when max_inflight requests are queued or running. */
+mrv_status mrv_submit(mrv_ctx ctx, const mrv_request* req, uint64_t* ticket);
+/* MRV_OK and the result in out (uint8[n_queries] for MV, mrv_conflict[n_queries]
+ * for FFC; the ticket is then released), MRV_PENDING, or an error. */
+mrv_status mrv_poll(mrv_ctx ctx, uint64_t ticket, void* out);
+/* Like mrv_poll but waits up to timeout_ms (< 0: forever). */
+mrv_status mrv_wait(mrv_ctx ctx, uint64_t ticket, int32_t timeout_ms, void* out);
+/* Cancel a queued or running request; its ticket then reports MRV_E_CANCELLED once. */
+mrv_status mrv_cancel(mrv_ctx ctx, uint64_t ticket);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MRV_H */

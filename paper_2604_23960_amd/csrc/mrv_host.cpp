@@ -1,0 +1,950 @@
+// Host runtime of libmrv: context, resident teams and environments, input
+// validation, scratch management and the MV/FFC call pipeline.  The C ABI is
+// declared in include/mrv.h; every exported function catches everything and
+// reports through mrv_last_error().
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/mrv.h"
+#include "mrv_internal.hpp"
+#include "mrv_runtime.hpp"
+
+using namespace mrv;
+
+namespace {
+
+thread_local std::string g_err;
+
+mrv_status fail(mrv_status s, const std::string& msg)
+{
+    g_err = msg;
+    return s;
+}
+
+// Packs host arrays into one device allocation, 256-byte aligned pieces.
+struct Packer {
+    std::vector<unsigned char> bytes;
+    size_t add(const void* src, size_t n)
+    {
+        size_t off = (bytes.size() + 255) & ~size_t(255);
+        bytes.resize(off + std::max<size_t>(n, 1), 0);
+        if (n) std::memcpy(bytes.data() + off, src, n);
+        return off;
+    }
+    template <class T>
+    size_t add(const std::vector<T>& v) { return add(v.data(), v.size() * sizeof(T)); }
+};
+
+struct TeamHost {
+    TeamDev dev{};
+    void* dmem = nullptr;
+    std::vector<int> dof;
+    int max_dof = 0;
+    mrv_tiling tiling[2] = {{0, 0}, {0, 0}};
+    int inflight = 0;
+};
+
+struct EnvHost {
+    EnvDev dev{};
+    void* dmem = nullptr;
+    int inflight = 0;
+};
+
+}  // namespace
+
+
+namespace {
+
+bool finite_all(const double* p, size_t n)
+{
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+}  // namespace
+
+struct mrv_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    double eps = 1e-5;
+    int n_cu = 0;
+    int next_handle = 1;
+    std::map<int, TeamHost> teams;
+    std::map<int, EnvHost> envs;
+    std::mutex handle_mu;   // guards teams/envs against the serving thread
+
+    Scratch sc;             // scratch of the synchronous and device-array calls
+    DevBuf in_begin, in_t, in_q, out_buf;
+
+    std::unique_ptr<ServeLoop> serve;
+    int max_inflight = 1024;
+    size_t serve_bytes = 256u << 20;
+};
+
+namespace {
+
+mrv_status guard(mrv_ctx ctx)
+{
+    if (!ctx) return fail(MRV_E_HANDLE, "null context");
+    return MRV_OK;
+}
+
+void set_device(mrv_ctx ctx) { HIPCHK(hipSetDevice(ctx->device)); }
+
+// ---------------------------------------------------------------------------
+// teams
+
+int build_team(mrv_ctx ctx, const mrv_robot_desc* robots, int n, TeamHost& out)
+{
+    if (!robots || n < 1 || n > MRV_MAX_ROBOTS)
+        throw Err{MRV_E_INVALID, "team must have 1.." + std::to_string(MRV_MAX_ROBOTS) + " robots"};
+    std::vector<int> r_nj(n), r_joint_off(n), r_sphere_off(n + 1, 0), r_frame_off(n);
+    std::vector<float> base32(n * 12);
+    std::vector<double> base64(n * 12);
+    std::vector<int> j_type;
+    std::vector<float> j32;
+    std::vector<double> j64;
+    std::vector<int> s_robot, s_slot, s_lframe;
+    std::vector<float> s_local32;
+    std::vector<double> s_local64;
+    std::vector<int> self_pairs;
+    int F = 0, S = 0, max_dof = 0;
+    for (int r = 0; r < n; ++r) {
+        const mrv_robot_desc& R = robots[r];
+        const std::string who = "robot " + std::to_string(r) + ": ";
+        if (R.n_joints < 0 || R.n_joints > MRV_MAX_JOINTS)
+            throw Err{MRV_E_INVALID, who + "n_joints out of range"};
+        if (R.n_joints > 0 && (!R.joint_type || !R.joint_fixed))
+            throw Err{MRV_E_INVALID, who + "null joint arrays"};
+        if (R.n_spheres < 1 || R.n_spheres > MRV_MAX_SPHERES_PER_ROBOT)
+            throw Err{MRV_E_INVALID, who + "n_spheres out of range"};
+        if (!R.sphere_frame || !R.sphere_xyzr) throw Err{MRV_E_INVALID, who + "null sphere arrays"};
+        if (R.n_self_pairs < 0 || (R.n_self_pairs > 0 && !R.self_pairs))
+            throw Err{MRV_E_INVALID, who + "bad self pair list"};
+        if (!finite_all(R.base, 12)) throw Err{MRV_E_INVALID, who + "non-finite base"};
+        if (R.n_joints > 0 && !finite_all(R.joint_fixed, (size_t)R.n_joints * 12))
+            throw Err{MRV_E_INVALID, who + "non-finite joint transform"};
+        if (!finite_all(R.sphere_xyzr, (size_t)R.n_spheres * 4))
+            throw Err{MRV_E_INVALID, who + "non-finite sphere"};
+        r_nj[r] = R.n_joints;
+        max_dof = std::max(max_dof, R.n_joints);
+        r_joint_off[r] = (int)j_type.size();
+        r_frame_off[r] = F;
+        F += R.n_joints + 1;
+        for (int i = 0; i < 12; ++i) {
+            base32[r * 12 + i] = (float)R.base[i];
+            base64[r * 12 + i] = R.base[i];
+        }
+        for (int j = 0; j < R.n_joints; ++j) {
+            int jt = R.joint_type[j];
+            if (jt < MRV_REV_Z || jt > MRV_PRI_Z) throw Err{MRV_E_INVALID, who + "unknown joint type"};
+            j_type.push_back(jt);
+            for (int i = 0; i < 12; ++i) {
+                j32.push_back((float)R.joint_fixed[j * 12 + i]);
+                j64.push_back(R.joint_fixed[j * 12 + i]);
+            }
+        }
+        for (int s = 0; s < R.n_spheres; ++s) {
+            int f = R.sphere_frame[s];
+            if (f < 0 || f > R.n_joints) throw Err{MRV_E_INVALID, who + "sphere frame out of range"};
+            double rad = R.sphere_xyzr[s * 4 + 3];
+            if (!(rad > 0.0)) throw Err{MRV_E_INVALID, who + "sphere radius must be > 0"};
+            s_robot.push_back(r);
+            s_slot.push_back(r_frame_off[r] + f);
+            s_lframe.push_back(f);
+            for (int i = 0; i < 4; ++i) {
+                s_local32.push_back((float)R.sphere_xyzr[s * 4 + i]);
+                s_local64.push_back(R.sphere_xyzr[s * 4 + i]);
+            }
+        }
+        for (int p = 0; p < R.n_self_pairs; ++p) {
+            int a = R.self_pairs[2 * p], b = R.self_pairs[2 * p + 1];
+            if (a < 0 || b < 0 || a >= R.n_spheres || b >= R.n_spheres || a == b)
+                throw Err{MRV_E_INVALID, who + "self pair index out of range"};
+            self_pairs.push_back(S + a);
+            self_pairs.push_back(S + b);
+        }
+        S += R.n_spheres;
+        r_sphere_off[r + 1] = S;
+    }
+    if (S > MRV_MAX_TEAM_SPHERES) throw Err{MRV_E_INVALID, "team has too many spheres"};
+    // robot-robot tasks: each 64-sphere slot against every robot above the slot's first robot
+    const int n_slots = (S + 63) / 64;
+    std::vector<int> rr_tasks;
+    for (int slot = 0; slot < n_slots; ++slot) {
+        const int rmin = s_robot[slot * 64];
+        for (int rb = rmin + 1; rb < n; ++rb) {
+            rr_tasks.push_back(slot);
+            rr_tasks.push_back(rb);
+        }
+    }
+    long long rr_per_t = 0;
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j)
+            rr_per_t += (long long)(r_sphere_off[i + 1] - r_sphere_off[i]) * (r_sphere_off[j + 1] - r_sphere_off[j]);
+
+    Packer pk;
+    const size_t o_nj = pk.add(r_nj), o_jo = pk.add(r_joint_off), o_so = pk.add(r_sphere_off),
+                 o_fo = pk.add(r_frame_off), o_b32 = pk.add(base32), o_b64 = pk.add(base64),
+                 o_jt = pk.add(j_type), o_j32 = pk.add(j32), o_j64 = pk.add(j64), o_sr = pk.add(s_robot),
+                 o_ss = pk.add(s_slot), o_sl = pk.add(s_lframe), o_l32 = pk.add(s_local32),
+                 o_l64 = pk.add(s_local64), o_sp = pk.add(self_pairs), o_rt = pk.add(rr_tasks);
+    void* d = nullptr;
+    if (hipMalloc(&d, pk.bytes.size()) != hipSuccess) throw Err{MRV_E_NOMEM, "team upload allocation failed"};
+    if (hipMemcpy(d, pk.bytes.data(), pk.bytes.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(d);
+        throw Err{MRV_E_DEVICE, "team upload failed"};
+    }
+    auto at = [&](size_t o) { return (unsigned char*)d + o; };
+    TeamDev& t = out.dev;
+    t.n_robots = n;
+    t.S = S;
+    t.F = F;
+    t.n_self = (int)self_pairs.size() / 2;
+    t.n_rr_tasks = (int)rr_tasks.size() / 2;
+    t.n_slots = n_slots;
+    t.P = n * (n - 1) / 2;
+    t.max_dof = max_dof;
+    t.rr_tests_per_t = rr_per_t;
+    t.r_nj = (const int*)at(o_nj);
+    t.r_joint_off = (const int*)at(o_jo);
+    t.r_sphere_off = (const int*)at(o_so);
+    t.r_frame_off = (const int*)at(o_fo);
+    t.r_base32 = (const float*)at(o_b32);
+    t.r_base64 = (const double*)at(o_b64);
+    t.j_type = (const int*)at(o_jt);
+    t.j_fixed32 = (const float*)at(o_j32);
+    t.j_fixed64 = (const double*)at(o_j64);
+    t.s_robot = (const int*)at(o_sr);
+    t.s_slot = (const int*)at(o_ss);
+    t.s_lframe = (const int*)at(o_sl);
+    t.s_local32 = (const float4*)at(o_l32);
+    t.s_local64 = (const double*)at(o_l64);
+    t.self_pairs = (const int2*)at(o_sp);
+    t.rr_tasks = (const int2*)at(o_rt);
+    out.dmem = d;
+    out.dof = r_nj;
+    out.max_dof = max_dof;
+    (void)ctx;
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
+// environments
+
+void build_env(const mrv_env_desc* e, EnvHost& out)
+{
+    if (!e) throw Err{MRV_E_INVALID, "null environment"};
+    if (e->n_spheres < 0 || e->n_boxes < 0 || e->n_cyls < 0 || e->n_points < 0)
+        throw Err{MRV_E_INVALID, "negative obstacle count"};
+    if ((e->n_spheres && !e->spheres) || (e->n_boxes && !e->boxes) || (e->n_cyls && !e->cylinders) ||
+        (e->n_points && !e->points))
+        throw Err{MRV_E_INVALID, "null obstacle array"};
+    if (e->n_spheres && !finite_all(e->spheres, (size_t)e->n_spheres * 4)) throw Err{MRV_E_INVALID, "non-finite sphere obstacle"};
+    if (e->n_boxes && !finite_all(e->boxes, (size_t)e->n_boxes * 15)) throw Err{MRV_E_INVALID, "non-finite box"};
+    if (e->n_cyls && !finite_all(e->cylinders, (size_t)e->n_cyls * 8)) throw Err{MRV_E_INVALID, "non-finite cylinder"};
+    if (e->n_points && !finite_all(e->points, (size_t)e->n_points * 3)) throw Err{MRV_E_INVALID, "non-finite point"};
+    if (!std::isfinite(e->point_radius) || e->point_radius < 0) throw Err{MRV_E_INVALID, "bad point radius"};
+    std::vector<float> sph32;
+    for (int i = 0; i < e->n_spheres; ++i) {
+        if (e->spheres[i * 4 + 3] < 0) throw Err{MRV_E_INVALID, "negative obstacle radius"};
+        for (int k = 0; k < 4; ++k) sph32.push_back((float)e->spheres[i * 4 + k]);
+    }
+    std::vector<float> box32;
+    for (int i = 0; i < e->n_boxes; ++i) {
+        const double* b = e->boxes + i * 15;
+        const double* R = b + 3;
+        for (int a = 0; a < 3; ++a)
+            for (int c = 0; c < 3; ++c) {
+                double dot = R[0 * 3 + a] * R[0 * 3 + c] + R[1 * 3 + a] * R[1 * 3 + c] + R[2 * 3 + a] * R[2 * 3 + c];
+                if (std::fabs(dot - (a == c ? 1.0 : 0.0)) > 1e-9)
+                    throw Err{MRV_E_INVALID, "box rotation is not orthonormal"};
+            }
+        if (b[12] < 0 || b[13] < 0 || b[14] < 0) throw Err{MRV_E_INVALID, "negative box half-extent"};
+        float row[16] = {(float)b[0], (float)b[1], (float)b[2],
+                         // R^T row-major: row k of R^T = column k of R
+                         (float)R[0], (float)R[3], (float)R[6],
+                         (float)R[1], (float)R[4], (float)R[7],
+                         (float)R[2], (float)R[5], (float)R[8],
+                         (float)b[12], (float)b[13], (float)b[14], 0.f};
+        box32.insert(box32.end(), row, row + 16);
+    }
+    std::vector<float> cyl32;
+    for (int i = 0; i < e->n_cyls; ++i) {
+        const double* y = e->cylinders + i * 8;
+        double nrm = y[3] * y[3] + y[4] * y[4] + y[5] * y[5];
+        if (std::fabs(nrm - 1.0) > 1e-9) throw Err{MRV_E_INVALID, "cylinder axis is not a unit vector"};
+        if (y[6] < 0 || y[7] < 0) throw Err{MRV_E_INVALID, "negative cylinder size"};
+        for (int k = 0; k < 8; ++k) cyl32.push_back((float)y[k]);
+    }
+    // point cloud: uniform grid, points sorted by cell (x fastest)
+    std::vector<float> pts32;
+    std::vector<double> pts64;
+    std::vector<int> cell_start(1, 0);
+    float grid_lo[3] = {0, 0, 0};
+    int dims[3] = {1, 1, 1};
+    double cell = e->grid_cell > 0 ? e->grid_cell : 0.05;
+    if (e->n_points > 0) {
+        if (e->n_points > (1ll << 30)) throw Err{MRV_E_INVALID, "too many points"};
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        for (long long i = 0; i < e->n_points; ++i)
+            for (int d = 0; d < 3; ++d) {
+                lo[d] = std::min(lo[d], e->points[i * 3 + d]);
+                hi[d] = std::max(hi[d], e->points[i * 3 + d]);
+            }
+        long long total = 1;
+        for (int d = 0; d < 3; ++d) {
+            dims[d] = (int)std::floor((hi[d] - lo[d]) / cell) + 1;
+            total *= dims[d];
+        }
+        if (total > (1ll << 26)) throw Err{MRV_E_INVALID, "point grid too fine for the cloud extent"};
+        for (int d = 0; d < 3; ++d) grid_lo[d] = (float)lo[d];
+        const float inv = (float)(1.0 / cell);
+        std::vector<int> cell_of(e->n_points);
+        std::vector<int> count(total + 1, 0);
+        for (long long i = 0; i < e->n_points; ++i) {
+            int ci[3];
+            for (int d = 0; d < 3; ++d) {
+                // bin with the same FP32 arithmetic the kernel uses for its lookups
+                int v = (int)std::floor(((float)e->points[i * 3 + d] - grid_lo[d]) * inv);
+                ci[d] = std::min(std::max(v, 0), dims[d] - 1);
+            }
+            cell_of[i] = (ci[2] * dims[1] + ci[1]) * dims[0] + ci[0];
+            count[cell_of[i] + 1]++;
+        }
+        cell_start.assign(total + 1, 0);
+        for (long long c = 0; c < total; ++c) cell_start[c + 1] = cell_start[c] + count[c + 1];
+        std::vector<int> cursor(cell_start.begin(), cell_start.end() - 1);
+        pts32.assign((size_t)e->n_points * 4, 0.f);
+        pts64.assign((size_t)e->n_points * 3, 0.0);
+        for (long long i = 0; i < e->n_points; ++i) {
+            int p = cursor[cell_of[i]]++;
+            for (int d = 0; d < 3; ++d) {
+                pts32[(size_t)p * 4 + d] = (float)e->points[i * 3 + d];
+                pts64[(size_t)p * 3 + d] = e->points[i * 3 + d];
+            }
+        }
+    }
+    std::vector<double> sph64(e->spheres, e->spheres + (size_t)e->n_spheres * 4);
+    std::vector<double> box64(e->boxes, e->boxes + (size_t)e->n_boxes * 15);
+    std::vector<double> cyl64(e->cylinders, e->cylinders + (size_t)e->n_cyls * 8);
+    Packer pk;
+    size_t o_s32 = pk.add(sph32), o_s64 = pk.add(sph64), o_b32 = pk.add(box32), o_b64 = pk.add(box64),
+           o_c32 = pk.add(cyl32), o_c64 = pk.add(cyl64), o_p32 = pk.add(pts32), o_p64 = pk.add(pts64),
+           o_cs = pk.add(cell_start);
+    void* d = nullptr;
+    if (hipMalloc(&d, pk.bytes.size()) != hipSuccess) throw Err{MRV_E_NOMEM, "environment upload allocation failed"};
+    if (hipMemcpy(d, pk.bytes.data(), pk.bytes.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(d);
+        throw Err{MRV_E_DEVICE, "environment upload failed"};
+    }
+    auto at = [&](size_t o) { return (unsigned char*)d + o; };
+    EnvDev& v = out.dev;
+    v.n_sph = e->n_spheres;
+    v.n_box = e->n_boxes;
+    v.n_cyl = e->n_cyls;
+    v.n_pts = e->n_points;
+    v.sph32 = (const float4*)at(o_s32);
+    v.sph64 = (const double*)at(o_s64);
+    v.box32 = (const float*)at(o_b32);
+    v.box64 = (const double*)at(o_b64);
+    v.cyl32 = (const float*)at(o_c32);
+    v.cyl64 = (const double*)at(o_c64);
+    v.pts32 = (const float4*)at(o_p32);
+    v.pts64 = (const double*)at(o_p64);
+    v.cell_start = (const int*)at(o_cs);
+    for (int k = 0; k < 3; ++k) {
+        v.grid_lo[k] = grid_lo[k];
+        v.grid_dim[k] = dims[k];
+    }
+    v.grid_cell = (float)cell;
+    v.grid_inv = (float)(1.0 / cell);
+    v.pt_radius = (float)e->point_radius;
+    v.pt_radius64 = e->point_radius;
+    out.dmem = d;
+}
+
+// ---------------------------------------------------------------------------
+// calls
+
+void check_paths_host(const TeamHost& tm, const mrv_paths* p)
+{
+    if (!p) throw Err{MRV_E_INVALID, "null paths"};
+    if (p->n_queries < 0) throw Err{MRV_E_INVALID, "negative n_queries"};
+    if (p->n_queries == 0) return;
+    const int n = tm.dev.n_robots;
+    if (!p->wp_begin || !p->wp_t || !p->wp_q) throw Err{MRV_E_INVALID, "null path array"};
+    if (p->dof_stride < std::max(tm.max_dof, 1) && !(tm.max_dof == 0 && p->dof_stride >= 0))
+        throw Err{MRV_E_INVALID, "dof_stride smaller than the team's largest dof"};
+    const long long npaths = (long long)p->n_queries * n;
+    if (p->wp_begin[0] != 0) throw Err{MRV_E_INVALID, "wp_begin[0] must be 0"};
+    if (p->wp_begin[npaths] != p->n_wp) throw Err{MRV_E_INVALID, "wp_begin[last] must equal n_wp"};
+    for (long long i = 0; i < npaths; ++i) {
+        const long long b = p->wp_begin[i], e = p->wp_begin[i + 1];
+        if (e <= b) throw Err{MRV_E_INVALID, "empty path (query " + std::to_string(i / n) + ")"};
+        if (p->wp_t[b] != 0) throw Err{MRV_E_INVALID, "first waypoint time must be 0"};
+        const int dof = tm.dof[i % n];
+        for (long long w = b; w < e; ++w) {
+            if (w > b && p->wp_t[w] <= p->wp_t[w - 1])
+                throw Err{MRV_E_INVALID, "waypoint times must strictly increase"};
+            for (int d = 0; d < dof; ++d)
+                if (!std::isfinite(p->wp_q[w * p->dof_stride + d]))
+                    throw Err{MRV_E_INVALID, "non-finite waypoint configuration"};
+        }
+        if (p->wp_t[e - 1] >= MRV_MAX_T) throw Err{MRV_E_INVALID, "path longer than MRV_MAX_T"};
+    }
+}
+
+long long max_horizon(const mrv_paths* p, int n_robots)
+{
+    long long m = 1;
+    const long long npaths = (long long)p->n_queries * n_robots;
+    for (long long i = 0; i < npaths; ++i) m = std::max<long long>(m, (long long)p->wp_t[p->wp_begin[i + 1] - 1] + 1);
+    return m;
+}
+
+int default_chunk(const TeamHost& tm, int kind)
+{
+    const size_t per_t = (size_t)(tm.dev.S + 3 * tm.dev.F) * sizeof(float4);
+    int cmax = (int)((kLdsBudget - 8 * 1024) / per_t);
+    cmax = std::min(cmax, kMaxChunk);
+    if (cmax < 1) cmax = 1;
+    const int want = kind == 0 ? 8 : 8;
+    return std::min(cmax, want);
+}
+
+size_t lds_bytes_for(const TeamHost& tm, int chunk)
+{
+    return (size_t)chunk * (size_t)(tm.dev.S + 3 * tm.dev.F) * sizeof(float4);
+}
+
+}  // namespace
+
+namespace mrv {
+// Make sc hold control words, `bins` tile-count bins and `queries` per-query slots.
+// Fresh bins are zeroed here; afterwards k_scan leaves them zero after every call.
+void ensure_scratch(Scratch& sc, size_t bins, size_t queries)
+{
+    if (!sc.ctrl.p) {
+        sc.ctrl.ensure(64 + 8 * ST_COUNT + 64);
+        HIPCHK(hipMemset(sc.ctrl.p, 0, sc.ctrl.cap));
+    }
+    if (!sc.ev0) {
+        HIPCHK(hipEventCreate(&sc.ev0));
+        HIPCHK(hipEventCreate(&sc.ev1));
+    }
+    if (bins > sc.bins) {
+        sc.hist.release();
+        sc.start.release();
+        sc.off.release();
+        sc.hist.ensure(bins * sizeof(int));
+        sc.start.ensure(bins * sizeof(int));
+        sc.off.ensure(bins * sizeof(long long));
+        HIPCHK(hipMemset(sc.hist.p, 0, sc.hist.cap));
+        sc.bins = bins;
+    }
+    const size_t Q = std::max<size_t>(queries, 1);
+    sc.q_T.ensure(Q * 4);
+    sc.q_nt.ensure(Q * 4);
+    sc.q_g.ensure(Q * 4);
+    sc.q_status.ensure(Q * 4);
+    sc.q_word.ensure(Q * 4);
+    sc.q_sorted.ensure(Q * 4);
+}
+}  // namespace mrv
+
+namespace {
+
+struct DevPaths {
+    const long long* wp_begin;
+    const int* wp_t;
+    const double* wp_q;
+    long long n_wp;
+    int n_queries;
+    int dof_stride;
+};
+
+// Queue the whole pipeline for one call on the context stream.
+// `max_T` bounds every query's horizon (MRV_MAX_T when unknown).
+void run_call(mrv_ctx ctx, Scratch& sc, TeamHost& tm, const EnvHost* env, int kind, uint32_t flags,
+              const DevPaths& dp, long long max_T, void* out_dev, hipStream_t stream)
+{
+    int chunk = tm.tiling[kind].chunk > 0 ? tm.tiling[kind].chunk : default_chunk(tm, kind);
+    ensure_scratch(sc, (size_t)((max_T + chunk - 1) / chunk) + 2, (size_t)dp.n_queries);
+    const size_t lds = lds_bytes_for(tm, chunk);
+    CallDev cd{};
+    cd.n_queries = dp.n_queries;
+    cd.n_robots = tm.dev.n_robots;
+    cd.dof_stride = dp.dof_stride;
+    cd.kind = kind;
+    cd.flags = flags;
+    cd.chunk = chunk;
+    cd.eps32 = (float)ctx->eps;
+    cd.eps64 = ctx->eps;
+    cd.n_wp = dp.n_wp;
+    cd.wp_begin = dp.wp_begin;
+    cd.wp_t = dp.wp_t;
+    cd.wp_q = dp.wp_q;
+    cd.T = (int*)sc.q_T.p;
+    cd.nt = (int*)sc.q_nt.p;
+    cd.gstep = (int*)sc.q_g.p;
+    cd.status = (int*)sc.q_status.p;
+    cd.word = (unsigned*)sc.q_word.p;
+    cd.sorted_q = (int*)sc.q_sorted.p;
+    cd.hist = (int*)sc.hist.p;
+    cd.start = (int*)sc.start.p;
+    cd.off = (int*)sc.off.p;
+    cd.ctrl = (int*)sc.ctrl.p;
+    cd.stats = (unsigned long long*)((char*)sc.ctrl.p + 64);
+    cd.valid_out = kind == 0 ? (unsigned char*)out_dev : nullptr;
+    cd.conflict_out = kind == 1 ? (int*)out_dev : nullptr;
+
+    EnvDev ed{};
+    if (env) ed = env->dev;
+
+    const int per_cu = std::max(1, validate_blocks_per_cu(kind, lds));
+    const int want = tm.tiling[kind].wg_per_cu > 0 ? std::min(tm.tiling[kind].wg_per_cu, per_cu) : per_cu;
+    const int grid = std::max(1, ctx->n_cu * want);
+
+    HIPCHK(launch_prepare(tm.dev, cd, stream));
+    HIPCHK(hipEventRecord(sc.ev0, stream));
+    HIPCHK(launch_validate(tm.dev, ed, cd, grid, lds, stream));
+    HIPCHK(hipEventRecord(sc.ev1, stream));
+    HIPCHK(launch_finalize(tm.dev, cd, stream));
+    sc.last_kind = kind;
+}
+
+TeamHost& find_team(mrv_ctx ctx, int h)
+{
+    auto it = ctx->teams.find(h);
+    if (it == ctx->teams.end()) throw Err{MRV_E_HANDLE, "unknown team handle " + std::to_string(h)};
+    return it->second;
+}
+
+const EnvHost* find_env(mrv_ctx ctx, int h)
+{
+    if (h < 0) return nullptr;
+    auto it = ctx->envs.find(h);
+    if (it == ctx->envs.end()) throw Err{MRV_E_HANDLE, "unknown environment handle " + std::to_string(h)};
+    return &it->second;
+}
+
+// Host-array call: validate, upload, run, download, wait.
+void host_call(mrv_ctx ctx, int team, int env, int kind, const mrv_paths* p, uint32_t flags, void* out_host)
+{
+    set_device(ctx);
+    std::lock_guard<std::mutex> lk(ctx->handle_mu);
+    TeamHost& tm = find_team(ctx, team);
+    const EnvHost* ev = kind == 0 ? find_env(ctx, env) : nullptr;
+    check_paths_host(tm, p);
+    if (p->n_queries == 0) return;
+    const int n = tm.dev.n_robots;
+    const size_t nb = ((size_t)p->n_queries * n + 1) * sizeof(long long);
+    const size_t nt = (size_t)p->n_wp * sizeof(int);
+    const size_t nq = (size_t)p->n_wp * (size_t)p->dof_stride * sizeof(double);
+    const size_t nout = kind == 0 ? (size_t)p->n_queries : (size_t)p->n_queries * sizeof(mrv_conflict);
+    ctx->in_begin.ensure(nb);
+    ctx->in_t.ensure(nt);
+    ctx->in_q.ensure(nq);
+    ctx->out_buf.ensure(nout);
+    HIPCHK(hipMemcpyAsync(ctx->in_begin.p, p->wp_begin, nb, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->in_t.p, p->wp_t, nt, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->in_q.p, p->wp_q, nq, hipMemcpyHostToDevice, ctx->stream));
+    DevPaths dp{(const long long*)ctx->in_begin.p, (const int*)ctx->in_t.p, (const double*)ctx->in_q.p,
+                p->n_wp, p->n_queries, p->dof_stride};
+    run_call(ctx, ctx->sc, tm, ev, kind, flags, dp, max_horizon(p, n), ctx->out_buf.p, ctx->stream);
+    HIPCHK(hipMemcpyAsync(out_host, ctx->out_buf.p, nout, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+}
+
+void device_call(mrv_ctx ctx, int team, int env, int kind, const mrv_paths* p, uint32_t flags, void* out_dev)
+{
+    set_device(ctx);
+    std::lock_guard<std::mutex> lk(ctx->handle_mu);
+    TeamHost& tm = find_team(ctx, team);
+    const EnvHost* ev = kind == 0 ? find_env(ctx, env) : nullptr;
+    if (!p) throw Err{MRV_E_INVALID, "null paths"};
+    if (p->n_queries < 0) throw Err{MRV_E_INVALID, "negative n_queries"};
+    if (p->n_queries == 0) return;
+    if (!p->wp_begin || !p->wp_t || !p->wp_q || !out_dev) throw Err{MRV_E_INVALID, "null device pointer"};
+    if (p->n_wp < 1) throw Err{MRV_E_INVALID, "n_wp must be positive"};
+    if (p->dof_stride < tm.max_dof) throw Err{MRV_E_INVALID, "dof_stride smaller than the team's largest dof"};
+    DevPaths dp{(const long long*)p->wp_begin, p->wp_t, p->wp_q, p->n_wp, p->n_queries, p->dof_stride};
+    run_call(ctx, ctx->sc, tm, ev, kind, flags, dp, MRV_MAX_T, out_dev, ctx->stream);
+}
+
+uint32_t check_flags(int kind, uint32_t flags)
+{
+    const uint32_t known = MRV_CHECK_ENV | MRV_EXHAUSTIVE | MRV_HIERARCHICAL | MRV_ORDER_RAKE | MRV_ORDER_LINEAR;
+    if (flags & ~known) throw Err{MRV_E_INVALID, "unknown flag bits"};
+    if ((flags & MRV_ORDER_RAKE) && (flags & MRV_ORDER_LINEAR)) throw Err{MRV_E_INVALID, "two tile orders requested"};
+    if (kind == 1) flags &= MRV_EXHAUSTIVE;
+    return flags;
+}
+
+template <class Fn>
+mrv_status wrap(Fn&& fn)
+{
+    try {
+        fn();
+        return MRV_OK;
+    } catch (const Err& e) {
+        return fail(e.s, e.msg);
+    } catch (const std::bad_alloc&) {
+        return fail(MRV_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(MRV_E_DEVICE, "unexpected internal error");
+    }
+}
+
+}  // namespace
+
+// ===========================================================================
+// exported (also used by the serving loop)
+
+namespace mrv {
+
+void serve_run_call(mrv_ctx ctx, Scratch& sc, int team, int env, int kind, uint32_t flags,
+                    const long long* wp_begin, const int* wp_t, const double* wp_q, long long n_wp,
+                    int n_queries, int dof_stride, long long max_T, void* out_dev, hipStream_t stream)
+{
+    TeamHost& tm = find_team(ctx, team);
+    const EnvHost* ev = kind == 0 ? find_env(ctx, env) : nullptr;
+    DevPaths dp{wp_begin, wp_t, wp_q, n_wp, n_queries, dof_stride};
+    run_call(ctx, sc, tm, ev, kind, flags, dp, max_T, out_dev, stream);
+}
+
+}  // namespace mrv
+
+extern "C" {
+
+const char* mrv_last_error(void) { return g_err.c_str(); }
+
+mrv_status mrv_create(const mrv_ctx_opts* opts, mrv_ctx* out)
+{
+    if (!out) return fail(MRV_E_INVALID, "null output handle");
+    return wrap([&] {
+        int ndev = 0;
+        HIPCHK(hipGetDeviceCount(&ndev));
+        const int dev = opts ? opts->device : 0;
+        if (dev < 0 || dev >= ndev) throw Err{MRV_E_INVALID, "device ordinal out of range"};
+        if (opts && opts->flags != 0) throw Err{MRV_E_INVALID, "unknown context flags"};
+        std::unique_ptr<mrv_ctx_s> c(new mrv_ctx_s());
+        c->device = dev;
+        HIPCHK(hipSetDevice(dev));
+        hipDeviceProp_t prop;
+        HIPCHK(hipGetDeviceProperties(&prop, dev));
+        c->n_cu = prop.multiProcessorCount;
+        if (opts && opts->near_eps > 0) c->eps = opts->near_eps;
+        if (!(c->eps < 1e-2)) throw Err{MRV_E_INVALID, "near_eps must be < 0.01 m"};
+        if (opts && opts->max_inflight > 0) c->max_inflight = opts->max_inflight;
+        if (opts && opts->serve_bytes > 0) c->serve_bytes = opts->serve_bytes;
+        if (opts && opts->stream) {
+            c->stream = (hipStream_t)opts->stream;
+        } else {
+            HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+            c->own_stream = true;
+        }
+        ensure_scratch(c->sc, (size_t)MRV_MAX_T + 2, 1);
+        *out = c.release();
+    });
+}
+
+mrv_status mrv_destroy(mrv_ctx ctx)
+{
+    if (!ctx) return MRV_OK;
+    mrv_status st = wrap([&] {
+        if (ctx->serve) ctx->serve.reset();
+        (void)hipSetDevice(ctx->device);
+        (void)hipStreamSynchronize(ctx->stream);
+        for (auto& kv : ctx->teams) (void)hipFree(kv.second.dmem);
+        for (auto& kv : ctx->envs) (void)hipFree(kv.second.dmem);
+        ctx->sc.release();
+        for (DevBuf* b : {&ctx->in_begin, &ctx->in_t, &ctx->in_q, &ctx->out_buf}) b->release();
+        if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    });
+    delete ctx;
+    return st;
+}
+
+mrv_status mrv_load_team(mrv_ctx ctx, const mrv_robot_desc* robots, int32_t n_robots, int32_t* team_out)
+{
+    if (guard(ctx)) return MRV_E_HANDLE;
+    if (!team_out) return fail(MRV_E_INVALID, "null team_out");
+    return wrap([&] {
+        set_device(ctx);
+        TeamHost th;
+        build_team(ctx, robots, n_robots, th);
+        std::lock_guard<std::mutex> lk(ctx->handle_mu);
+        const int h = ctx->next_handle++;
+        ctx->teams.emplace(h, th);
+        *team_out = h;
+    });
+}
+
+mrv_status mrv_load_env(mrv_ctx ctx, const mrv_env_desc* env, int32_t* env_out)
+{
+    if (guard(ctx)) return MRV_E_HANDLE;
+    if (!env_out) return fail(MRV_E_INVALID, "null env_out");
+    return wrap([&] {
+        set_device(ctx);
+        EnvHost eh;
+        build_env(env, eh);
+        std::lock_guard<std::mutex> lk(ctx->handle_mu);
+        const int h = ctx->next_handle++;
+        ctx->envs.emplace(h, eh);
+        *env_out = h;
+    });
+}
+
+mrv_status mrv_unload(mrv_ctx ctx, int32_t handle)
+{
+    if (guard(ctx)) return MRV_E_HANDLE;
+    return wrap([&] {
+        set_device(ctx);
+        std::lock_guard<std::mutex> lk(ctx->handle_mu);
+        auto t = ctx->teams.find(handle);
+        if (t != ctx->teams.end()) {
+            if (t->second.inflight > 0) throw Err{MRV_E_BUSY, "team is used by a queued request"};
+            HIPCHK(hipStreamSynchronize(ctx->stream));
+            (void)hipFree(t->second.dmem);
+            ctx->teams.erase(t);
+            return;
+        }
+        auto e = ctx->envs.find(handle);
+        if (e != ctx->envs.end()) {
+            if (e->second.inflight > 0) throw Err{MRV_E_BUSY, "environment is used by a queued request"};
+            HIPCHK(hipStreamSynchronize(ctx->stream));
+            (void)hipFree(e->second.dmem);
+            ctx->envs.erase(e);
+            return;
+        }
+        throw Err{MRV_E_HANDLE, "unknown handle " + std::to_string(handle)};
+    });
+}
+
+mrv_status mrv_mv(mrv_ctx ctx, int32_t team, int32_t env, const mrv_paths* paths, uint32_t flags,
+                  uint8_t* valid_out)
+{
+    if (guard(ctx)) return MRV_E_HANDLE;
+    if (!valid_out && paths && paths->n_queries > 0) return fail(MRV_E_INVALID, "null valid_out");
+    return wrap([&] {
+        const uint32_t f = check_flags(0, flags);
+        host_call(ctx, team, env, 0, paths, f, valid_out);
+    });
+}
+
+mrv_status mrv_ffc(mrv_ctx ctx, int32_t team, const mrv_paths* paths, uint32_t flags, mrv_conflict* out)
+{
+    if (guard(ctx)) return MRV_E_HANDLE;
+    if (!out && paths && paths->n_queries > 0) return fail(MRV_E_INVALID, "null output");
+    return wrap([&] {
+        const uint32_t f = check_flags(1, flags);
+        host_call(ctx, team, -1, 1, paths, f, out);
+    });
+}
+
+mrv_status mrv_mv_device(mrv_ctx ctx, int32_t team, int32_t env, const mrv_paths* paths, uint32_t flags,
+                         uint8_t* valid_out)
+{
+    if (guard(ctx)) return MRV_E_HANDLE;
+    return wrap([&] {
+        const uint32_t f = check_flags(0, flags);
+        device_call(ctx, team, env, 0, paths, f, valid_out);
+    });
+}
+
+mrv_status mrv_ffc_device(mrv_ctx ctx, int32_t team, const mrv_paths* paths, uint32_t flags, mrv_conflict* out)
+{
+    if (guard(ctx)) return MRV_E_HANDLE;
+    return wrap([&] {
+        const uint32_t f = check_flags(1, flags);
+        device_call(ctx, team, -1, 1, paths, f, out);
+    });
+}
+
+mrv_status mrv_sync(mrv_ctx ctx)
+{
+    if (guard(ctx)) return MRV_E_HANDLE;
+    int bad = 0;
+    mrv_status st = wrap([&] {
+        set_device(ctx);
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        HIPCHK(hipMemcpy(&bad, (int*)ctx->sc.ctrl.p + 3, sizeof(int), hipMemcpyDeviceToHost));
+        if (bad) {
+            const int zero = 0;
+            HIPCHK(hipMemcpy((int*)ctx->sc.ctrl.p + 3, &zero, sizeof(int), hipMemcpyHostToDevice));
+        }
+    });
+    if (st != MRV_OK) return st;
+    if (bad) return fail(MRV_E_INVALID, std::to_string(bad) + " queries had malformed path data");
+    return MRV_OK;
+}
+
+int64_t mrv_motion_steps(const double* dq, int32_t dof, double step, int32_t metric)
+{
+    if (!dq || dof < 0 || !(step > 0) || !std::isfinite(step) || (metric != 0 && metric != 1)) {
+        g_err = "invalid arguments";
+        return -1;
+    }
+    double d = 0.0;
+    for (int k = 0; k < dof; ++k) {
+        if (!std::isfinite(dq[k])) {
+            g_err = "non-finite dq";
+            return -1;
+        }
+        if (metric == 0) d += dq[k] * dq[k];
+        else d = std::max(d, std::fabs(dq[k]));
+    }
+    if (metric == 0) d = std::sqrt(d);
+    const double n = std::ceil(d / step);
+    if (n > (double)(MRV_MAX_T - 1)) {
+        g_err = "motion needs more than MRV_MAX_T steps";
+        return -1;
+    }
+    return (int64_t)n;
+}
+
+mrv_status mrv_set_tiling(mrv_ctx ctx, int32_t team, int32_t kind, const mrv_tiling* tiling)
+{
+    if (guard(ctx)) return MRV_E_HANDLE;
+    return wrap([&] {
+        if (!tiling || (kind != 0 && kind != 1)) throw Err{MRV_E_INVALID, "bad tiling arguments"};
+        std::lock_guard<std::mutex> lk(ctx->handle_mu);
+        TeamHost& tm = find_team(ctx, team);
+        if (tiling->chunk < 0 || tiling->chunk > kMaxChunk) throw Err{MRV_E_INVALID, "chunk out of range"};
+        if (tiling->chunk > 0 && lds_bytes_for(tm, tiling->chunk) > (size_t)kLdsBudget - 8 * 1024)
+            throw Err{MRV_E_INVALID, "chunk does not fit in LDS for this team"};
+        if (tiling->wg_per_cu < 0 || tiling->wg_per_cu > 32) throw Err{MRV_E_INVALID, "wg_per_cu out of range"};
+        tm.tiling[kind] = *tiling;
+    });
+}
+
+mrv_status mrv_get_tiling(mrv_ctx ctx, int32_t team, int32_t kind, mrv_tiling* tiling)
+{
+    if (guard(ctx)) return MRV_E_HANDLE;
+    return wrap([&] {
+        if (!tiling || (kind != 0 && kind != 1)) throw Err{MRV_E_INVALID, "bad tiling arguments"};
+        std::lock_guard<std::mutex> lk(ctx->handle_mu);
+        TeamHost& tm = find_team(ctx, team);
+        mrv_tiling t = tm.tiling[kind];
+        if (t.chunk == 0) t.chunk = default_chunk(tm, kind);
+        *tiling = t;
+    });
+}
+
+mrv_status mrv_last_stats(mrv_ctx ctx, mrv_stats* out)
+{
+    if (guard(ctx)) return MRV_E_HANDLE;
+    if (!out) return fail(MRV_E_INVALID, "null output");
+    return wrap([&] {
+        set_device(ctx);
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        unsigned long long s[ST_COUNT];
+        HIPCHK(hipMemcpy(s, (char*)ctx->sc.ctrl.p + 64, sizeof(s), hipMemcpyDeviceToHost));
+        mrv_stats r{};
+        r.tiles_run = s[ST_TILES_RUN];
+        r.tiles_skipped = s[ST_TILES_SKIPPED];
+        r.states_evaluated = s[ST_STATES_EVAL];
+        r.states_covered = s[ST_STATES_COVERED];
+        r.rr_tests = s[ST_RR_TESTS];
+        r.env_tests = s[ST_ENV_TESTS];
+        r.self_tests = s[ST_SELF_TESTS];
+        r.near_rechecks = s[ST_RECHECKS];
+        float ms = 0.f;
+        if (ctx->sc.last_kind >= 0 && hipEventElapsedTime(&ms, ctx->sc.ev0, ctx->sc.ev1) == hipSuccess)
+            r.kernel_ms = ms;
+        *out = r;
+    });
+}
+
+// --------------------------------------------------------------- serving
+
+mrv_status mrv_submit(mrv_ctx ctx, const mrv_request* req, uint64_t* ticket)
+{
+    if (guard(ctx)) return MRV_E_HANDLE;
+    if (!req || !ticket) return fail(MRV_E_INVALID, "null argument");
+    return wrap([&] {
+        if (!ctx->serve) ctx->serve.reset(new ServeLoop(ctx, ctx->device, ctx->max_inflight, ctx->serve_bytes));
+        // validate against the resident handles, then copy
+        std::vector<int> dofs;
+        int n_robots = 0;
+        {
+            std::lock_guard<std::mutex> lk(ctx->handle_mu);
+            if (req->kind != 0 && req->kind != 1) throw Err{MRV_E_INVALID, "kind must be 0 (MV) or 1 (FFC)"};
+            TeamHost& tm = find_team(ctx, req->team);
+            if (req->kind == 0) (void)find_env(ctx, req->env);
+            check_flags(req->kind, req->flags);
+            check_paths_host(tm, &req->paths);
+            dofs = tm.dof;
+            n_robots = tm.dev.n_robots;
+            tm.inflight++;
+            if (req->kind == 0 && req->env >= 0) ctx->envs.find(req->env)->second.inflight++;
+        }
+        mrv_status s = ctx->serve->submit(*req, n_robots, ticket);
+        if (s != MRV_OK) {
+            std::lock_guard<std::mutex> lk(ctx->handle_mu);
+            ctx->teams.find(req->team)->second.inflight--;
+            if (req->kind == 0 && req->env >= 0) ctx->envs.find(req->env)->second.inflight--;
+            throw Err{s, s == MRV_E_BUSY ? "request queue full" : "submit failed"};
+        }
+    });
+}
+
+mrv_status mrv_poll(mrv_ctx ctx, uint64_t ticket, void* out)
+{
+    if (guard(ctx)) return MRV_E_HANDLE;
+    if (!ctx->serve) return fail(MRV_E_HANDLE, "unknown ticket");
+    std::string msg;
+    mrv_status s = ctx->serve->poll(ticket, out, 0, &msg);
+    if (s < 0) return fail(s, msg);
+    return s;
+}
+
+mrv_status mrv_wait(mrv_ctx ctx, uint64_t ticket, int32_t timeout_ms, void* out)
+{
+    if (guard(ctx)) return MRV_E_HANDLE;
+    if (!ctx->serve) return fail(MRV_E_HANDLE, "unknown ticket");
+    std::string msg;
+    mrv_status s = ctx->serve->poll(ticket, out, timeout_ms < 0 ? -1 : timeout_ms, &msg);
+    if (s == MRV_PENDING) return fail(MRV_E_TIMEOUT, "request still running");
+    if (s < 0) return fail(s, msg);
+    return s;
+}
+
+mrv_status mrv_cancel(mrv_ctx ctx, uint64_t ticket)
+{
+    if (guard(ctx)) return MRV_E_HANDLE;
+    if (!ctx->serve) return fail(MRV_E_HANDLE, "unknown ticket");
+    mrv_status s = ctx->serve->cancel(ticket);
+    if (s < 0) return fail(s, "unknown ticket");
+    return s;
+}
+
+}  // extern "C"
+
+// called by the serving loop when a request leaves the system
+namespace mrv {
+void serve_release_handles(mrv_ctx ctx, int team, int env, int kind)
+{
+    std::lock_guard<std::mutex> lk(ctx->handle_mu);
+    auto t = ctx->teams.find(team);
+    if (t != ctx->teams.end()) t->second.inflight--;
+    if (kind == 0 && env >= 0) {
+        auto e = ctx->envs.find(env);
+        if (e != ctx->envs.end()) e->second.inflight--;
+    }
+}
+std::mutex& serve_handle_mutex(mrv_ctx ctx) { return ctx->handle_mu; }
+}  // namespace mrv

@@ -1,0 +1,121 @@
+// Internal layouts shared by the host runtime (mrv_host.cpp) and the device
+// kernels (mrv_kernels.hip) of libmrv.  Nothing here is part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace mrv {
+
+constexpr int kWG = 256;            // threads per workgroup (4 waves of 64)
+constexpr int kWave = 64;
+constexpr int kWavesPerWG = kWG / kWave;
+constexpr int kMaxRobots = 32;
+constexpr int kMaxJoints = 8;
+constexpr int kMaxChunk = 64;       // timesteps per tile
+constexpr int kRecheckCap = 256;    // FP64 re-evaluations queued per tile before inline fallback
+constexpr int kLdsBudget = 64 * 1024;
+
+enum RecheckKind : int { RK_RR = 0, RK_SELF = 1, RK_ENV_SPH = 2, RK_ENV_BOX = 3, RK_ENV_CYL = 4, RK_ENV_PT = 5 };
+
+// Per-call counters (uint64 each), see mrv_stats.
+enum StatSlot : int {
+    ST_TILES_RUN = 0, ST_TILES_SKIPPED, ST_STATES_EVAL, ST_STATES_COVERED,
+    ST_RR_TESTS, ST_ENV_TESTS, ST_SELF_TESTS, ST_RECHECKS, ST_COUNT
+};
+
+// Resident team.  Spheres of all robots are flattened in robot order; frames of
+// one timestep are numbered robot by robot, frame 0 of a robot being its base.
+struct TeamDev {
+    int n_robots;
+    int S;                 // total spheres
+    int F;                 // frame slots per timestep: sum over robots of (n_joints + 1)
+    int n_self;            // flattened self-collision pairs
+    int n_rr_tasks;        // (slot, partner robot) tasks per timestep
+    int n_slots;           // ceil(S / 64)
+    int P;                 // robot pairs n(n-1)/2
+    int max_dof;
+    long long rr_tests_per_t;   // sum_{i<j} n_i n_j
+    const int* r_nj;            // [n]
+    const int* r_joint_off;     // [n]
+    const int* r_sphere_off;    // [n+1]
+    const int* r_frame_off;     // [n]
+    const float* r_base32;      // [n][12]
+    const double* r_base64;     // [n][12]
+    const int* j_type;          // [joints]
+    const float* j_fixed32;     // [joints][12]
+    const double* j_fixed64;    // [joints][12]
+    const int* s_robot;         // [S]
+    const int* s_slot;          // [S] frame slot = r_frame_off[robot] + local frame
+    const int* s_lframe;        // [S] local frame 0..n_joints
+    const float4* s_local32;    // [S] centre, radius
+    const double* s_local64;    // [S][4]
+    const int2* self_pairs;     // [n_self] flattened sphere indices
+    const int2* rr_tasks;       // [n_rr_tasks] (slot, partner robot)
+};
+
+// Resident environment in the world frame.
+struct EnvDev {
+    int n_sph, n_box, n_cyl;
+    long long n_pts;
+    const float4* sph32;        // [n] centre, radius
+    const double* sph64;        // [n][4]
+    const float* box32;         // [n][16] centre(3), R^T row-major (9), half-extents(3), pad
+    const double* box64;        // [n][15] as given
+    const float* cyl32;         // [n][8] centre(3), axis(3), half-length, radius
+    const double* cyl64;        // [n][8]
+    // uniform grid over the point cloud (CSR by cell)
+    const float4* pts32;        // [n_pts] points sorted by cell (x, y, z, 0)
+    const double* pts64;        // [n_pts][3] in the same order
+    const int* cell_start;      // [n_cells + 1]
+    float grid_lo[3];
+    float grid_inv;             // 1 / cell size
+    float grid_cell;
+    int grid_dim[3];
+    float pt_radius;
+    double pt_radius64;
+};
+
+// One MV/FFC call.
+struct CallDev {
+    int n_queries;
+    int n_robots;
+    int dof_stride;
+    int kind;                   // 0 = MV, 1 = FFC
+    unsigned flags;
+    int chunk;                  // timesteps per tile
+    float eps32;
+    double eps64;
+    long long n_wp;
+    const long long* wp_begin;
+    const int* wp_t;
+    const double* wp_q;
+    // per-query scratch
+    int* T;
+    int* nt;
+    int* gstep;
+    int* status;                // 0 ok, 1 invalid input
+    unsigned* word;             // MV: hit flag; FFC: best key t*P + pair
+    int* sorted_q;
+    // tile enumeration scratch (sized for MRV_MAX_T / 1 + 2 bins)
+    int* hist;
+    int* start;
+    int* off;
+    int* ctrl;                  // [0] max nt, [1] total tiles, [2] tile counter, [3] invalid count
+    unsigned long long* stats;  // [ST_COUNT]
+    // outputs
+    unsigned char* valid_out;
+    int* conflict_out;          // [n_queries][3]
+};
+
+// Kernel launchers (mrv_kernels.hip).  All launch on `stream` and return the
+// first launch error.
+hipError_t launch_prepare(const TeamDev& tm, const CallDev& cd, hipStream_t stream);
+hipError_t launch_validate(const TeamDev& tm, const EnvDev& env, const CallDev& cd, int grid,
+                           size_t lds_bytes, hipStream_t stream);
+hipError_t launch_finalize(const TeamDev& tm, const CallDev& cd, hipStream_t stream);
+hipError_t fill_u32(void* p, unsigned v, size_t n, hipStream_t stream);
+// Occupancy-derived workgroups per CU for the validation kernel.
+int validate_blocks_per_cu(int kind, size_t lds_bytes);
+
+}  // namespace mrv

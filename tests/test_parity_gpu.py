@@ -1,0 +1,206 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+MV booleans and FFC (t, i, j) must be identical (bit-exact for these integer
+results); the FP32 tests are exact thanks to the FP64 re-evaluation of
+near-contact tests.  Sizes are chosen so the oracle finishes in seconds while
+the GPU path still spans many tiles and ragged tails.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2604_23960_amd import mrv
+from paper_2604_23960_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FLAG_SETS = [
+    mrv.CHECK_ENV,
+    mrv.CHECK_ENV | mrv.EXHAUSTIVE,
+    mrv.CHECK_ENV | mrv.HIERARCHICAL,
+    mrv.CHECK_ENV | mrv.ORDER_RAKE,
+    mrv.CHECK_ENV | mrv.ORDER_LINEAR | mrv.EXHAUSTIVE,
+    0,
+    mrv.EXHAUSTIVE,
+]
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = mrv.Context(0)
+    yield c
+    c.close()
+
+
+def oracle_set(w):
+    return oracle.Team(w.team), oracle.Env(w.env), oracle.Paths(w.paths)
+
+
+def spread_arms(n_queries, seed=5, half=1.0):
+    models = W.arm_models(1)
+    team = [m.with_base(W.arm_base(x * half / 0.5, y * half / 0.5)) for m, (x, y) in zip(models, W.CORNERS)]
+    rng = np.random.default_rng([seed, 3])
+    p = W.random_timed_paths(rng, team, n_queries, 20, 400, 2, 6, 7)
+    return W.Workload("spread-arms", team, W.cube_env(1), p, "ffc")
+
+
+def test_disks_full_mv_ffc(ctx):
+    w = W.disks_workload(4096)
+    say("disks 4096 MV+FFC")
+    ot, oe, op = oracle_set(w)
+    team, env = ctx.load_team(w.team), ctx.load_env(w.env)
+    ref_mv = oracle.mv(ot, oe, op)
+    ref_ffc = oracle.ffc(ot, op)
+    for flags in FLAG_SETS:
+        got = ctx.mv(team, env, w.paths, flags)
+        ref = ref_mv if flags & mrv.CHECK_ENV else oracle.mv(ot, oe, op, check_env=False)
+        assert np.array_equal(got, ref), f"flags={flags}: {np.nonzero(got != ref)[0][:10]}"
+    got = ctx.ffc(team, w.paths)
+    assert np.array_equal(got, ref_ffc), np.nonzero(np.any(got != ref_ffc, axis=1))[0][:10]
+    got = ctx.ffc(team, w.paths, mrv.EXHAUSTIVE)
+    assert np.array_equal(got, ref_ffc)
+
+
+@pytest.fixture(scope="module")
+def arms():
+    w = W.arms_workload(768)
+    return w, oracle_set(w)
+
+
+@pytest.mark.parametrize("flags", FLAG_SETS)
+def test_arms_mv(ctx, arms, flags):
+    w, (ot, oe, op) = arms
+    say("arms MV flags", flags)
+    team, env = ctx.load_team(w.team), ctx.load_env(w.env)
+    got = ctx.mv(team, env, w.paths, flags)
+    ref = oracle.mv(ot, oe, op, check_env=bool(flags & mrv.CHECK_ENV))
+    assert np.array_equal(got, ref), np.nonzero(got != ref)[0][:10]
+    if not flags & mrv.CHECK_ENV:
+        assert 0 < ref.sum() < len(ref)
+
+
+def test_arms_ffc(ctx, arms):
+    w, (ot, oe, op) = arms
+    say("arms FFC")
+    team = ctx.load_team(w.team)
+    ref = oracle.ffc(ot, op)
+    for flags in (0, mrv.EXHAUSTIVE):
+        got = ctx.ffc(team, w.paths, flags)
+        assert np.array_equal(got, ref), np.nonzero(np.any(got != ref, axis=1))[0][:10]
+
+
+def test_spread_arms_ffc_late_conflicts(ctx):
+    w = spread_arms(384)
+    say("spread arms FFC 384")
+    ot, op = oracle.Team(w.team), oracle.Paths(w.paths)
+    ref = oracle.ffc(ot, op)
+    assert (ref[:, 0] > 20).sum() > 5 and (ref[:, 0] < 0).sum() > 100
+    team = ctx.load_team(w.team)
+    for chunk in (0, 1, 3, 10):
+        ctx.set_tiling(team, 1, chunk)
+        got = ctx.ffc(team, w.paths)
+        assert np.array_equal(got, ref), (chunk, np.nonzero(np.any(got != ref, axis=1))[0][:10])
+    # MV without environment is the same question
+    got = ctx.mv(team, -1, w.paths, 0)
+    assert np.array_equal(got.astype(bool), ref[:, 0] < 0)
+
+
+def test_hetero_ffc(ctx):
+    w = W.ffc_workload(384)
+    say("hetero FFC 384")
+    ot, op = oracle.Team(w.team), oracle.Paths(w.paths)
+    ref = oracle.ffc(ot, op)
+    team = ctx.load_team(w.team)
+    for chunk in (0, 5):
+        ctx.set_tiling(team, 1, chunk)
+        got = ctx.ffc(team, w.paths)
+        assert np.array_equal(got, ref), np.nonzero(np.any(got != ref, axis=1))[0][:10]
+
+
+@pytest.mark.parametrize("chunk", [1, 2, 7, 10])
+def test_arms_mv_chunk_independent(ctx, arms, chunk):
+    w, (ot, oe, op) = arms
+    say("arms MV chunk", chunk)
+    team, env = ctx.load_team(w.team), ctx.load_env(w.env)
+    ctx.set_tiling(team, 0, chunk)
+    ref = oracle.mv(ot, oe, op, check_env=False)
+    got = ctx.mv(team, env, w.paths, 0)
+    assert np.array_equal(got, ref)
+    got = ctx.mv(team, env, w.paths, mrv.CHECK_ENV | mrv.EXHAUSTIVE)
+    assert np.array_equal(got, oracle.mv(ot, oe, op))
+
+
+def test_device_entry_points_match_host(ctx, arms):
+    import torch
+    w, (ot, oe, op) = arms
+    say("device entry points")
+    team, env = ctx.load_team(w.team), ctx.load_env(w.env)
+    dp = mrv.DevicePaths(w.paths)
+    out = torch.zeros(w.paths.n_queries, dtype=torch.uint8, device="cuda")
+    ctx.mv_device(team, env, dp, mrv.CHECK_ENV, out.data_ptr())
+    ctx.sync()
+    assert np.array_equal(out.cpu().numpy(), oracle.mv(ot, oe, op))
+    cf = torch.zeros((w.paths.n_queries, 3), dtype=torch.int32, device="cuda")
+    ctx.ffc_device(team, dp, 0, cf.data_ptr())
+    ctx.sync()
+    assert np.array_equal(cf.cpu().numpy(), oracle.ffc(ot, op))
+
+
+def test_edge_cases(ctx):
+    say("edge cases")
+    w = W.arms_workload(64)
+    ot, oe = oracle.Team(w.team), oracle.Env(w.env)
+    team, env = ctx.load_team(w.team), ctx.load_env(w.env)
+    # zero-length motions: one state each
+    rows = [[(np.array([0]), w.paths.path(q, r)[1][:1]) for r in range(4)] for q in range(64)]
+    p0 = W.paths_from_lists(rows, 7)
+    assert np.array_equal(ctx.mv(team, env, p0, mrv.CHECK_ENV), oracle.mv(ot, oe, oracle.Paths(p0)))
+    assert np.array_equal(ctx.ffc(team, p0), oracle.ffc(ot, oracle.Paths(p0)))
+    # one robot: FFC is always null, MV without env always valid
+    one = ctx.load_team(w.team[:1])
+    p1 = W.paths_from_lists([[w.paths.path(q, 0)] for q in range(64)], 7)
+    assert np.all(ctx.ffc(one, p1)[:, 0] == -1)
+    assert np.all(ctx.mv(one, -1, p1, 0) == 1)
+    assert np.array_equal(ctx.mv(one, env, p1, mrv.CHECK_ENV),
+                          oracle.mv(oracle.Team(w.team[:1]), oe, oracle.Paths(p1)))
+    # empty query list
+    pe = W.paths_from_lists([], 7)
+    assert ctx.mv(team, env, pe, mrv.CHECK_ENV).shape == (0,)
+    # uneven lengths with padding: robots end at different times
+    rng = np.random.default_rng(3)
+    rows = []
+    for q in range(48):
+        rows.append([(np.array([0, int(rng.integers(1, 90))]), rng.uniform(-2.9, 2.9, (2, 7))) for _ in range(4)])
+    pu = W.paths_from_lists(rows, 7)
+    assert np.array_equal(ctx.mv(team, env, pu, 0), oracle.mv(ot, oe, oracle.Paths(pu), check_env=False))
+    assert np.array_equal(ctx.ffc(team, pu), oracle.ffc(ot, oracle.Paths(pu)))
+
+
+def test_invalid_inputs_rejected(ctx):
+    say("invalid inputs")
+    w = W.arms_workload(8)
+    team, env = ctx.load_team(w.team), ctx.load_env(w.env)
+    bad = W.paths_from_lists([[w.paths.path(q, r) for r in range(4)] for q in range(8)], 7)
+    bad.wp_t = bad.wp_t.copy()
+    bad.wp_t[1] = 0          # non-increasing time in the first path
+    out = np.full(8, 7, np.uint8)
+    with pytest.raises(mrv.MrvError) as e:
+        ctx.mv(team, env, bad, mrv.CHECK_ENV)
+    assert e.value.status == mrv.MRV_E_INVALID
+    with pytest.raises(mrv.MrvError) as e:
+        ctx.mv(team + 1000, env, w.paths, mrv.CHECK_ENV)
+    assert e.value.status == mrv.MRV_E_HANDLE
+    # the device path flags the malformed query and reports at sync
+    import torch
+    dp = mrv.DevicePaths(bad)
+    o = torch.zeros(8, dtype=torch.uint8, device="cuda")
+    ctx.mv_device(team, env, dp, mrv.CHECK_ENV, o.data_ptr())
+    with pytest.raises(mrv.MrvError):
+        ctx.sync()
+    assert o.cpu().numpy()[0] == 2
+    ctx.sync()   # error reported once
+    del out
