@@ -100,6 +100,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-queries", type=int, default=65536)
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="first run a plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
@@ -113,6 +115,14 @@ def main():
     def log(*a):
         print("[bench]", *a, file=sys.stderr, flush=True)
 
+    if args.copy_calib_mib > 0:
+        n = args.copy_calib_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {args.copy_calib_mib} MiB read + written")
+        del src, dst
     log("generating the four-arm workload")
     w = W.arms_workload(args.queries)
     ctx = mrv.Context(0)

@@ -189,6 +189,22 @@ int build_team(mrv_ctx ctx, const mrv_robot_desc* robots, int n, TeamHost& out)
             rr_tasks.push_back(rb);
         }
     }
+    // sphere groups: up to 16 consecutive spheres of one robot
+    std::vector<int> s_group(S), r_group_off(n + 1, 0), g_range;
+    int G = 0;
+    for (int r = 0; r < n; ++r) {
+        r_group_off[r] = G;
+        for (int b = r_sphere_off[r]; b < r_sphere_off[r + 1]; b += 16) {
+            const int e = std::min(b + 16, r_sphere_off[r + 1]);
+            for (int s2 = b; s2 < e; ++s2) s_group[s2] = G;
+            g_range.push_back(b);
+            g_range.push_back(e);
+            ++G;
+        }
+    }
+    r_group_off[n] = G;
+    float r_max = 0.f;
+    for (int s2 = 0; s2 < S; ++s2) r_max = std::max(r_max, s_local32[s2 * 4 + 3]);
     long long rr_per_t = 0;
     for (int i = 0; i < n; ++i)
         for (int j = i + 1; j < n; ++j)
@@ -199,7 +215,8 @@ int build_team(mrv_ctx ctx, const mrv_robot_desc* robots, int n, TeamHost& out)
                  o_fo = pk.add(r_frame_off), o_b32 = pk.add(base32), o_b64 = pk.add(base64),
                  o_jt = pk.add(j_type), o_j32 = pk.add(j32), o_j64 = pk.add(j64), o_sr = pk.add(s_robot),
                  o_ss = pk.add(s_slot), o_sl = pk.add(s_lframe), o_l32 = pk.add(s_local32),
-                 o_l64 = pk.add(s_local64), o_sp = pk.add(self_pairs), o_rt = pk.add(rr_tasks);
+                 o_l64 = pk.add(s_local64), o_sp = pk.add(self_pairs), o_rt = pk.add(rr_tasks),
+                 o_sg = pk.add(s_group), o_gr = pk.add(g_range), o_rg = pk.add(r_group_off);
     void* d = nullptr;
     if (hipMalloc(&d, pk.bytes.size()) != hipSuccess) throw Err{MRV_E_NOMEM, "team upload allocation failed"};
     if (hipMemcpy(d, pk.bytes.data(), pk.bytes.size(), hipMemcpyHostToDevice) != hipSuccess) {
@@ -216,7 +233,12 @@ int build_team(mrv_ctx ctx, const mrv_robot_desc* robots, int n, TeamHost& out)
     t.n_slots = n_slots;
     t.P = n * (n - 1) / 2;
     t.max_dof = max_dof;
+    t.G = G;
+    t.r_max = r_max;
     t.rr_tests_per_t = rr_per_t;
+    t.s_group = (const int*)at(o_sg);
+    t.g_range = (const int2*)at(o_gr);
+    t.r_group_off = (const int*)at(o_rg);
     t.r_nj = (const int*)at(o_nj);
     t.r_joint_off = (const int*)at(o_jo);
     t.r_sphere_off = (const int*)at(o_so);
@@ -272,12 +294,18 @@ void build_env(const mrv_env_desc* e, EnvHost& out)
                     throw Err{MRV_E_INVALID, "box rotation is not orthonormal"};
             }
         if (b[12] < 0 || b[13] < 0 || b[14] < 0) throw Err{MRV_E_INVALID, "negative box half-extent"};
-        float row[16] = {(float)b[0], (float)b[1], (float)b[2],
-                         // R^T row-major: row k of R^T = column k of R
-                         (float)R[0], (float)R[3], (float)R[6],
-                         (float)R[1], (float)R[4], (float)R[7],
-                         (float)R[2], (float)R[5], (float)R[8],
-                         (float)b[12], (float)b[13], (float)b[14], 0.f};
+        // box frame coordinates p_k = (R^T)_k . x - (R^T c)_k: row k of R^T is column k of R
+        float row[16];
+        for (int k = 0; k < 3; ++k) {
+            row[4 * k + 0] = (float)R[0 * 3 + k];
+            row[4 * k + 1] = (float)R[1 * 3 + k];
+            row[4 * k + 2] = (float)R[2 * 3 + k];
+            row[4 * k + 3] = (float)(-(R[0 * 3 + k] * b[0] + R[1 * 3 + k] * b[1] + R[2 * 3 + k] * b[2]));
+        }
+        row[12] = (float)b[12];
+        row[13] = (float)b[13];
+        row[14] = (float)b[14];
+        row[15] = 0.f;
         box32.insert(box32.end(), row, row + 16);
     }
     std::vector<float> cyl32;
@@ -414,10 +442,15 @@ long long max_horizon(const mrv_paths* p, int n_robots)
     return m;
 }
 
+size_t lds_per_t(const TeamHost& tm)
+{
+    return (size_t)tm.dev.S * 16 + (size_t)tm.dev.S * 4 + (size_t)tm.dev.G * 16 + (size_t)tm.dev.F * 48;
+}
+
 int default_chunk(const TeamHost& tm, int kind)
 {
-    const size_t per_t = (size_t)(tm.dev.S + 3 * tm.dev.F) * sizeof(float4);
-    int cmax = (int)((kLdsBudget - 8 * 1024) / per_t);
+    const size_t per_t = lds_per_t(tm);
+    int cmax = (int)((kLdsBudget - 2 * 1024) / per_t);
     cmax = std::min(cmax, kMaxChunk);
     if (cmax < 1) cmax = 1;
     const int want = kind == 0 ? 8 : 8;
@@ -426,7 +459,7 @@ int default_chunk(const TeamHost& tm, int kind)
 
 size_t lds_bytes_for(const TeamHost& tm, int chunk)
 {
-    return (size_t)chunk * (size_t)(tm.dev.S + 3 * tm.dev.F) * sizeof(float4);
+    return (size_t)chunk * lds_per_t(tm) + 64;
 }
 
 }  // namespace
@@ -444,6 +477,7 @@ void ensure_scratch(Scratch& sc, size_t bins, size_t queries)
         HIPCHK(hipEventCreate(&sc.ev0));
         HIPCHK(hipEventCreate(&sc.ev1));
     }
+    sc.gq.ensure((size_t)Scratch::kGlobalRecheckCap * 16);
     if (bins > sc.bins) {
         sc.hist.release();
         sc.start.release();
@@ -506,6 +540,8 @@ void run_call(mrv_ctx ctx, Scratch& sc, TeamHost& tm, const EnvHost* env, int ki
     cd.start = (int*)sc.start.p;
     cd.off = (int*)sc.off.p;
     cd.ctrl = (int*)sc.ctrl.p;
+    cd.gq = (int4*)sc.gq.p;
+    cd.gq_cap = Scratch::kGlobalRecheckCap;
     cd.stats = (unsigned long long*)((char*)sc.ctrl.p + 64);
     cd.valid_out = kind == 0 ? (unsigned char*)out_dev : nullptr;
     cd.conflict_out = kind == 1 ? (int*)out_dev : nullptr;
@@ -564,6 +600,12 @@ void host_call(mrv_ctx ctx, int team, int env, int kind, const mrv_paths* p, uin
     DevPaths dp{(const long long*)ctx->in_begin.p, (const int*)ctx->in_t.p, (const double*)ctx->in_q.p,
                 p->n_wp, p->n_queries, p->dof_stride};
     run_call(ctx, ctx->sc, tm, ev, kind, flags, dp, max_horizon(p, n), ctx->out_buf.p, ctx->stream);
+    int unresolved = 0;
+    HIPCHK(hipMemcpyAsync(&unresolved, (int*)ctx->sc.ctrl.p + 1, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (unresolved)
+        throw Err{MRV_E_NOMEM, std::to_string(unresolved) +
+                                   " queries exceeded the near-contact re-evaluation queue; split the batch"};
     HIPCHK(hipMemcpyAsync(out_host, ctx->out_buf.p, nout, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
 }
@@ -777,10 +819,11 @@ mrv_status mrv_ffc_device(mrv_ctx ctx, int32_t team, const mrv_paths* paths, uin
 mrv_status mrv_sync(mrv_ctx ctx)
 {
     if (guard(ctx)) return MRV_E_HANDLE;
-    int bad = 0;
+    int bad = 0, unresolved = 0;
     mrv_status st = wrap([&] {
         set_device(ctx);
         HIPCHK(hipStreamSynchronize(ctx->stream));
+        HIPCHK(hipMemcpy(&unresolved, (int*)ctx->sc.ctrl.p + 1, sizeof(int), hipMemcpyDeviceToHost));
         HIPCHK(hipMemcpy(&bad, (int*)ctx->sc.ctrl.p + 3, sizeof(int), hipMemcpyDeviceToHost));
         if (bad) {
             const int zero = 0;
@@ -789,6 +832,9 @@ mrv_status mrv_sync(mrv_ctx ctx)
     });
     if (st != MRV_OK) return st;
     if (bad) return fail(MRV_E_INVALID, std::to_string(bad) + " queries had malformed path data");
+    if (unresolved)
+        return fail(MRV_E_NOMEM, std::to_string(unresolved) +
+                                     " queries exceeded the near-contact re-evaluation queue (results 3 / t = -3)");
     return MRV_OK;
 }
 
@@ -824,7 +870,7 @@ mrv_status mrv_set_tiling(mrv_ctx ctx, int32_t team, int32_t kind, const mrv_til
         std::lock_guard<std::mutex> lk(ctx->handle_mu);
         TeamHost& tm = find_team(ctx, team);
         if (tiling->chunk < 0 || tiling->chunk > kMaxChunk) throw Err{MRV_E_INVALID, "chunk out of range"};
-        if (tiling->chunk > 0 && lds_bytes_for(tm, tiling->chunk) > (size_t)kLdsBudget - 8 * 1024)
+        if (tiling->chunk > 0 && lds_bytes_for(tm, tiling->chunk) > (size_t)kLdsBudget - 2 * 1024)
             throw Err{MRV_E_INVALID, "chunk does not fit in LDS for this team"};
         if (tiling->wg_per_cu < 0 || tiling->wg_per_cu > 32) throw Err{MRV_E_INVALID, "wg_per_cu out of range"};
         tm.tiling[kind] = *tiling;

@@ -13,7 +13,6 @@ constexpr int kWavesPerWG = kWG / kWave;
 constexpr int kMaxRobots = 32;
 constexpr int kMaxJoints = 8;
 constexpr int kMaxChunk = 64;       // timesteps per tile
-constexpr int kRecheckCap = 256;    // FP64 re-evaluations queued per tile before inline fallback
 constexpr int kLdsBudget = 64 * 1024;
 
 enum RecheckKind : int { RK_RR = 0, RK_SELF = 1, RK_ENV_SPH = 2, RK_ENV_BOX = 3, RK_ENV_CYL = 4, RK_ENV_PT = 5 };
@@ -35,6 +34,8 @@ struct TeamDev {
     int n_slots;           // ceil(S / 64)
     int P;                 // robot pairs n(n-1)/2
     int max_dof;
+    int G;                 // sphere groups per timestep (16 consecutive spheres of one robot)
+    float r_max;           // largest sphere radius of the team
     long long rr_tests_per_t;   // sum_{i<j} n_i n_j
     const int* r_nj;            // [n]
     const int* r_joint_off;     // [n]
@@ -50,6 +51,9 @@ struct TeamDev {
     const int* s_lframe;        // [S] local frame 0..n_joints
     const float4* s_local32;    // [S] centre, radius
     const double* s_local64;    // [S][4]
+    const int* s_group;         // [S] group of each sphere
+    const int2* g_range;        // [G] sphere range [begin, end) of each group
+    const int* r_group_off;     // [n+1] first group of each robot
     const int2* self_pairs;     // [n_self] flattened sphere indices
     const int2* rr_tasks;       // [n_rr_tasks] (slot, partner robot)
 };
@@ -60,7 +64,7 @@ struct EnvDev {
     long long n_pts;
     const float4* sph32;        // [n] centre, radius
     const double* sph64;        // [n][4]
-    const float* box32;         // [n][16] centre(3), R^T row-major (9), half-extents(3), pad
+    const float* box32;         // [n][16] rows (R^T row k, -(R^T c)_k) for k = 0..2, then half-extents, pad
     const double* box64;        // [n][15] as given
     const float* cyl32;         // [n][8] centre(3), axis(3), half-length, radius
     const double* cyl64;        // [n][8]
@@ -101,7 +105,10 @@ struct CallDev {
     int* hist;
     int* start;
     int* off;
-    int* ctrl;                  // [0] max nt, [1] total tiles, [2] tile counter, [3] invalid count
+    int* ctrl;                  // [0] max nt, [1] unresolved queries, [2] global recheck count,
+                                // [3] invalid-input queries (kept until read), then u64 total tiles, u64 next tile
+    int4* gq;                   // global recheck queue, 2 int4 per record
+    int gq_cap;
     unsigned long long* stats;  // [ST_COUNT]
     // outputs
     unsigned char* valid_out;

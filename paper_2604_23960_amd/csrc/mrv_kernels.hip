@@ -362,15 +362,17 @@ __global__ void k_finalize(TeamDev tm, CallDev cd)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= cd.n_queries) return;
-    const bool bad = cd.status[q] != 0;
+    const int st = cd.status[q];
+    const bool bad = st != 0;
     const unsigned w = cd.word[q];
+    if (st == 2) atomicAdd(&cd.ctrl[1], 1);
     if (cd.kind == 0) {
-        cd.valid_out[q] = bad ? 2 : (w == 0u ? 1 : 0);
+        cd.valid_out[q] = bad ? (st == 2 ? 3 : 2) : (w == 0u ? 1 : 0);
         return;
     }
     int t = -1, ri = -1, rj = -1;
     if (bad) {
-        t = ri = rj = -2;
+        t = ri = rj = (st == 2 ? -3 : -2);
     } else if (w != 0xFFFFFFFFu) {
         const int n = tm.n_robots;
         const unsigned P = (unsigned)tm.P;
@@ -395,16 +397,83 @@ __global__ void k_fill_u32(unsigned* p, unsigned v, size_t n)
 // ---------------------------------------------------------------------------
 // validation
 
-struct Tile {
-    int q, k, phase, nv;
-};
-
-__device__ __forceinline__ void push_recheck(int4* rq, int* rqn, int kind, int c, int a, int b,
-                                             bool& overflow)
+// Queue a near-contact test for FP64 re-evaluation by k_recheck, which runs after
+// the validation kernel; when the call's queue is full the query is marked
+// unresolved (status 2) and the call reports the overflow.
+__device__ __forceinline__ void push_recheck(const CallDev& cd, int q, int t, int kind, int a, int b)
 {
-    const int i = atomicAdd(rqn, 1);
-    if (i < kRecheckCap) rq[i] = make_int4(kind | (c << 8), a, b, 0);
-    else overflow = true;
+    const unsigned g = atomicAdd(reinterpret_cast<unsigned*>(cd.ctrl + 2), 1u);
+    if (g < (unsigned)cd.gq_cap) cd.gq[g] = make_int4(q, t | (kind << 24), a, b);
+    else atomicMax(cd.status + q, 2);
+}
+
+// One robot-robot rotation step: lane L tests its sphere (a-side, scaled by -2 and
+// centred on the group) against partner record (L + R) mod 16 of its 16-lane row:
+//   acc = w_b + ax x_b + ay y_b + az z_b + ar r_b.
+template <int R>
+__device__ __forceinline__ float rr_step(float bw, float bx, float by, float bz, float br, float ax, float ay,
+                                         float az, float ar)
+{
+    float acc;
+    asm("v_mov_b32_dpp %0, %1 row_ror:%c2 row_mask:0xf bank_mask:0xf" : "=v"(acc) : "v"(bw), "i"(R));
+    asm("v_fmac_f32_dpp %0, %1, %2 row_ror:%c3 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(bx), "v"(ax), "i"(R));
+    asm("v_fmac_f32_dpp %0, %1, %2 row_ror:%c3 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(by), "v"(ay), "i"(R));
+    asm("v_fmac_f32_dpp %0, %1, %2 row_ror:%c3 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(bz), "v"(az), "i"(R));
+    asm("v_fmac_f32_dpp %0, %1, %2 row_ror:%c3 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(br), "v"(ar), "i"(R));
+    return acc;
+}
+
+// Minimum over the 16 records of a row of  w_b - 2 a'.b' - 2 ra rb.
+__device__ __forceinline__ float rr_group_min(float bw, float bx, float by, float bz, float br, float ax, float ay,
+                                              float az, float ar)
+{
+    float m = fmaf(ax, bx, fmaf(ay, by, fmaf(az, bz, fmaf(ar, br, bw))));
+#define MRV_RR2(R1, R2) m = fminf(m, fminf(rr_step<R1>(bw, bx, by, bz, br, ax, ay, az, ar), \
+                                             rr_step<R2>(bw, bx, by, bz, br, ax, ay, az, ar)));
+    MRV_RR2(1, 2) MRV_RR2(3, 4) MRV_RR2(5, 6) MRV_RR2(7, 8) MRV_RR2(9, 10) MRV_RR2(11, 12) MRV_RR2(13, 14)
+#undef MRV_RR2
+    m = fminf(m, rr_step<15>(bw, bx, by, bz, br, ax, ay, az, ar));
+    return m;
+}
+
+__device__ __forceinline__ float wave_max_f32(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Squared distance from x to a box surface region (0 inside), box in the
+// precomputed row form of EnvDev::box32.
+__device__ __forceinline__ float box_val(float x, float y, float z, const float* B)
+{
+    const float p0 = fmaf(B[0], x, fmaf(B[1], y, fmaf(B[2], z, B[3])));
+    const float p1 = fmaf(B[4], x, fmaf(B[5], y, fmaf(B[6], z, B[7])));
+    const float p2 = fmaf(B[8], x, fmaf(B[9], y, fmaf(B[10], z, B[11])));
+    const float e0 = fmaxf(fabsf(p0) - B[12], 0.f);
+    const float e1 = fmaxf(fabsf(p1) - B[13], 0.f);
+    const float e2 = fmaxf(fabsf(p2) - B[14], 0.f);
+    return fmaf(e0, e0, fmaf(e1, e1, e2 * e2));
+}
+
+__device__ __forceinline__ float cyl_val(float x, float y, float z, const float* Y)
+{
+    const float vx = x - Y[0], vy = y - Y[1], vz = z - Y[2];
+    const float h = fmaf(vx, Y[3], fmaf(vy, Y[4], vz * Y[5]));
+    const float wx = fmaf(-h, Y[3], vx), wy = fmaf(-h, Y[4], vy), wz = fmaf(-h, Y[5], vz);
+    const float sr = sqrtf(fmaf(wx, wx, fmaf(wy, wy, wz * wz)));
+    const float er = fmaxf(sr - Y[7], 0.f);
+    const float ea = fmaxf(fabsf(h) - Y[6], 0.f);
+    return fmaf(er, er, ea * ea);
+}
+
+// 0 free, 1 hit, 2 near contact, for a squared distance d2 against a contact distance R.
+__device__ __forceinline__ int classify(float d2, float R, float eps)
+{
+    const float hi = R + eps;
+    if (d2 > hi * hi) return 0;
+    const float lo = fmaxf(R - eps, 0.f);
+    return d2 < lo * lo ? 1 : 2;
 }
 
 template <int KIND>
@@ -414,14 +483,16 @@ __global__ __launch_bounds__(kWG) void k_validate(TeamDev tm, EnvDev env, CallDe
     const int C = cd.chunk;
     const int S = tm.S;
     const int F = tm.F;
+    const int G = tm.G;
     const int n = tm.n_robots;
-    float4* sph = dyn;                 // [C][S] centre xyz, radius
-    float4* fr = dyn + C * S;          // [C][F][3] frame rows (R row, p)
+    float4* rec = dyn;                                  // [C][S] (x', y', z', r) relative to the group centre
+    float* rw = reinterpret_cast<float*>(dyn + C * S);  // [C][S] w' = |x'|^2 - r^2
+    float4* gc = dyn + C * S + (C * S + 3) / 4;         // [C][G] group centres
+    float4* fr = gc + C * G;                            // [C][F][3] frame rows
 
     __shared__ int s_t[kMaxChunk];
-    __shared__ int s_q, s_k, s_nv, s_phase, s_hit, s_rqn;
-    __shared__ unsigned s_key;
-    __shared__ int4 s_rq[kRecheckCap];
+    __shared__ int s_q, s_nv, s_phase, s_hit;
+    __shared__ unsigned s_key, s_rho2;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -440,15 +511,13 @@ __global__ __launch_bounds__(kWG) void k_validate(TeamDev tm, EnvDev env, CallDe
 
     long long k_cur = 0;
     int phase_cur = 0;
-    unsigned long long n_rr = 0, n_env = 0, n_self = 0;
-    unsigned long long n_run = 0, n_skip = 0, n_states = 0, n_re = 0;
-
-    if (tid == 0) { s_rqn = 0; }
+    unsigned long long c_rr = 0, c_env = 0, c_self = 0;                 // wave-uniform counters
+    unsigned long long n_run = 0, n_skip = 0, n_states = 0;             // thread 0
 
     for (;;) {
         if (tid == 0) {
             const long long g = (long long)atomicAdd(&w64[1], 1ull);
-            int q = -1, k = 0, phase = 0, nv = 0;
+            int q = -1, nv = 0, phase = 0;
             if (g < gtotal) {
                 long long gg = g;
                 if (hier) {
@@ -474,7 +543,7 @@ __global__ __launch_bounds__(kWG) void k_validate(TeamDev tm, EnvDev env, CallDe
                     }
                 }
                 k_cur = lo;
-                k = (int)lo;
+                const int k = (int)lo;
                 q = cd.sorted_q[gg - off[lo]];
                 const int T = cd.T[q];
                 const int nt = cd.nt[q];
@@ -497,11 +566,9 @@ __global__ __launch_bounds__(kWG) void k_validate(TeamDev tm, EnvDev env, CallDe
                 }
                 if (skip) { nv = 0; ++n_skip; }
                 else { ++n_run; n_states += (unsigned long long)nv * n; }
-            } else {
-                q = -1;
             }
-            s_q = q; s_k = k; s_phase = phase; s_nv = nv;
-            s_hit = 0; s_key = 0xFFFFFFFFu;
+            s_q = q; s_phase = phase; s_nv = nv;
+            s_hit = 0; s_key = 0xFFFFFFFFu; s_rho2 = 0u;
         }
         __syncthreads();
         const int q = s_q;
@@ -590,108 +657,158 @@ __global__ __launch_bounds__(kWG) void k_validate(TeamDev tm, EnvDev env, CallDe
         }
         __syncthreads();
 
-        // --- sphere placement: one lane per (timestep, sphere)
+        // --- sphere centres (absolute, temporarily), one lane per (timestep, sphere)
         for (int idx = tid; idx < nv * S; idx += kWG) {
             const int c = idx / S;
             const int s = idx - c * S;
             const float4 L = tm.s_local32[s];
             const float4* Fp = fr + ((long long)c * F + tm.s_slot[s]) * 3;
             const float4 r0 = Fp[0], r1 = Fp[1], r2 = Fp[2];
-            sph[idx] = make_float4(r0.x * L.x + r0.y * L.y + r0.z * L.z + r0.w,
-                                   r1.x * L.x + r1.y * L.y + r1.z * L.z + r1.w,
-                                   r2.x * L.x + r2.y * L.y + r2.z * L.z + r2.w, L.w);
+            rec[idx] = make_float4(fmaf(r0.x, L.x, fmaf(r0.y, L.y, fmaf(r0.z, L.z, r0.w))),
+                                   fmaf(r1.x, L.x, fmaf(r1.y, L.y, fmaf(r1.z, L.z, r1.w))),
+                                   fmaf(r2.x, L.x, fmaf(r2.y, L.y, fmaf(r2.z, L.z, r2.w))), L.w);
         }
         __syncthreads();
-
-        bool overflow = false;   // this lane queued more than the tile capacity
+        // --- group centres: mean of the group's sphere centres
+        for (int idx = tid; idx < nv * G; idx += kWG) {
+            const int c = idx / G;
+            const int2 rg = tm.g_range[idx - c * G];
+            float sx = 0.f, sy = 0.f, sz = 0.f;
+            for (int s = rg.x; s < rg.y; ++s) {
+                const float4 X = rec[c * S + s];
+                sx += X.x; sy += X.y; sz += X.z;
+            }
+            const float inv = 1.f / (float)(rg.y - rg.x);
+            gc[idx] = make_float4(sx * inv, sy * inv, sz * inv, 0.f);
+        }
+        __syncthreads();
+        // --- records relative to the group centre
+        {
+            float r2max = 0.f;
+            for (int idx = tid; idx < nv * S; idx += kWG) {
+                const int c = idx / S;
+                const int s = idx - c * S;
+                const float4 X = rec[idx];
+                const float4 O = gc[c * G + tm.s_group[s]];
+                const float x = X.x - O.x, y = X.y - O.y, z = X.z - O.z;
+                const float d2 = fmaf(x, x, fmaf(y, y, z * z));
+                rec[idx] = make_float4(x, y, z, X.w);
+                rw[idx] = fmaf(-X.w, X.w, d2);
+                r2max = fmaxf(r2max, d2);
+            }
+            r2max = wave_max_f32(r2max);
+            if (lane == 0) atomicMax(&s_rho2, __float_as_uint(r2max));
+        }
+        __syncthreads();
 
         // --- robot-obstacle and self tests (MV with environment checking)
         if (do_env) {
             const int nslots = tm.n_slots;
             const int ntask = nv * nslots;
+            float ro_max = 0.f;
+            for (int o = 0; o < env.n_sph; ++o) ro_max = fmaxf(ro_max, env.sph32[o].w);
             for (int task = wave; task < ntask; task += kWavesPerWG) {
                 if (!exhaustive && *(volatile int*)&s_hit) break;
                 const int c = task / nslots;
-                const int slot = task - c * nslots;
-                const int a = slot * 64 + lane;
-                bool hit = false;
+                const int a = (task - c * nslots) * 64 + lane;
+                bool hit = false, unsure = false;
+                float X0 = 0.f, X1 = 0.f, X2 = 0.f, rad = 0.f;
                 if (a < S) {
-                    const float4 X = sph[c * S + a];
-                    const float rlo = X.w - eps, rhi = X.w + eps;
-                    const float lo2 = rlo * rlo, hi2 = rhi * rhi;
+                    const float4 Xr = rec[c * S + a];
+                    const float4 O = gc[c * G + tm.s_group[a]];
+                    X0 = Xr.x + O.x; X1 = Xr.y + O.y; X2 = Xr.z + O.z; rad = Xr.w;
+                    float mb = 3.0e38f;
+                    for (int o = 0; o < env.n_box; ++o) mb = fminf(mb, box_val(X0, X1, X2, env.box32 + o * 16));
+                    for (int o = 0; o < env.n_cyl; ++o) mb = fminf(mb, cyl_val(X0, X1, X2, env.cyl32 + o * 8));
+                    float ms = 3.0e38f;
                     for (int o = 0; o < env.n_sph; ++o) {
-                        const float4 O = env.sph32[o];
-                        const float dx = X.x - O.x, dy = X.y - O.y, dz = X.z - O.z;
-                        const float d2 = dx * dx + dy * dy + dz * dz;
-                        const float R = X.w + O.w;
-                        const float Rh = R + eps;
-                        if (d2 <= Rh * Rh) {
-                            const float Rl = R - eps;
-                            if (d2 < Rl * Rl) hit = true;
-                            else push_recheck(s_rq, &s_rqn, RK_ENV_SPH, c, a, o, overflow);
-                        }
+                        const float4 Ob = env.sph32[o];
+                        const float dx = X0 - Ob.x, dy = X1 - Ob.y, dz = X2 - Ob.z;
+                        const float Rs = rad + Ob.w;
+                        ms = fminf(ms, fmaf(-Rs, Rs, fmaf(dx, dx, fmaf(dy, dy, dz * dz))));
                     }
-                    for (int o = 0; o < env.n_box; ++o) {
-                        const float* B = env.box32 + o * 16;
-                        const float vx = X.x - B[0], vy = X.y - B[1], vz = X.z - B[2];
-                        const float p0 = B[3] * vx + B[4] * vy + B[5] * vz;
-                        const float p1 = B[6] * vx + B[7] * vy + B[8] * vz;
-                        const float p2 = B[9] * vx + B[10] * vy + B[11] * vz;
-                        const float e0 = fmaxf(fabsf(p0) - B[12], 0.f);
-                        const float e1 = fmaxf(fabsf(p1) - B[13], 0.f);
-                        const float e2 = fmaxf(fabsf(p2) - B[14], 0.f);
-                        const float val = e0 * e0 + e1 * e1 + e2 * e2;
-                        if (val <= hi2) {
-                            if (val < lo2) hit = true;
-                            else push_recheck(s_rq, &s_rqn, RK_ENV_BOX, c, a, o, overflow);
-                        }
-                    }
-                    for (int o = 0; o < env.n_cyl; ++o) {
-                        const float* Y = env.cyl32 + o * 8;
-                        const float vx = X.x - Y[0], vy = X.y - Y[1], vz = X.z - Y[2];
-                        const float h = vx * Y[3] + vy * Y[4] + vz * Y[5];
-                        const float wx = vx - h * Y[3], wy = vy - h * Y[4], wz = vz - h * Y[5];
-                        const float sr = sqrtf(wx * wx + wy * wy + wz * wz);
-                        const float er = fmaxf(sr - Y[7], 0.f);
-                        const float ea = fmaxf(fabsf(h) - Y[6], 0.f);
-                        const float val = er * er + ea * ea;
-                        if (val <= hi2) {
-                            if (val < lo2) hit = true;
-                            else push_recheck(s_rq, &s_rqn, RK_ENV_CYL, c, a, o, overflow);
-                        }
-                    }
-                    if (env.n_pts > 0) {
-                        // uniform grid: visit cells overlapping the sphere's reach
-                        const float reach = X.w + env.pt_radius + eps;
+                    const float rlo = fmaxf(rad - eps, 0.f), rhi = rad + eps;
+                    const float Rb = rad + ro_max;
+                    hit = (mb < rlo * rlo) || (ms < -2.f * Rb * eps);
+                    unsure = !hit && ((mb <= rhi * rhi) || (ms <= fmaf(2.f * Rb, eps, eps * eps)));
+                    if (env.n_pts > 0 && !hit) {
+                        const float reach = rad + env.pt_radius + eps;
+                        const float xs[3] = { X0, X1, X2 };
                         int lo3[3], hi3[3];
-                        const float xs[3] = { X.x, X.y, X.z };
 #pragma unroll
                         for (int d = 0; d < 3; ++d) {
-                            int l = (int)floorf((xs[d] - reach - env.grid_lo[d]) * env.grid_inv);
-                            int h = (int)floorf((xs[d] + reach - env.grid_lo[d]) * env.grid_inv);
+                            const int l = (int)floorf((xs[d] - reach - env.grid_lo[d]) * env.grid_inv);
+                            const int h = (int)floorf((xs[d] + reach - env.grid_lo[d]) * env.grid_inv);
                             lo3[d] = l < 0 ? 0 : l;
                             hi3[d] = h >= env.grid_dim[d] ? env.grid_dim[d] - 1 : h;
                         }
-                        const float Rp = X.w + env.pt_radius;
-                        const float plo = (Rp - eps) * (Rp - eps), phi = (Rp + eps) * (Rp + eps);
-                        for (int cz = lo3[2]; cz <= hi3[2]; ++cz)
-                            for (int cy = lo3[1]; cy <= hi3[1]; ++cy) {
-                                const int row = (cz * env.grid_dim[1] + cy) * env.grid_dim[0];
-                                if (lo3[0] > hi3[0]) continue;
-                                const int pb = env.cell_start[row + lo3[0]];
-                                const int pe = env.cell_start[row + hi3[0] + 1];
-                                for (int p = pb; p < pe; ++p) {
-                                    const float4 Pt = env.pts32[p];
-                                    const float dx = X.x - Pt.x, dy = X.y - Pt.y, dz = X.z - Pt.z;
-                                    const float d2 = dx * dx + dy * dy + dz * dz;
-                                    if (d2 <= phi) {
-                                        if (d2 < plo) hit = true;
-                                        else push_recheck(s_rq, &s_rqn, RK_ENV_PT, c, a, p, overflow);
+                        const float Rp = rad + env.pt_radius;
+                        float mp = 3.0e38f;
+                        if (lo3[0] <= hi3[0])
+                            for (int cz = lo3[2]; cz <= hi3[2]; ++cz)
+                                for (int cy = lo3[1]; cy <= hi3[1]; ++cy) {
+                                    const int row = (cz * env.grid_dim[1] + cy) * env.grid_dim[0];
+                                    const int pb = env.cell_start[row + lo3[0]];
+                                    const int pe = env.cell_start[row + hi3[0] + 1];
+                                    for (int p = pb; p < pe; ++p) {
+                                        const float4 Pt = env.pts32[p];
+                                        const float dx = X0 - Pt.x, dy = X1 - Pt.y, dz = X2 - Pt.z;
+                                        mp = fminf(mp, fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
                                     }
                                 }
-                            }
+                        const int cl = classify(mp, Rp, eps);
+                        hit = cl == 1;
+                        unsure = unsure || cl == 2;
                     }
-                    n_env += (unsigned long long)(env.n_sph + env.n_box + env.n_cyl);
+                    c_env += (unsigned long long)(env.n_sph + env.n_box + env.n_cyl);
+                }
+                if (unsure && !hit) {
+                    // rare: find the near obstacles and settle each in FP64
+                    const float rlo = fmaxf(rad - eps, 0.f), rhi = rad + eps;
+                    for (int o = 0; o < env.n_box && !hit; ++o) {
+                        const float v = box_val(X0, X1, X2, env.box32 + o * 16);
+                        if (v < rlo * rlo) hit = true;
+                        else if (v <= rhi * rhi) push_recheck(cd, q, s_t[c], RK_ENV_BOX, a, o);
+                    }
+                    for (int o = 0; o < env.n_cyl && !hit; ++o) {
+                        const float v = cyl_val(X0, X1, X2, env.cyl32 + o * 8);
+                        if (v < rlo * rlo) hit = true;
+                        else if (v <= rhi * rhi) push_recheck(cd, q, s_t[c], RK_ENV_CYL, a, o);
+                    }
+                    for (int o = 0; o < env.n_sph && !hit; ++o) {
+                        const float4 Ob = env.sph32[o];
+                        const float dx = X0 - Ob.x, dy = X1 - Ob.y, dz = X2 - Ob.z;
+                        const int cl = classify(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), rad + Ob.w, eps);
+                        if (cl == 1) hit = true;
+                        else if (cl == 2) push_recheck(cd, q, s_t[c], RK_ENV_SPH, a, o);
+                    }
+                    if (env.n_pts > 0 && !hit) {
+                        const float reach = rad + env.pt_radius + eps;
+                        const float xs[3] = { X0, X1, X2 };
+                        int lo3[3], hi3[3];
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) {
+                            const int l = (int)floorf((xs[d] - reach - env.grid_lo[d]) * env.grid_inv);
+                            const int h = (int)floorf((xs[d] + reach - env.grid_lo[d]) * env.grid_inv);
+                            lo3[d] = l < 0 ? 0 : l;
+                            hi3[d] = h >= env.grid_dim[d] ? env.grid_dim[d] - 1 : h;
+                        }
+                        const float Rp = rad + env.pt_radius;
+                        if (lo3[0] <= hi3[0])
+                            for (int cz = lo3[2]; cz <= hi3[2] && !hit; ++cz)
+                                for (int cy = lo3[1]; cy <= hi3[1] && !hit; ++cy) {
+                                    const int row = (cz * env.grid_dim[1] + cy) * env.grid_dim[0];
+                                    const int pb = env.cell_start[row + lo3[0]];
+                                    const int pe = env.cell_start[row + hi3[0] + 1];
+                                    for (int p = pb; p < pe && !hit; ++p) {
+                                        const float4 Pt = env.pts32[p];
+                                        const float dx = X0 - Pt.x, dy = X1 - Pt.y, dz = X2 - Pt.z;
+                                        const int cl = classify(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), Rp, eps);
+                                        if (cl == 1) hit = true;
+                                        else if (cl == 2) push_recheck(cd, q, s_t[c], RK_ENV_PT, a, p);
+                                    }
+                                }
+                    }
                 }
                 if (__ballot(hit) && lane == 0) s_hit = 1;
             }
@@ -705,25 +822,34 @@ __global__ __launch_bounds__(kWG) void k_validate(TeamDev tm, EnvDev env, CallDe
                 bool hit = false;
                 if (p < tm.n_self) {
                     const int2 pr = tm.self_pairs[p];
-                    const float4 A = sph[c * S + pr.x];
-                    const float4 B = sph[c * S + pr.y];
-                    const float dx = A.x - B.x, dy = A.y - B.y, dz = A.z - B.z;
-                    const float d2 = dx * dx + dy * dy + dz * dz;
-                    const float R = A.w + B.w;
-                    const float Rh = R + eps;
-                    if (d2 <= Rh * Rh) {
-                        const float Rl = R - eps;
-                        if (d2 < Rl * Rl) hit = true;
-                        else push_recheck(s_rq, &s_rqn, RK_SELF, c, pr.x, pr.y, overflow);
-                    }
-                    ++n_self;
+                    const float4 A = rec[c * S + pr.x];
+                    const float4 B = rec[c * S + pr.y];
+                    const float4 OA = gc[c * G + tm.s_group[pr.x]];
+                    const float4 OB = gc[c * G + tm.s_group[pr.y]];
+                    const float dx = (A.x - B.x) + (OA.x - OB.x);
+                    const float dy = (A.y - B.y) + (OA.y - OB.y);
+                    const float dz = (A.z - B.z) + (OA.z - OB.z);
+                    const int cl = classify(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), A.w + B.w, eps);
+                    if (cl == 1) hit = true;
+                    else if (cl == 2) push_recheck(cd, q, s_t[c], RK_SELF, pr.x, pr.y);
                 }
+                c_self += (unsigned long long)__popcll(__ballot(p < tm.n_self));
                 if (__ballot(hit) && lane == 0) s_hit = 1;
             }
         }
 
-        // --- robot-robot tests: lane = sphere a of the lower robot, loop over the partner's spheres
+        // --- robot-robot tests.  Lane = sphere a of the lower robot; the partner's
+        // spheres come in groups of 16, centred on the group, and rotate through the
+        // 16-lane rows.  Coarse expanded-form bound first; only lanes within the
+        // bound's uncertainty revisit their partners directly.
         if (do_rr && !(KIND == 0 && !exhaustive && do_env && *(volatile int*)&s_hit)) {
+            const float rho = sqrtf(__uint_as_float(s_rho2));
+            const float Rm = 2.f * tm.r_max;
+            const float u = 5.9604645e-8f;
+            const float span = 2.f * rho + Rm + eps;
+            const float e_err = 12.f * u * (span * span + Rm * Rm);
+            const float e_hi = e_err + fmaf(2.f * Rm, eps, eps * eps);
+            const float e_lo = -(e_err + 2.f * Rm * eps);
             const int ntk = tm.n_rr_tasks;
             const int ntask = nv * ntk;
             for (int task = wave; task < ntask; task += kWavesPerWG) {
@@ -735,142 +861,64 @@ __global__ __launch_bounds__(kWG) void k_validate(TeamDev tm, EnvDev env, CallDe
                     if (best != 0xFFFFFFFFu && best < (unsigned)s_t[c] * (unsigned)tm.P) break;
                 }
                 const int2 tk = tm.rr_tasks[task - c * ntk];
-                const int slot = tk.x;
                 const int rb = tk.y;
-                const int a = slot * 64 + lane;
+                const int a = tk.x * 64 + lane;
                 const bool act = a < S && tm.s_robot[a] < rb;
-                const float4 A = act ? sph[c * S + a] : make_float4(3e18f, 3e18f, 3e18f, 0.f);
-                const float rae = A.w + eps;
-                const int b0 = tm.r_sphere_off[rb];
-                const int b1 = tm.r_sphere_off[rb + 1];
-                const float4* Bp = sph + c * S;
-                bool maybe = false;
-                for (int b = b0; b < b1; ++b) {
-                    const float4 B = Bp[b];
-                    const float dx = A.x - B.x, dy = A.y - B.y, dz = A.z - B.z;
-                    const float d2 = dx * dx + dy * dy + dz * dz;
-                    const float R = rae + B.w;
-                    maybe |= d2 < R * R;
+                float XA0 = 0.f, XA1 = 0.f, XA2 = 0.f, ra = 0.f;
+                if (act) {
+                    const float4 Xr = rec[c * S + a];
+                    const float4 O = gc[c * G + tm.s_group[a]];
+                    XA0 = Xr.x + O.x; XA1 = Xr.y + O.y; XA2 = Xr.z + O.z; ra = Xr.w;
                 }
-                if (act) n_rr += (unsigned long long)(b1 - b0);
-                bool hit = false;
-                if (__ballot(maybe)) {
-                    if (maybe) {
-                        for (int b = b0; b < b1; ++b) {
-                            const float4 B = Bp[b];
-                            const float dx = A.x - B.x, dy = A.y - B.y, dz = A.z - B.z;
-                            const float d2 = dx * dx + dy * dy + dz * dz;
-                            const float R = A.w + B.w;
-                            const float Rh = R + eps;
-                            if (d2 <= Rh * Rh) {
-                                const float Rl = R - eps;
-                                if (d2 < Rl * Rl) hit = true;
-                                else push_recheck(s_rq, &s_rqn, RK_RR, c, a, b, overflow);
-                            }
+                const float ar = -2.f * ra;
+                const float nra2 = -ra * ra;
+                const int g0 = tm.r_group_off[rb];
+                const int g1 = tm.r_group_off[rb + 1];
+                float best = 3.0e38f;
+                for (int g = g0; g < g1; ++g) {
+                    const int2 rg = tm.g_range[g];
+                    const float4 O = gc[c * G + g];
+                    const float px = XA0 - O.x, py = XA1 - O.y, pz = XA2 - O.z;
+                    const float wa = act ? fmaf(px, px, fmaf(py, py, fmaf(pz, pz, nra2))) : 1.0e30f;
+                    const int lb = rg.x + (lane & 15);
+                    float4 B = make_float4(0.f, 0.f, 0.f, 0.f);
+                    float bw = 1.0e30f;
+                    if (lb < rg.y) {
+                        B = rec[c * S + lb];
+                        bw = rw[c * S + lb];
+                    }
+                    const float m = rr_group_min(bw, B.x, B.y, B.z, B.w, -2.f * px, -2.f * py, -2.f * pz, ar);
+                    best = fminf(best, m + wa);
+                }
+                c_rr += (unsigned long long)__popcll(__ballot(act)) *
+                        (unsigned long long)(tm.r_sphere_off[rb + 1] - tm.r_sphere_off[rb]);
+                bool hit = best < e_lo;
+                const bool unsure = !hit && best < e_hi;
+                if (__ballot(unsure)) {
+                    if (unsure) {
+                        for (int b = tm.r_sphere_off[rb]; b < tm.r_sphere_off[rb + 1] && !hit; ++b) {
+                            const float4 Br = rec[c * S + b];
+                            const float4 O = gc[c * G + tm.s_group[b]];
+                            const float dx = XA0 - (Br.x + O.x), dy = XA1 - (Br.y + O.y), dz = XA2 - (Br.z + O.z);
+                            const int cl = classify(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), ra + Br.w, eps);
+                            if (cl == 1) hit = true;
+                            else if (cl == 2) push_recheck(cd, q, s_t[c], RK_RR, a, b);
                         }
                     }
-                    if (KIND == 0) {
-                        if (__ballot(hit) && lane == 0) s_hit = 1;
-                    } else {
-                        unsigned key = 0xFFFFFFFFu;
-                        if (hit) key = (unsigned)s_t[c] * (unsigned)tm.P + pair_index(tm.s_robot[a], rb, n);
-                        key = wave_min_u32(key);
-                        if (lane == 0 && key != 0xFFFFFFFFu) atomicMin(&s_key, key);
-                    }
+                }
+                if (KIND == 0) {
+                    if (__ballot(hit) && lane == 0) s_hit = 1;
+                } else if (__ballot(hit)) {
+                    unsigned key = 0xFFFFFFFFu;
+                    if (hit) key = (unsigned)s_t[c] * (unsigned)tm.P + pair_index(tm.s_robot[a], rb, n);
+                    key = wave_min_u32(key);
+                    if (lane == 0) atomicMin(&s_key, key);
                 }
             }
         }
 
-        // --- FP64 re-evaluation of near-contact tests
         __syncthreads();
-        {
-            const int nq = min(s_rqn, kRecheckCap);
-            for (int i = tid; i < nq; i += kWG) {
-                const int4 rec = s_rq[i];
-                const int kind = rec.x & 0xff;
-                const int c = rec.x >> 8;
-                const int t = s_t[c];
-                if (recheck64(tm, env, cd, q, t, kind, rec.y, rec.z)) {
-                    if (KIND == 0) s_hit = 1;
-                    else atomicMin(&s_key, (unsigned)t * (unsigned)tm.P +
-                                               pair_index(tm.s_robot[rec.y], tm.s_robot[rec.z], n));
-                }
-            }
-            n_re += (unsigned long long)(nq > tid ? (nq - tid + kWG - 1) / kWG : 0);
-        }
-        // records beyond the queue capacity: re-evaluate them by walking the tile again
-        if (__syncthreads_or(overflow ? 1 : 0)) {
-            // Rare path: every test of this tile is revisited and each near-contact
-            // one re-evaluated in FP64 by its own lane.
-            if (do_env) {
-                const int nslots = tm.n_slots;
-                for (int idx = tid; idx < nv * S; idx += kWG) {
-                    const int c = idx / S;
-                    const int a = idx - c * S;
-                    const float4 X = sph[c * S + a];
-                    const int t = s_t[c];
-                    (void)nslots;
-                    for (int o = 0; o < env.n_sph; ++o) {
-                        const float4 O = env.sph32[o];
-                        const float dx = X.x - O.x, dy = X.y - O.y, dz = X.z - O.z;
-                        const float d2 = dx * dx + dy * dy + dz * dz;
-                        const float R = X.w + O.w;
-                        if (d2 <= (R + eps) * (R + eps) && d2 >= (R - eps) * (R - eps))
-                            if (recheck64(tm, env, cd, q, t, RK_ENV_SPH, a, o)) s_hit = 1;
-                    }
-                    for (int o = 0; o < env.n_box; ++o)
-                        if (recheck64(tm, env, cd, q, t, RK_ENV_BOX, a, o)) s_hit = 1;
-                    for (int o = 0; o < env.n_cyl; ++o)
-                        if (recheck64(tm, env, cd, q, t, RK_ENV_CYL, a, o)) s_hit = 1;
-                }
-                for (int idx = tid; idx < nv * tm.n_self; idx += kWG) {
-                    const int c = idx / tm.n_self;
-                    const int2 pr = tm.self_pairs[idx - c * tm.n_self];
-                    if (recheck64(tm, env, cd, q, s_t[c], RK_SELF, pr.x, pr.y)) s_hit = 1;
-                }
-                if (env.n_pts > 0) {
-                    for (int idx = tid; idx < nv * S; idx += kWG) {
-                        const int c = idx / S;
-                        const int a = idx - c * S;
-                        const float4 X = sph[c * S + a];
-                        const float Rp = X.w + env.pt_radius;
-                        for (long long p = 0; p < env.n_pts; ++p) {
-                            const float4 Pt = env.pts32[p];
-                            const float dx = X.x - Pt.x, dy = X.y - Pt.y, dz = X.z - Pt.z;
-                            const float d2 = dx * dx + dy * dy + dz * dz;
-                            if (d2 <= (Rp + eps) * (Rp + eps))
-                                if (recheck64(tm, env, cd, q, s_t[c], RK_ENV_PT, a, (int)p)) s_hit = 1;
-                        }
-                    }
-                }
-            }
-            if (do_rr) {
-                for (int idx = tid; idx < nv * S; idx += kWG) {
-                    const int c = idx / S;
-                    const int a = idx - c * S;
-                    const int ra = tm.s_robot[a];
-                    const float4 A = sph[c * S + a];
-                    for (int b = tm.r_sphere_off[ra + 1]; b < S; ++b) {
-                        const float4 B = sph[c * S + b];
-                        const float dx = A.x - B.x, dy = A.y - B.y, dz = A.z - B.z;
-                        const float d2 = dx * dx + dy * dy + dz * dz;
-                        const float R = A.w + B.w;
-                        if (d2 <= (R + eps) * (R + eps) && d2 >= (R - eps) * (R - eps)) {
-                            const int t = s_t[c];
-                            if (recheck64(tm, env, cd, q, t, RK_RR, a, b)) {
-                                if (KIND == 0) s_hit = 1;
-                                else atomicMin(&s_key, (unsigned)t * (unsigned)tm.P +
-                                                           pair_index(ra, tm.s_robot[b], n));
-                            }
-                        }
-                    }
-                }
-            }
-        }
-        __syncthreads();
-
         if (tid == 0) {
-            s_rqn = 0;
             if (KIND == 0) {
                 if (s_hit) atomicOr(cd.word + q, 1u);
             } else {
@@ -880,15 +928,29 @@ __global__ __launch_bounds__(kWG) void k_validate(TeamDev tm, EnvDev env, CallDe
         __syncthreads();
     }
 
-    // counters
-    atomicAdd(&cd.stats[ST_RR_TESTS], n_rr);
-    if (n_env) atomicAdd(&cd.stats[ST_ENV_TESTS], n_env);
-    if (n_self) atomicAdd(&cd.stats[ST_SELF_TESTS], n_self);
-    if (n_re) atomicAdd(&cd.stats[ST_RECHECKS], n_re);
+    if (lane == 0) {
+        if (c_rr) atomicAdd(&cd.stats[ST_RR_TESTS], c_rr);
+        if (c_self) atomicAdd(&cd.stats[ST_SELF_TESTS], c_self);
+    }
+    if (c_env) atomicAdd(&cd.stats[ST_ENV_TESTS], c_env);
     if (tid == 0) {
         atomicAdd(&cd.stats[ST_TILES_RUN], n_run);
         atomicAdd(&cd.stats[ST_TILES_SKIPPED], n_skip);
         atomicAdd(&cd.stats[ST_STATES_EVAL], n_states);
+    }
+}
+
+// FP64 re-evaluation of the near-contact tests that did not fit a tile's queue.
+__global__ void k_recheck(TeamDev tm, EnvDev env, CallDev cd)
+{
+    const unsigned n = min(*reinterpret_cast<const unsigned*>(cd.ctrl + 2), (unsigned)cd.gq_cap);
+    if (blockIdx.x == 0 && threadIdx.x == 0) cd.stats[ST_RECHECKS] = n;
+    for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int4 r0 = cd.gq[i];
+        const int q = r0.x, t = r0.y & 0xffffff, kind = r0.y >> 24, a = r0.z, b = r0.w;
+        if (!recheck64(tm, env, cd, q, t, kind, a, b)) continue;
+        if (cd.kind == 0) atomicOr(cd.word + q, 1u);
+        else atomicMin(cd.word + q, (unsigned)t * (unsigned)tm.P + pair_index(tm.s_robot[a], tm.s_robot[b], tm.n_robots));
     }
 }
 
@@ -925,6 +987,9 @@ hipError_t launch_validate(const TeamDev& tm, const EnvDev& env, const CallDev& 
         hipLaunchKernelGGL(k_validate<0>, dim3(grid), dim3(kWG), lds_bytes, stream, tm, env, cd);
     else
         hipLaunchKernelGGL(k_validate<1>, dim3(grid), dim3(kWG), lds_bytes, stream, tm, env, cd);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_recheck, dim3(256), dim3(256), 0, stream, tm, env, cd);
     return hipGetLastError();
 }
 

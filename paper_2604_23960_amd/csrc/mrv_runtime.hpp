@@ -59,11 +59,14 @@ struct Scratch {
     DevBuf hist, start, off;
     size_t bins = 0;
     DevBuf q_T, q_nt, q_g, q_status, q_word, q_sorted;
+    DevBuf gq;              // near-contact queue (int4 records)
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     int last_kind = -1;
+    static constexpr int kGlobalRecheckCap = 1 << 21;
     void release()
     {
-        for (DevBuf* b : {&ctrl, &hist, &start, &off, &q_T, &q_nt, &q_g, &q_status, &q_word, &q_sorted}) b->release();
+        for (DevBuf* b : {&ctrl, &hist, &start, &off, &q_T, &q_nt, &q_g, &q_status, &q_word, &q_sorted, &gq})
+            b->release();
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
         ev0 = ev1 = nullptr;
@@ -72,7 +75,7 @@ struct Scratch {
     size_t bytes() const
     {
         return ctrl.cap + hist.cap + start.cap + off.cap + q_T.cap + q_nt.cap + q_g.cap + q_status.cap +
-               q_word.cap + q_sorted.cap;
+               q_word.cap + q_sorted.cap + gq.cap;
     }
 };
 

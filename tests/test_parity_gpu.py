@@ -36,6 +36,17 @@ def ctx():
     c.close()
 
 
+def fit_chunk(ctx, team, kind, want):
+    """Largest chunk <= want that the team's LDS footprint allows."""
+    for c in range(want, 0, -1):
+        try:
+            ctx.set_tiling(team, kind, c)
+            return c
+        except mrv.MrvError:
+            continue
+    raise AssertionError("no chunk fits")
+
+
 def oracle_set(w):
     return oracle.Team(w.team), oracle.Env(w.env), oracle.Paths(w.paths)
 
@@ -101,7 +112,10 @@ def test_spread_arms_ffc_late_conflicts(ctx):
     assert (ref[:, 0] > 20).sum() > 5 and (ref[:, 0] < 0).sum() > 100
     team = ctx.load_team(w.team)
     for chunk in (0, 1, 3, 10):
-        ctx.set_tiling(team, 1, chunk)
+        if chunk:
+            fit_chunk(ctx, team, 1, chunk)
+        else:
+            ctx.set_tiling(team, 1, 0)
         got = ctx.ffc(team, w.paths)
         assert np.array_equal(got, ref), (chunk, np.nonzero(np.any(got != ref, axis=1))[0][:10])
     # MV without environment is the same question
@@ -116,7 +130,10 @@ def test_hetero_ffc(ctx):
     ref = oracle.ffc(ot, op)
     team = ctx.load_team(w.team)
     for chunk in (0, 5):
-        ctx.set_tiling(team, 1, chunk)
+        if chunk:
+            fit_chunk(ctx, team, 1, chunk)
+        else:
+            ctx.set_tiling(team, 1, 0)
         got = ctx.ffc(team, w.paths)
         assert np.array_equal(got, ref), np.nonzero(np.any(got != ref, axis=1))[0][:10]
 
@@ -126,7 +143,7 @@ def test_arms_mv_chunk_independent(ctx, arms, chunk):
     w, (ot, oe, op) = arms
     say("arms MV chunk", chunk)
     team, env = ctx.load_team(w.team), ctx.load_env(w.env)
-    ctx.set_tiling(team, 0, chunk)
+    fit_chunk(ctx, team, 0, chunk)
     ref = oracle.mv(ot, oe, op, check_env=False)
     got = ctx.mv(team, env, w.paths, 0)
     assert np.array_equal(got, ref)
