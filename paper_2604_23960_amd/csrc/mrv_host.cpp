@@ -557,7 +557,7 @@ void run_call(mrv_ctx ctx, Scratch& sc, TeamHost& tm, const EnvHost* env, int ki
     HIPCHK(hipEventRecord(sc.ev0, stream));
     HIPCHK(launch_validate(tm.dev, ed, cd, grid, lds, stream));
     HIPCHK(hipEventRecord(sc.ev1, stream));
-    HIPCHK(launch_finalize(tm.dev, cd, stream));
+    HIPCHK(launch_finalize(tm.dev, ed, cd, stream));
     sc.last_kind = kind;
 }
 

@@ -14,6 +14,7 @@ constexpr int kMaxRobots = 32;
 constexpr int kMaxJoints = 8;
 constexpr int kMaxChunk = 64;       // timesteps per tile
 constexpr int kLdsBudget = 64 * 1024;
+constexpr int kEnvC = 8;           // timesteps a lane carries through the obstacle loops
 
 enum RecheckKind : int { RK_RR = 0, RK_SELF = 1, RK_ENV_SPH = 2, RK_ENV_BOX = 3, RK_ENV_CYL = 4, RK_ENV_PT = 5 };
 
@@ -120,7 +121,7 @@ struct CallDev {
 hipError_t launch_prepare(const TeamDev& tm, const CallDev& cd, hipStream_t stream);
 hipError_t launch_validate(const TeamDev& tm, const EnvDev& env, const CallDev& cd, int grid,
                            size_t lds_bytes, hipStream_t stream);
-hipError_t launch_finalize(const TeamDev& tm, const CallDev& cd, hipStream_t stream);
+hipError_t launch_finalize(const TeamDev& tm, const EnvDev& env, const CallDev& cd, hipStream_t stream);
 hipError_t fill_u32(void* p, unsigned v, size_t n, hipStream_t stream);
 // Occupancy-derived workgroups per CU for the validation kernel.
 int validate_blocks_per_cu(int kind, size_t lds_bytes);

@@ -701,40 +701,76 @@ __global__ __launch_bounds__(kWG) void k_validate(TeamDev tm, EnvDev env, CallDe
         }
         __syncthreads();
 
-        // --- robot-obstacle and self tests (MV with environment checking)
+        // --- robot-obstacle and self tests (MV with environment checking).  A lane keeps
+        // one sphere (or one self pair) for up to kEnvC timesteps of the tile, so each
+        // obstacle's parameters are read once per kEnvC tests.
         if (do_env) {
             const int nslots = tm.n_slots;
-            const int ntask = nv * nslots;
+            const int ncb = (nv + kEnvC - 1) / kEnvC;
+            const int ntask = nslots * ncb;
             float ro_max = 0.f;
             for (int o = 0; o < env.n_sph; ++o) ro_max = fmaxf(ro_max, env.sph32[o].w);
             for (int task = wave; task < ntask; task += kWavesPerWG) {
                 if (!exhaustive && *(volatile int*)&s_hit) break;
-                const int c = task / nslots;
-                const int a = (task - c * nslots) * 64 + lane;
-                bool hit = false, unsure = false;
-                float X0 = 0.f, X1 = 0.f, X2 = 0.f, rad = 0.f;
-                if (a < S) {
-                    const float4 Xr = rec[c * S + a];
-                    const float4 O = gc[c * G + tm.s_group[a]];
-                    X0 = Xr.x + O.x; X1 = Xr.y + O.y; X2 = Xr.z + O.z; rad = Xr.w;
-                    float mb = 3.0e38f;
-                    for (int o = 0; o < env.n_box; ++o) mb = fminf(mb, box_val(X0, X1, X2, env.box32 + o * 16));
-                    for (int o = 0; o < env.n_cyl; ++o) mb = fminf(mb, cyl_val(X0, X1, X2, env.cyl32 + o * 8));
-                    float ms = 3.0e38f;
-                    for (int o = 0; o < env.n_sph; ++o) {
-                        const float4 Ob = env.sph32[o];
-                        const float dx = X0 - Ob.x, dy = X1 - Ob.y, dz = X2 - Ob.z;
-                        const float Rs = rad + Ob.w;
-                        ms = fminf(ms, fmaf(-Rs, Rs, fmaf(dx, dx, fmaf(dy, dy, dz * dz))));
+                const int cb = task / nslots;
+                const int a = (task - cb * nslots) * 64 + lane;
+                const int c0 = cb * kEnvC;
+                const int nc = min(kEnvC, nv - c0);
+                const bool act = a < S;
+                float X0[kEnvC], X1[kEnvC], X2[kEnvC], mb[kEnvC], ms[kEnvC];
+                float rad = 0.f;
+                if (act) rad = rec[c0 * S + a].w;
+#pragma unroll
+                for (int cc = 0; cc < kEnvC; ++cc) {
+                    X0[cc] = 1.0e18f; X1[cc] = 1.0e18f; X2[cc] = 1.0e18f;
+                    mb[cc] = 3.0e38f; ms[cc] = 3.0e38f;
+                    if (act && cc < nc) {
+                        const int c = c0 + cc;
+                        const float4 Xr = rec[c * S + a];
+                        const float4 O = gc[c * G + tm.s_group[a]];
+                        X0[cc] = Xr.x + O.x; X1[cc] = Xr.y + O.y; X2[cc] = Xr.z + O.z;
                     }
-                    const float rlo = fmaxf(rad - eps, 0.f), rhi = rad + eps;
-                    const float Rb = rad + ro_max;
-                    hit = (mb < rlo * rlo) || (ms < -2.f * Rb * eps);
-                    unsure = !hit && ((mb <= rhi * rhi) || (ms <= fmaf(2.f * Rb, eps, eps * eps)));
-                    if (env.n_pts > 0 && !hit) {
-                        const float reach = rad + env.pt_radius + eps;
-                        const float xs[3] = { X0, X1, X2 };
+                }
+                for (int o = 0; o < env.n_box; ++o) {
+                    const float* B = env.box32 + o * 16;
+#pragma unroll
+                    for (int cc = 0; cc < kEnvC; ++cc) mb[cc] = fminf(mb[cc], box_val(X0[cc], X1[cc], X2[cc], B));
+                }
+                for (int o = 0; o < env.n_cyl; ++o) {
+                    const float* Y = env.cyl32 + o * 8;
+#pragma unroll
+                    for (int cc = 0; cc < kEnvC; ++cc) mb[cc] = fminf(mb[cc], cyl_val(X0[cc], X1[cc], X2[cc], Y));
+                }
+                for (int o = 0; o < env.n_sph; ++o) {
+                    const float4 Ob = env.sph32[o];
+                    const float Rs = rad + Ob.w;
+#pragma unroll
+                    for (int cc = 0; cc < kEnvC; ++cc) {
+                        const float dx = X0[cc] - Ob.x, dy = X1[cc] - Ob.y, dz = X2[cc] - Ob.z;
+                        ms[cc] = fminf(ms[cc], fmaf(-Rs, Rs, fmaf(dx, dx, fmaf(dy, dy, dz * dz))));
+                    }
+                }
+                if (act) c_env += (unsigned long long)nc * (unsigned long long)(env.n_sph + env.n_box + env.n_cyl);
+                const float rlo = fmaxf(rad - eps, 0.f), rhi = rad + eps;
+                const float Rb = rad + ro_max;
+                bool hit = false;
+                unsigned unsure = 0u;
+#pragma unroll
+                for (int cc = 0; cc < kEnvC; ++cc) {
+                    if (!act || cc >= nc) continue;
+                    const bool h = (mb[cc] < rlo * rlo) || (ms[cc] < -2.f * Rb * eps);
+                    hit = hit || h;
+                    if (!h && ((mb[cc] <= rhi * rhi) || (ms[cc] <= fmaf(2.f * Rb, eps, eps * eps)))) unsure |= 1u << cc;
+                }
+                if (env.n_pts > 0 && act) {
+                    const float Rp = rad + env.pt_radius;
+                    for (int cc = 0; cc < nc; ++cc) {
+                        const int c = c0 + cc;
+                        const float4 Xr = rec[c * S + a];
+                        const float4 O = gc[c * G + tm.s_group[a]];
+                        const float xs[3] = { Xr.x + O.x, Xr.y + O.y, Xr.z + O.z };
                         int lo3[3], hi3[3];
+                        const float reach = Rp + eps;
 #pragma unroll
                         for (int d = 0; d < 3; ++d) {
                             const int l = (int)floorf((xs[d] - reach - env.grid_lo[d]) * env.grid_inv);
@@ -742,8 +778,8 @@ __global__ __launch_bounds__(kWG) void k_validate(TeamDev tm, EnvDev env, CallDe
                             lo3[d] = l < 0 ? 0 : l;
                             hi3[d] = h >= env.grid_dim[d] ? env.grid_dim[d] - 1 : h;
                         }
-                        const float Rp = rad + env.pt_radius;
-                        float mp = 3.0e38f;
+                        const float plo = fmaxf(Rp - eps, 0.f), phi = Rp + eps;
+                        const float plo2 = plo * plo, phi2 = phi * phi;
                         if (lo3[0] <= hi3[0])
                             for (int cz = lo3[2]; cz <= hi3[2]; ++cz)
                                 for (int cy = lo3[1]; cy <= hi3[1]; ++cy) {
@@ -752,88 +788,68 @@ __global__ __launch_bounds__(kWG) void k_validate(TeamDev tm, EnvDev env, CallDe
                                     const int pe = env.cell_start[row + hi3[0] + 1];
                                     for (int p = pb; p < pe; ++p) {
                                         const float4 Pt = env.pts32[p];
-                                        const float dx = X0 - Pt.x, dy = X1 - Pt.y, dz = X2 - Pt.z;
-                                        mp = fminf(mp, fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+                                        const float dx = xs[0] - Pt.x, dy = xs[1] - Pt.y, dz = xs[2] - Pt.z;
+                                        const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                                        if (d2 <= phi2) {
+                                            if (d2 < plo2) hit = true;
+                                            else push_recheck(cd, q, s_t[c], RK_ENV_PT, a, p);
+                                        }
                                     }
                                 }
-                        const int cl = classify(mp, Rp, eps);
-                        hit = cl == 1;
-                        unsure = unsure || cl == 2;
                     }
-                    c_env += (unsigned long long)(env.n_sph + env.n_box + env.n_cyl);
                 }
-                if (unsure && !hit) {
-                    // rare: find the near obstacles and settle each in FP64
-                    const float rlo = fmaxf(rad - eps, 0.f), rhi = rad + eps;
-                    for (int o = 0; o < env.n_box && !hit; ++o) {
-                        const float v = box_val(X0, X1, X2, env.box32 + o * 16);
-                        if (v < rlo * rlo) hit = true;
-                        else if (v <= rhi * rhi) push_recheck(cd, q, s_t[c], RK_ENV_BOX, a, o);
-                    }
-                    for (int o = 0; o < env.n_cyl && !hit; ++o) {
-                        const float v = cyl_val(X0, X1, X2, env.cyl32 + o * 8);
-                        if (v < rlo * rlo) hit = true;
-                        else if (v <= rhi * rhi) push_recheck(cd, q, s_t[c], RK_ENV_CYL, a, o);
-                    }
-                    for (int o = 0; o < env.n_sph && !hit; ++o) {
-                        const float4 Ob = env.sph32[o];
-                        const float dx = X0 - Ob.x, dy = X1 - Ob.y, dz = X2 - Ob.z;
-                        const int cl = classify(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), rad + Ob.w, eps);
-                        if (cl == 1) hit = true;
-                        else if (cl == 2) push_recheck(cd, q, s_t[c], RK_ENV_SPH, a, o);
-                    }
-                    if (env.n_pts > 0 && !hit) {
-                        const float reach = rad + env.pt_radius + eps;
-                        const float xs[3] = { X0, X1, X2 };
-                        int lo3[3], hi3[3];
-#pragma unroll
-                        for (int d = 0; d < 3; ++d) {
-                            const int l = (int)floorf((xs[d] - reach - env.grid_lo[d]) * env.grid_inv);
-                            const int h = (int)floorf((xs[d] + reach - env.grid_lo[d]) * env.grid_inv);
-                            lo3[d] = l < 0 ? 0 : l;
-                            hi3[d] = h >= env.grid_dim[d] ? env.grid_dim[d] - 1 : h;
+                if (unsure && !(hit && !exhaustive)) {
+                    // rare: find the near obstacles and queue each for FP64 re-evaluation
+                    for (int cc = 0; cc < nc; ++cc) {
+                        if (!(unsure & (1u << cc))) continue;
+                        const int c = c0 + cc;
+                        const float4 Xr = rec[c * S + a];
+                        const float4 O = gc[c * G + tm.s_group[a]];
+                        const float x = Xr.x + O.x, y = Xr.y + O.y, z = Xr.z + O.z;
+                        for (int o = 0; o < env.n_box; ++o) {
+                            const float v = box_val(x, y, z, env.box32 + o * 16);
+                            if (v < rlo * rlo) hit = true;
+                            else if (v <= rhi * rhi) push_recheck(cd, q, s_t[c], RK_ENV_BOX, a, o);
                         }
-                        const float Rp = rad + env.pt_radius;
-                        if (lo3[0] <= hi3[0])
-                            for (int cz = lo3[2]; cz <= hi3[2] && !hit; ++cz)
-                                for (int cy = lo3[1]; cy <= hi3[1] && !hit; ++cy) {
-                                    const int row = (cz * env.grid_dim[1] + cy) * env.grid_dim[0];
-                                    const int pb = env.cell_start[row + lo3[0]];
-                                    const int pe = env.cell_start[row + hi3[0] + 1];
-                                    for (int p = pb; p < pe && !hit; ++p) {
-                                        const float4 Pt = env.pts32[p];
-                                        const float dx = X0 - Pt.x, dy = X1 - Pt.y, dz = X2 - Pt.z;
-                                        const int cl = classify(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), Rp, eps);
-                                        if (cl == 1) hit = true;
-                                        else if (cl == 2) push_recheck(cd, q, s_t[c], RK_ENV_PT, a, p);
-                                    }
-                                }
+                        for (int o = 0; o < env.n_cyl; ++o) {
+                            const float v = cyl_val(x, y, z, env.cyl32 + o * 8);
+                            if (v < rlo * rlo) hit = true;
+                            else if (v <= rhi * rhi) push_recheck(cd, q, s_t[c], RK_ENV_CYL, a, o);
+                        }
+                        for (int o = 0; o < env.n_sph; ++o) {
+                            const float4 Ob = env.sph32[o];
+                            const float dx = x - Ob.x, dy = y - Ob.y, dz = z - Ob.z;
+                            const int cl = classify(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), rad + Ob.w, eps);
+                            if (cl == 1) hit = true;
+                            else if (cl == 2) push_recheck(cd, q, s_t[c], RK_ENV_SPH, a, o);
+                        }
                     }
                 }
                 if (__ballot(hit) && lane == 0) s_hit = 1;
             }
-            // self-collision pairs
+            // self-collision pairs: a lane keeps one pair for the tile's timesteps
             const int nsc = (tm.n_self + 63) >> 6;
-            const int ntask2 = nv * nsc;
-            for (int task = wave; task < ntask2; task += kWavesPerWG) {
+            for (int task = wave; task < nsc; task += kWavesPerWG) {
                 if (!exhaustive && *(volatile int*)&s_hit) break;
-                const int c = task / nsc;
-                const int p = (task - c * nsc) * 64 + lane;
+                const int p = task * 64 + lane;
                 bool hit = false;
                 if (p < tm.n_self) {
                     const int2 pr = tm.self_pairs[p];
-                    const float4 A = rec[c * S + pr.x];
-                    const float4 B = rec[c * S + pr.y];
-                    const float4 OA = gc[c * G + tm.s_group[pr.x]];
-                    const float4 OB = gc[c * G + tm.s_group[pr.y]];
-                    const float dx = (A.x - B.x) + (OA.x - OB.x);
-                    const float dy = (A.y - B.y) + (OA.y - OB.y);
-                    const float dz = (A.z - B.z) + (OA.z - OB.z);
-                    const int cl = classify(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), A.w + B.w, eps);
-                    if (cl == 1) hit = true;
-                    else if (cl == 2) push_recheck(cd, q, s_t[c], RK_SELF, pr.x, pr.y);
+                    const int ga = tm.s_group[pr.x], gb = tm.s_group[pr.y];
+                    for (int c = 0; c < nv; ++c) {
+                        const float4 A = rec[c * S + pr.x];
+                        const float4 B = rec[c * S + pr.y];
+                        const float4 OA = gc[c * G + ga];
+                        const float4 OB = gc[c * G + gb];
+                        const float dx = (A.x - B.x) + (OA.x - OB.x);
+                        const float dy = (A.y - B.y) + (OA.y - OB.y);
+                        const float dz = (A.z - B.z) + (OA.z - OB.z);
+                        const int cl = classify(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), A.w + B.w, eps);
+                        if (cl == 1) hit = true;
+                        else if (cl == 2) push_recheck(cd, q, s_t[c], RK_SELF, pr.x, pr.y);
+                    }
                 }
-                c_self += (unsigned long long)__popcll(__ballot(p < tm.n_self));
+                c_self += (unsigned long long)__popcll(__ballot(p < tm.n_self)) * (unsigned long long)nv;
                 if (__ballot(hit) && lane == 0) s_hit = 1;
             }
         }
@@ -987,15 +1003,13 @@ hipError_t launch_validate(const TeamDev& tm, const EnvDev& env, const CallDev& 
         hipLaunchKernelGGL(k_validate<0>, dim3(grid), dim3(kWG), lds_bytes, stream, tm, env, cd);
     else
         hipLaunchKernelGGL(k_validate<1>, dim3(grid), dim3(kWG), lds_bytes, stream, tm, env, cd);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_recheck, dim3(256), dim3(256), 0, stream, tm, env, cd);
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const TeamDev& tm, const CallDev& cd, hipStream_t stream)
+hipError_t launch_finalize(const TeamDev& tm, const EnvDev& env, const CallDev& cd, hipStream_t stream)
 {
     if (cd.n_queries == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_recheck, dim3(256), dim3(256), 0, stream, tm, env, cd);
     const unsigned blocks = (unsigned)((cd.n_queries + 255) / 256);
     hipLaunchKernelGGL(k_finalize, dim3(blocks), dim3(256), 0, stream, tm, cd);
     return hipGetLastError();
