@@ -34,6 +34,26 @@ FLOP_SPHERE_PLACE = 18
 PEAK_FP32_VALU = 157.3e12   # MI355X FP32 vector peak (published)
 
 
+PROFILE = os.path.join(ROOT, "profiles", "k_validate_mv_arms65536_exhaustive.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_2604_23960_amd", "csrc", "mrv_kernels.hip")
+
+
+def profiled_traffic():
+    """HBM bytes per launch from the committed rocprofv3 summary, only while the kernel
+    source is the one that was profiled (else None)."""
+    import hashlib
+    try:
+        text = open(PROFILE).read()
+    except OSError:
+        return None
+    want = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    vals = dict(line.split(": ", 1) for line in text.splitlines()
+                if line.startswith(("traffic_bytes_per_launch: ", "kernel_source_sha256: ")))
+    if vals.get("kernel_source_sha256", "").strip() != want:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def per_timestep_flop(team, env, check_env=True):
     """Algorithmic FLOP to validate one timestep of the whole team."""
     from paper_2604_23960_amd import workloads as W
@@ -140,7 +160,7 @@ def main():
     flop = ts * per_timestep_flop(w.team, w.env, True)
     achieved = flop / (kernel_ms * 1e-3)
     roofline = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_FP32_VALU / 1e12, unit="TFLOP/s",
-                    frac=achieved / PEAK_FP32_VALU, traffic=None, kernel="k_validate<MV>",
+                    frac=achieved / PEAK_FP32_VALU, traffic=profiled_traffic(), kernel="k_validate<MV>",
                     kernel_ms=kernel_ms, flop_per_launch=flop)
     extra = dict(states_covered=st["states_covered"], rr_tests=st["rr_tests"], env_tests=st["env_tests"],
                  self_tests=st["self_tests"], near_rechecks=st["near_rechecks"],
