@@ -93,6 +93,36 @@ def run_device(ctx, team, env, dp, kind, flags, out, steps, warmup):
     return wall, kernel_ms, stats
 
 
+def serving_bench(log, n_requests=3000, n_plain=400):
+    """Served (mrv_submit/mrv_wait, continuous batching) vs plain (one synchronous
+    call per query) on 64 simulated clients with resident teams of 2-8 robots."""
+    from paper_2604_23960_amd import loadgen, mrv
+    from paper_2604_23960_amd import workloads as W
+    teams, env, reqs = W.serving_workload(n_requests)
+    ctx = mrv.Context(0)
+    handles = [ctx.load_team(t) for t in teams]
+    e = ctx.load_env(env)
+    hps = loadgen.prepare(reqs)
+    # warm both forms
+    loadgen.run_plain(ctx, handles, e, reqs[:20], hps[:20], float("inf"))
+    loadgen.run_served(ctx, handles, e, reqs[:200], hps[:200], float("inf"))
+    log("serving: saturation throughput")
+    plain_sat, _ = loadgen.run_plain(ctx, handles, e, reqs[:n_plain], hps[:n_plain], float("inf"))
+    served_sat, _ = loadgen.run_served(ctx, handles, e, reqs, hps, float("inf"))
+    rate = 0.8 * plain_sat["qps"]
+    log(f"serving: Poisson load at {rate:.0f} req/s (0.8 x plain saturation) and at 5x that")
+    plain_at, _ = loadgen.run_plain(ctx, handles, e, reqs[:n_plain], hps[:n_plain], rate, seed=1)
+    served_at, _ = loadgen.run_served(ctx, handles, e, reqs[:n_plain], hps[:n_plain], rate, seed=1)
+    n5 = min(len(reqs), 5 * n_plain)
+    served_5x, _ = loadgen.run_served(ctx, handles, e, reqs[:n5], hps[:n5], 5 * rate, seed=2)
+    ctx.close()
+    return dict(clients=len(teams), requests=len(reqs), mv_fraction=float(np.mean([r.kind == 0 for r in reqs])),
+                plain_saturated=plain_sat, served_saturated=served_sat,
+                offered_rate=rate, plain_at_rate=plain_at, served_at_rate=served_at,
+                served_at_5x_rate=served_5x,
+                served_over_plain_throughput=served_sat["qps"] / plain_sat["qps"])
+
+
 def cpu_baseline(w, max_queries):
     import oracle
     n = w.paths.n_queries
@@ -185,6 +215,8 @@ def main():
         wall4, kms4, st4 = run_device(ctx, tf, -1, dpf, 1, mrv.EXHAUSTIVE, cf, 3, 1)
         extra["ffc_hetero_exhaustive"] = dict(ms_per_call=wall4 / 3 * 1e3,
                                               states_per_s=st4["states_evaluated"] * 3 / wall4)
+        log("serving loop vs plain launches")
+        extra["serving"] = serving_bench(log)
     cpu = None
     if not args.no_cpu:
         log("timing the FP64 oracle on the host")

@@ -46,6 +46,7 @@ struct Packer {
 
 struct TeamHost {
     TeamDev dev{};
+    TeamDev* d_dev = nullptr;   // device copy of dev (inside dmem)
     void* dmem = nullptr;
     std::vector<int> dof;
     int max_dof = 0;
@@ -55,6 +56,7 @@ struct TeamHost {
 
 struct EnvHost {
     EnvDev dev{};
+    EnvDev* d_dev = nullptr;    // device copy of dev (inside dmem)
     void* dmem = nullptr;
     int inflight = 0;
 };
@@ -63,6 +65,9 @@ struct EnvHost {
 
 
 namespace {
+
+size_t lds_per_t(const TeamHost& tm);
+int default_chunk(const TeamHost& tm, int kind);
 
 bool finite_all(const double* p, size_t n)
 {
@@ -217,12 +222,10 @@ int build_team(mrv_ctx ctx, const mrv_robot_desc* robots, int n, TeamHost& out)
                  o_ss = pk.add(s_slot), o_sl = pk.add(s_lframe), o_l32 = pk.add(s_local32),
                  o_l64 = pk.add(s_local64), o_sp = pk.add(self_pairs), o_rt = pk.add(rr_tasks),
                  o_sg = pk.add(s_group), o_gr = pk.add(g_range), o_rg = pk.add(r_group_off);
+    const TeamDev blank{};
+    const size_t o_self = pk.add(&blank, sizeof(TeamDev));
     void* d = nullptr;
     if (hipMalloc(&d, pk.bytes.size()) != hipSuccess) throw Err{MRV_E_NOMEM, "team upload allocation failed"};
-    if (hipMemcpy(d, pk.bytes.data(), pk.bytes.size(), hipMemcpyHostToDevice) != hipSuccess) {
-        (void)hipFree(d);
-        throw Err{MRV_E_DEVICE, "team upload failed"};
-    }
     auto at = [&](size_t o) { return (unsigned char*)d + o; };
     TeamDev& t = out.dev;
     t.n_robots = n;
@@ -256,8 +259,17 @@ int build_team(mrv_ctx ctx, const mrv_robot_desc* robots, int n, TeamHost& out)
     t.self_pairs = (const int2*)at(o_sp);
     t.rr_tasks = (const int2*)at(o_rt);
     out.dmem = d;
+    out.d_dev = (TeamDev*)at(o_self);
     out.dof = r_nj;
     out.max_dof = max_dof;
+    t.lds_per_t = (int)lds_per_t(out);
+    t.chunk[0] = default_chunk(out, 0);
+    t.chunk[1] = default_chunk(out, 1);
+    std::memcpy(pk.bytes.data() + o_self, &t, sizeof(TeamDev));
+    if (hipMemcpy(d, pk.bytes.data(), pk.bytes.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(d);
+        throw Err{MRV_E_DEVICE, "team upload failed"};
+    }
     (void)ctx;
     return 0;
 }
@@ -371,12 +383,10 @@ void build_env(const mrv_env_desc* e, EnvHost& out)
     size_t o_s32 = pk.add(sph32), o_s64 = pk.add(sph64), o_b32 = pk.add(box32), o_b64 = pk.add(box64),
            o_c32 = pk.add(cyl32), o_c64 = pk.add(cyl64), o_p32 = pk.add(pts32), o_p64 = pk.add(pts64),
            o_cs = pk.add(cell_start);
+    const EnvDev blank{};
+    const size_t o_self = pk.add(&blank, sizeof(EnvDev));
     void* d = nullptr;
     if (hipMalloc(&d, pk.bytes.size()) != hipSuccess) throw Err{MRV_E_NOMEM, "environment upload allocation failed"};
-    if (hipMemcpy(d, pk.bytes.data(), pk.bytes.size(), hipMemcpyHostToDevice) != hipSuccess) {
-        (void)hipFree(d);
-        throw Err{MRV_E_DEVICE, "environment upload failed"};
-    }
     auto at = [&](size_t o) { return (unsigned char*)d + o; };
     EnvDev& v = out.dev;
     v.n_sph = e->n_spheres;
@@ -401,6 +411,12 @@ void build_env(const mrv_env_desc* e, EnvHost& out)
     v.pt_radius = (float)e->point_radius;
     v.pt_radius64 = e->point_radius;
     out.dmem = d;
+    out.d_dev = (EnvDev*)at(o_self);
+    std::memcpy(pk.bytes.data() + o_self, &v, sizeof(EnvDev));
+    if (hipMemcpy(d, pk.bytes.data(), pk.bytes.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(d);
+        throw Err{MRV_E_DEVICE, "environment upload failed"};
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -492,6 +508,7 @@ void ensure_scratch(Scratch& sc, size_t bins, size_t queries)
     sc.q_T.ensure(Q * 4);
     sc.q_nt.ensure(Q * 4);
     sc.q_g.ensure(Q * 4);
+    sc.q_chunk.ensure(Q * 4);
     sc.q_status.ensure(Q * 4);
     sc.q_word.ensure(Q * 4);
     sc.q_sorted.ensure(Q * 4);
@@ -500,39 +517,34 @@ void ensure_scratch(Scratch& sc, size_t bins, size_t queries)
 
 namespace {
 
-struct DevPaths {
-    const long long* wp_begin;
-    const int* wp_t;
-    const double* wp_q;
-    long long n_wp;
-    int n_queries;
-    int dof_stride;
-};
 
-// Queue the whole pipeline for one call on the context stream.
-// `max_T` bounds every query's horizon (MRV_MAX_T when unknown).
-void run_call(mrv_ctx ctx, Scratch& sc, TeamHost& tm, const EnvHost* env, int kind, uint32_t flags,
-              const DevPaths& dp, long long max_T, void* out_dev, hipStream_t stream)
+// Queue the whole pipeline for one call on `stream`.
+void run_plan(mrv_ctx ctx, Scratch& sc, const CallPlan& pl, void* out_dev, hipStream_t stream)
 {
-    int chunk = tm.tiling[kind].chunk > 0 ? tm.tiling[kind].chunk : default_chunk(tm, kind);
-    ensure_scratch(sc, (size_t)((max_T + chunk - 1) / chunk) + 2, (size_t)dp.n_queries);
-    const size_t lds = lds_bytes_for(tm, chunk);
+    const int kind = pl.kind;
+    const int min_chunk = std::max(1, pl.min_chunk);
+    ensure_scratch(sc, (size_t)((pl.max_T + min_chunk - 1) / min_chunk) + 2, (size_t)pl.dp.n_queries);
     CallDev cd{};
-    cd.n_queries = dp.n_queries;
-    cd.n_robots = tm.dev.n_robots;
-    cd.dof_stride = dp.dof_stride;
+    cd.n_queries = pl.dp.n_queries;
+    cd.dof_stride = pl.dp.dof_stride;
     cd.kind = kind;
-    cd.flags = flags;
-    cd.chunk = chunk;
+    cd.flags = pl.flags;
+    cd.lds_bytes = (int)pl.lds;
+    cd.team0 = pl.team0;
+    cd.q_team = pl.q_team;
+    cd.env0 = pl.env0;
+    cd.q_env = pl.q_env;
+    cd.q_pathoff = pl.q_pathoff;
     cd.eps32 = (float)ctx->eps;
     cd.eps64 = ctx->eps;
-    cd.n_wp = dp.n_wp;
-    cd.wp_begin = dp.wp_begin;
-    cd.wp_t = dp.wp_t;
-    cd.wp_q = dp.wp_q;
+    cd.n_wp = pl.dp.n_wp;
+    cd.wp_begin = pl.dp.wp_begin;
+    cd.wp_t = pl.dp.wp_t;
+    cd.wp_q = pl.dp.wp_q;
     cd.T = (int*)sc.q_T.p;
     cd.nt = (int*)sc.q_nt.p;
     cd.gstep = (int*)sc.q_g.p;
+    cd.q_chunk = (int*)sc.q_chunk.p;
     cd.status = (int*)sc.q_status.p;
     cd.word = (unsigned*)sc.q_word.p;
     cd.sorted_q = (int*)sc.q_sorted.p;
@@ -546,19 +558,33 @@ void run_call(mrv_ctx ctx, Scratch& sc, TeamHost& tm, const EnvHost* env, int ki
     cd.valid_out = kind == 0 ? (unsigned char*)out_dev : nullptr;
     cd.conflict_out = kind == 1 ? (int*)out_dev : nullptr;
 
-    EnvDev ed{};
-    if (env) ed = env->dev;
-
-    const int per_cu = std::max(1, validate_blocks_per_cu(kind, lds));
-    const int want = tm.tiling[kind].wg_per_cu > 0 ? std::min(tm.tiling[kind].wg_per_cu, per_cu) : per_cu;
+    const int per_cu = std::max(1, validate_blocks_per_cu(kind, pl.lds));
+    const int want = pl.wg_per_cu > 0 ? std::min(pl.wg_per_cu, per_cu) : per_cu;
     const int grid = std::max(1, ctx->n_cu * want);
 
-    HIPCHK(launch_prepare(tm.dev, cd, stream));
+    HIPCHK(launch_prepare(cd, stream));
     HIPCHK(hipEventRecord(sc.ev0, stream));
-    HIPCHK(launch_validate(tm.dev, ed, cd, grid, lds, stream));
+    HIPCHK(launch_validate(cd, grid, stream));
     HIPCHK(hipEventRecord(sc.ev1, stream));
-    HIPCHK(launch_finalize(tm.dev, ed, cd, stream));
+    HIPCHK(launch_finalize(cd, stream));
     sc.last_kind = kind;
+}
+
+// Plan for a call whose queries all use one team and environment.
+CallPlan single_plan(const TeamHost& tm, const EnvHost* env, int kind, uint32_t flags, const DevPaths& dp,
+                     long long max_T)
+{
+    CallPlan pl{};
+    pl.kind = kind;
+    pl.flags = flags;
+    pl.dp = dp;
+    pl.team0 = tm.d_dev;
+    pl.env0 = env ? env->d_dev : nullptr;
+    pl.max_T = max_T;
+    pl.min_chunk = tm.dev.chunk[kind];
+    pl.lds = lds_bytes_for(tm, tm.dev.chunk[kind]);
+    pl.wg_per_cu = tm.tiling[kind].wg_per_cu;
+    return pl;
 }
 
 TeamHost& find_team(mrv_ctx ctx, int h)
@@ -580,9 +606,18 @@ const EnvHost* find_env(mrv_ctx ctx, int h)
 void host_call(mrv_ctx ctx, int team, int env, int kind, const mrv_paths* p, uint32_t flags, void* out_host)
 {
     set_device(ctx);
-    std::lock_guard<std::mutex> lk(ctx->handle_mu);
-    TeamHost& tm = find_team(ctx, team);
-    const EnvHost* ev = kind == 0 ? find_env(ctx, env) : nullptr;
+    TeamHost tm;
+    EnvHost evh;
+    const EnvHost* ev = nullptr;
+    {
+        // copy the handles' descriptors; the device data stay owned by the context
+        std::lock_guard<std::mutex> lk(ctx->handle_mu);
+        tm = find_team(ctx, team);
+        if (kind == 0 && find_env(ctx, env)) {
+            evh = *find_env(ctx, env);
+            ev = &evh;
+        }
+    }
     check_paths_host(tm, p);
     if (p->n_queries == 0) return;
     const int n = tm.dev.n_robots;
@@ -599,7 +634,7 @@ void host_call(mrv_ctx ctx, int team, int env, int kind, const mrv_paths* p, uin
     HIPCHK(hipMemcpyAsync(ctx->in_q.p, p->wp_q, nq, hipMemcpyHostToDevice, ctx->stream));
     DevPaths dp{(const long long*)ctx->in_begin.p, (const int*)ctx->in_t.p, (const double*)ctx->in_q.p,
                 p->n_wp, p->n_queries, p->dof_stride};
-    run_call(ctx, ctx->sc, tm, ev, kind, flags, dp, max_horizon(p, n), ctx->out_buf.p, ctx->stream);
+    run_plan(ctx, ctx->sc, single_plan(tm, ev, kind, flags, dp, max_horizon(p, n)), ctx->out_buf.p, ctx->stream);
     int unresolved = 0;
     HIPCHK(hipMemcpyAsync(&unresolved, (int*)ctx->sc.ctrl.p + 1, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -613,9 +648,17 @@ void host_call(mrv_ctx ctx, int team, int env, int kind, const mrv_paths* p, uin
 void device_call(mrv_ctx ctx, int team, int env, int kind, const mrv_paths* p, uint32_t flags, void* out_dev)
 {
     set_device(ctx);
-    std::lock_guard<std::mutex> lk(ctx->handle_mu);
-    TeamHost& tm = find_team(ctx, team);
-    const EnvHost* ev = kind == 0 ? find_env(ctx, env) : nullptr;
+    TeamHost tm;
+    EnvHost evh;
+    const EnvHost* ev = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(ctx->handle_mu);
+        tm = find_team(ctx, team);
+        if (kind == 0 && find_env(ctx, env)) {
+            evh = *find_env(ctx, env);
+            ev = &evh;
+        }
+    }
     if (!p) throw Err{MRV_E_INVALID, "null paths"};
     if (p->n_queries < 0) throw Err{MRV_E_INVALID, "negative n_queries"};
     if (p->n_queries == 0) return;
@@ -623,7 +666,7 @@ void device_call(mrv_ctx ctx, int team, int env, int kind, const mrv_paths* p, u
     if (p->n_wp < 1) throw Err{MRV_E_INVALID, "n_wp must be positive"};
     if (p->dof_stride < tm.max_dof) throw Err{MRV_E_INVALID, "dof_stride smaller than the team's largest dof"};
     DevPaths dp{(const long long*)p->wp_begin, p->wp_t, p->wp_q, p->n_wp, p->n_queries, p->dof_stride};
-    run_call(ctx, ctx->sc, tm, ev, kind, flags, dp, MRV_MAX_T, out_dev, ctx->stream);
+    run_plan(ctx, ctx->sc, single_plan(tm, ev, kind, flags, dp, MRV_MAX_T), out_dev, ctx->stream);
 }
 
 uint32_t check_flags(int kind, uint32_t flags)
@@ -657,14 +700,9 @@ mrv_status wrap(Fn&& fn)
 
 namespace mrv {
 
-void serve_run_call(mrv_ctx ctx, Scratch& sc, int team, int env, int kind, uint32_t flags,
-                    const long long* wp_begin, const int* wp_t, const double* wp_q, long long n_wp,
-                    int n_queries, int dof_stride, long long max_T, void* out_dev, hipStream_t stream)
+void serve_run_plan(mrv_ctx ctx, Scratch& sc, const CallPlan& pl, void* out_dev, hipStream_t stream)
 {
-    TeamHost& tm = find_team(ctx, team);
-    const EnvHost* ev = kind == 0 ? find_env(ctx, env) : nullptr;
-    DevPaths dp{wp_begin, wp_t, wp_q, n_wp, n_queries, dof_stride};
-    run_call(ctx, sc, tm, ev, kind, flags, dp, max_T, out_dev, stream);
+    run_plan(ctx, sc, pl, out_dev, stream);
 }
 
 }  // namespace mrv
@@ -874,6 +912,8 @@ mrv_status mrv_set_tiling(mrv_ctx ctx, int32_t team, int32_t kind, const mrv_til
             throw Err{MRV_E_INVALID, "chunk does not fit in LDS for this team"};
         if (tiling->wg_per_cu < 0 || tiling->wg_per_cu > 32) throw Err{MRV_E_INVALID, "wg_per_cu out of range"};
         tm.tiling[kind] = *tiling;
+        tm.dev.chunk[kind] = tiling->chunk > 0 ? tiling->chunk : default_chunk(tm, kind);
+        HIPCHK(hipMemcpy(tm.d_dev, &tm.dev, sizeof(TeamDev), hipMemcpyHostToDevice));
     });
 }
 
@@ -885,7 +925,7 @@ mrv_status mrv_get_tiling(mrv_ctx ctx, int32_t team, int32_t kind, mrv_tiling* t
         std::lock_guard<std::mutex> lk(ctx->handle_mu);
         TeamHost& tm = find_team(ctx, team);
         mrv_tiling t = tm.tiling[kind];
-        if (t.chunk == 0) t.chunk = default_chunk(tm, kind);
+        t.chunk = tm.dev.chunk[kind];
         *tiling = t;
     });
 }
@@ -923,22 +963,24 @@ mrv_status mrv_submit(mrv_ctx ctx, const mrv_request* req, uint64_t* ticket)
     if (!req || !ticket) return fail(MRV_E_INVALID, "null argument");
     return wrap([&] {
         if (!ctx->serve) ctx->serve.reset(new ServeLoop(ctx, ctx->device, ctx->max_inflight, ctx->serve_bytes));
-        // validate against the resident handles, then copy
-        std::vector<int> dofs;
-        int n_robots = 0;
+        // validate against the resident handles, resolve their device descriptors, then copy
+        ServeRefs refs{};
         {
             std::lock_guard<std::mutex> lk(ctx->handle_mu);
             if (req->kind != 0 && req->kind != 1) throw Err{MRV_E_INVALID, "kind must be 0 (MV) or 1 (FFC)"};
             TeamHost& tm = find_team(ctx, req->team);
-            if (req->kind == 0) (void)find_env(ctx, req->env);
+            const EnvHost* ev = req->kind == 0 ? find_env(ctx, req->env) : nullptr;
             check_flags(req->kind, req->flags);
             check_paths_host(tm, &req->paths);
-            dofs = tm.dof;
-            n_robots = tm.dev.n_robots;
+            refs.team = tm.d_dev;
+            refs.env = ev ? ev->d_dev : nullptr;
+            refs.n_robots = tm.dev.n_robots;
+            refs.chunk = tm.dev.chunk[req->kind];
+            refs.lds = lds_bytes_for(tm, tm.dev.chunk[req->kind]);
             tm.inflight++;
             if (req->kind == 0 && req->env >= 0) ctx->envs.find(req->env)->second.inflight++;
         }
-        mrv_status s = ctx->serve->submit(*req, n_robots, ticket);
+        mrv_status s = ctx->serve->submit(*req, refs, ticket);
         if (s != MRV_OK) {
             std::lock_guard<std::mutex> lk(ctx->handle_mu);
             ctx->teams.find(req->team)->second.inflight--;

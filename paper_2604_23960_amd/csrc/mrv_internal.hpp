@@ -36,6 +36,8 @@ struct TeamDev {
     int P;                 // robot pairs n(n-1)/2
     int max_dof;
     int G;                 // sphere groups per timestep (16 consecutive spheres of one robot)
+    int chunk[2];          // timesteps per tile for MV / FFC
+    int lds_per_t;         // LDS bytes one timestep of a tile needs
     float r_max;           // largest sphere radius of the team
     long long rr_tests_per_t;   // sum_{i<j} n_i n_j
     const int* r_nj;            // [n]
@@ -81,14 +83,20 @@ struct EnvDev {
     double pt_radius64;
 };
 
-// One MV/FFC call.
+// One MV/FFC call.  Every query has a team and an environment: either the same
+// for all (team0/env0) or per query (q_team/q_env), and its paths start at
+// q_pathoff[q] (or q * n_robots when all queries share team0).
 struct CallDev {
     int n_queries;
-    int n_robots;
     int dof_stride;
     int kind;                   // 0 = MV, 1 = FFC
     unsigned flags;
-    int chunk;                  // timesteps per tile
+    int lds_bytes;              // dynamic LDS of the validation launch
+    const TeamDev* team0;
+    const TeamDev* const* q_team;
+    const EnvDev* env0;         // null: no obstacles
+    const EnvDev* const* q_env;
+    const long long* q_pathoff;
     float eps32;
     double eps64;
     long long n_wp;
@@ -99,6 +107,7 @@ struct CallDev {
     int* T;
     int* nt;
     int* gstep;
+    int* q_chunk;               // timesteps per tile chosen for each query
     int* status;                // 0 ok, 1 invalid input
     unsigned* word;             // MV: hit flag; FFC: best key t*P + pair
     int* sorted_q;
@@ -118,10 +127,9 @@ struct CallDev {
 
 // Kernel launchers (mrv_kernels.hip).  All launch on `stream` and return the
 // first launch error.
-hipError_t launch_prepare(const TeamDev& tm, const CallDev& cd, hipStream_t stream);
-hipError_t launch_validate(const TeamDev& tm, const EnvDev& env, const CallDev& cd, int grid,
-                           size_t lds_bytes, hipStream_t stream);
-hipError_t launch_finalize(const TeamDev& tm, const EnvDev& env, const CallDev& cd, hipStream_t stream);
+hipError_t launch_prepare(const CallDev& cd, hipStream_t stream);
+hipError_t launch_validate(const CallDev& cd, int grid, hipStream_t stream);
+hipError_t launch_finalize(const CallDev& cd, hipStream_t stream);
 hipError_t fill_u32(void* p, unsigned v, size_t n, hipStream_t stream);
 // Occupancy-derived workgroups per CU for the validation kernel.
 int validate_blocks_per_cu(int kind, size_t lds_bytes);

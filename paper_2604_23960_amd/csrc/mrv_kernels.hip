@@ -34,6 +34,35 @@ namespace {
 
 __device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+__device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v)
+{
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return (unsigned long long)lo | ((unsigned long long)hi << 32);
+}
+
+// Copy of a descriptor that no kernel writes, read through the constant address
+// space so that a wave-uniform address turns into scalar loads.
+template <class T>
+__device__ __forceinline__ T load_descriptor(unsigned long long p)
+{
+    static_assert(sizeof(T) % 4 == 0, "descriptor size");
+    T out;
+    typedef const __attribute__((address_space(4))) unsigned cu32;
+    cu32* src = (cu32*)p;
+    unsigned* dst = reinterpret_cast<unsigned*>(&out);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) dst[i] = src[i];
+    return out;
+}
+
+__device__ __forceinline__ const TeamDev* team_of(const CallDev& cd, int q) { return cd.q_team ? cd.q_team[q] : cd.team0; }
+__device__ __forceinline__ const EnvDev* env_of(const CallDev& cd, int q) { return cd.q_env ? cd.q_env[q] : cd.env0; }
+__device__ __forceinline__ long long path_of(const CallDev& cd, int n_robots, int q)
+{
+    return cd.q_pathoff ? cd.q_pathoff[q] : (long long)q * n_robots;
+}
+
 __device__ __forceinline__ unsigned wave_min_u32(unsigned v)
 {
 #pragma unroll
@@ -78,8 +107,9 @@ __device__ void fk64_sphere(const TeamDev& tm, const CallDev& cd, int q, int t, 
 #pragma clang fp contract(off)
     const int r = tm.s_robot[s];
     const int f = tm.s_lframe[s];
-    const long long pb = cd.wp_begin[(long long)q * cd.n_robots + r];
-    const long long pe = cd.wp_begin[(long long)q * cd.n_robots + r + 1];
+    const long long p0 = path_of(cd, tm.n_robots, q);
+    const long long pb = cd.wp_begin[p0 + r];
+    const long long pe = cd.wp_begin[p0 + r + 1];
     const long long k = find_segment(cd.wp_t, pb, pe, t);
     const bool last = (k == pe - 1);
     double sfrac = 0.0;
@@ -247,16 +277,20 @@ __global__ void k_reset(CallDev cd)
     }
 }
 
-__global__ void k_query_info(TeamDev tm, CallDev cd)
+__global__ void k_query_info(CallDev cd)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= cd.n_queries) return;
-    const int n = cd.n_robots;
+    const TeamDev& tm = *team_of(cd, q);
+    const int n = tm.n_robots;
+    const long long p0 = path_of(cd, n, q);
+    int chunk = min(tm.chunk[cd.kind], (cd.lds_bytes - 64) / tm.lds_per_t);
+    chunk = max(1, min(chunk, kMaxChunk));
     int T = 0;
     bool ok = true;
     for (int r = 0; r < n && ok; ++r) {
-        const long long b = cd.wp_begin[(long long)q * n + r];
-        const long long e = cd.wp_begin[(long long)q * n + r + 1];
+        const long long b = cd.wp_begin[p0 + r];
+        const long long e = cd.wp_begin[p0 + r + 1];
         if (b < 0 || e <= b || e > cd.n_wp) { ok = false; break; }
         int prev = cd.wp_t[b];
         if (prev != 0) { ok = false; break; }
@@ -273,12 +307,13 @@ __global__ void k_query_info(TeamDev tm, CallDev cd)
     }
     int nt = 0, g = 1;
     if (ok) {
-        nt = (T + cd.chunk - 1) / cd.chunk;
+        nt = (T + chunk - 1) / chunk;
         g = golden_step(nt);
     }
     cd.T[q] = ok ? T : 0;
     cd.nt[q] = nt;
     cd.gstep[q] = g;
+    cd.q_chunk[q] = chunk;
     cd.status[q] = ok ? 0 : 1;
     cd.word[q] = cd.kind == 1 ? 0xFFFFFFFFu : 0u;
     if (!ok) {
@@ -358,10 +393,11 @@ __global__ void k_assign(CallDev cd)
     }
 }
 
-__global__ void k_finalize(TeamDev tm, CallDev cd)
+__global__ void k_finalize(CallDev cd)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= cd.n_queries) return;
+    const TeamDev& tm = *team_of(cd, q);
     const int st = cd.status[q];
     const bool bad = st != 0;
     const unsigned w = cd.word[q];
@@ -477,22 +513,14 @@ __device__ __forceinline__ int classify(float d2, float R, float eps)
 }
 
 template <int KIND>
-__global__ __launch_bounds__(kWG) void k_validate(TeamDev tm, EnvDev env, CallDev cd)
+__global__ __launch_bounds__(kWG) void k_validate(CallDev cd)
 {
     extern __shared__ float4 dyn[];
-    const int C = cd.chunk;
-    const int S = tm.S;
-    const int F = tm.F;
-    const int G = tm.G;
-    const int n = tm.n_robots;
-    float4* rec = dyn;                                  // [C][S] (x', y', z', r) relative to the group centre
-    float* rw = reinterpret_cast<float*>(dyn + C * S);  // [C][S] w' = |x'|^2 - r^2
-    float4* gc = dyn + C * S + (C * S + 3) / 4;         // [C][G] group centres
-    float4* fr = gc + C * G;                            // [C][F][3] frame rows
 
     __shared__ int s_t[kMaxChunk];
-    __shared__ int s_q, s_nv, s_phase, s_hit;
+    __shared__ int s_q, s_nv, s_phase, s_hit, s_chunk;
     __shared__ unsigned s_key, s_rho2;
+    __shared__ unsigned long long s_tp, s_ep;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -517,7 +545,7 @@ __global__ __launch_bounds__(kWG) void k_validate(TeamDev tm, EnvDev env, CallDe
     for (;;) {
         if (tid == 0) {
             const long long g = (long long)atomicAdd(&w64[1], 1ull);
-            int q = -1, nv = 0, phase = 0;
+            int q = -1, nv = 0, phase = 0, C = 1;
             if (g < gtotal) {
                 long long gg = g;
                 if (hier) {
@@ -545,6 +573,11 @@ __global__ __launch_bounds__(kWG) void k_validate(TeamDev tm, EnvDev env, CallDe
                 k_cur = lo;
                 const int k = (int)lo;
                 q = cd.sorted_q[gg - off[lo]];
+                const TeamDev* tq = team_of(cd, q);
+                const EnvDev* eq = env_of(cd, q);
+                s_tp = (unsigned long long)tq;
+                s_ep = (unsigned long long)eq;
+                C = cd.q_chunk[q];
                 const int T = cd.T[q];
                 const int nt = cd.nt[q];
                 int base, stride;
@@ -562,12 +595,12 @@ __global__ __launch_bounds__(kWG) void k_validate(TeamDev tm, EnvDev env, CallDe
                 if (!exhaustive) {
                     const unsigned w = load_word(cd.word + q);
                     if (KIND == 0) skip = (w != 0u);
-                    else skip = (w != 0xFFFFFFFFu) && (w < (unsigned)base * (unsigned)tm.P);
+                    else skip = (w != 0xFFFFFFFFu) && (w < (unsigned)base * (unsigned)tq->P);
                 }
                 if (skip) { nv = 0; ++n_skip; }
-                else { ++n_run; n_states += (unsigned long long)nv * n; }
+                else { ++n_run; n_states += (unsigned long long)nv * tq->n_robots; }
             }
-            s_q = q; s_phase = phase; s_nv = nv;
+            s_q = q; s_phase = phase; s_nv = nv; s_chunk = C;
             s_hit = 0; s_key = 0xFFFFFFFFu; s_rho2 = 0u;
         }
         __syncthreads();
@@ -578,14 +611,28 @@ __global__ __launch_bounds__(kWG) void k_validate(TeamDev tm, EnvDev env, CallDe
         const int phase = s_phase;
         const bool do_env = check_env && (!hier || phase == 0);
         const bool do_rr = !hier || phase == 1;
+        // this tile's team and environment, and its LDS partition
+        const TeamDev tm = load_descriptor<TeamDev>(uniform_u64(s_tp));
+        const unsigned long long epu = uniform_u64(s_ep);
+        const EnvDev env = epu ? load_descriptor<EnvDev>(epu) : EnvDev{};
+        const int C = wave_uniform(s_chunk);
+        const int S = tm.S;
+        const int F = tm.F;
+        const int G = tm.G;
+        const int n = tm.n_robots;
+        const long long qp0 = path_of(cd, n, q);
+        float4* rec = dyn;                                  // [C][S] (x', y', z', r) relative to the group centre
+        float* rw = reinterpret_cast<float*>(dyn + C * S);  // [C][S] w' = |x'|^2 - r^2
+        float4* gc = dyn + C * S + (C * S + 3) / 4;         // [C][G] group centres
+        float4* fr = gc + C * G;                            // [C][F][3] frame rows
 
         // --- configurations and FP32 forward kinematics: one lane per (timestep, robot)
         for (int idx = tid; idx < nv * n; idx += kWG) {
             const int c = idx / n;
             const int r = idx - c * n;
             const int t = s_t[c];
-            const long long pb = cd.wp_begin[(long long)q * n + r];
-            const long long pe = cd.wp_begin[(long long)q * n + r + 1];
+            const long long pb = cd.wp_begin[qp0 + r];
+            const long long pe = cd.wp_begin[qp0 + r + 1];
             const long long kseg = find_segment(cd.wp_t, pb, pe, t);
             const bool last = (kseg == pe - 1);
             double sfrac = 0.0;
@@ -957,14 +1004,17 @@ __global__ __launch_bounds__(kWG) void k_validate(TeamDev tm, EnvDev env, CallDe
 }
 
 // FP64 re-evaluation of the near-contact tests that did not fit a tile's queue.
-__global__ void k_recheck(TeamDev tm, EnvDev env, CallDev cd)
+__global__ void k_recheck(CallDev cd)
 {
+    const EnvDev none{};
     const unsigned n = min(*reinterpret_cast<const unsigned*>(cd.ctrl + 2), (unsigned)cd.gq_cap);
     if (blockIdx.x == 0 && threadIdx.x == 0) cd.stats[ST_RECHECKS] = n;
     for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const int4 r0 = cd.gq[i];
         const int q = r0.x, t = r0.y & 0xffffff, kind = r0.y >> 24, a = r0.z, b = r0.w;
-        if (!recheck64(tm, env, cd, q, t, kind, a, b)) continue;
+        const TeamDev& tm = *team_of(cd, q);
+        const EnvDev* ep = env_of(cd, q);
+        if (!recheck64(tm, ep ? *ep : none, cd, q, t, kind, a, b)) continue;
         if (cd.kind == 0) atomicOr(cd.word + q, 1u);
         else atomicMin(cd.word + q, (unsigned)t * (unsigned)tm.P + pair_index(tm.s_robot[a], tm.s_robot[b], tm.n_robots));
     }
@@ -983,35 +1033,34 @@ hipError_t fill_u32(void* p, unsigned v, size_t n, hipStream_t stream)
     return hipGetLastError();
 }
 
-hipError_t launch_prepare(const TeamDev& tm, const CallDev& cd, hipStream_t stream)
+hipError_t launch_prepare(const CallDev& cd, hipStream_t stream)
 {
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, cd);
     if (cd.n_queries > 0) {
         const unsigned blocks = (unsigned)((cd.n_queries + 255) / 256);
-        hipLaunchKernelGGL(k_query_info, dim3(blocks), dim3(256), 0, stream, tm, cd);
+        hipLaunchKernelGGL(k_query_info, dim3(blocks), dim3(256), 0, stream, cd);
         hipLaunchKernelGGL(k_scan, dim3(1), dim3(256), 0, stream, cd);
         hipLaunchKernelGGL(k_assign, dim3(blocks), dim3(256), 0, stream, cd);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_validate(const TeamDev& tm, const EnvDev& env, const CallDev& cd, int grid,
-                           size_t lds_bytes, hipStream_t stream)
+hipError_t launch_validate(const CallDev& cd, int grid, hipStream_t stream)
 {
     if (cd.n_queries == 0) return hipSuccess;
     if (cd.kind == 0)
-        hipLaunchKernelGGL(k_validate<0>, dim3(grid), dim3(kWG), lds_bytes, stream, tm, env, cd);
+        hipLaunchKernelGGL(k_validate<0>, dim3(grid), dim3(kWG), (size_t)cd.lds_bytes, stream, cd);
     else
-        hipLaunchKernelGGL(k_validate<1>, dim3(grid), dim3(kWG), lds_bytes, stream, tm, env, cd);
+        hipLaunchKernelGGL(k_validate<1>, dim3(grid), dim3(kWG), (size_t)cd.lds_bytes, stream, cd);
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const TeamDev& tm, const EnvDev& env, const CallDev& cd, hipStream_t stream)
+hipError_t launch_finalize(const CallDev& cd, hipStream_t stream)
 {
     if (cd.n_queries == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_recheck, dim3(256), dim3(256), 0, stream, tm, env, cd);
+    hipLaunchKernelGGL(k_recheck, dim3(256), dim3(256), 0, stream, cd);
     const unsigned blocks = (unsigned)((cd.n_queries + 255) / 256);
-    hipLaunchKernelGGL(k_finalize, dim3(blocks), dim3(256), 0, stream, tm, cd);
+    hipLaunchKernelGGL(k_finalize, dim3(blocks), dim3(256), 0, stream, cd);
     return hipGetLastError();
 }
 

@@ -58,14 +58,14 @@ struct Scratch {
     DevBuf ctrl;            // 8 ints + ST_COUNT u64
     DevBuf hist, start, off;
     size_t bins = 0;
-    DevBuf q_T, q_nt, q_g, q_status, q_word, q_sorted;
+    DevBuf q_T, q_nt, q_g, q_chunk, q_status, q_word, q_sorted;
     DevBuf gq;              // near-contact queue (int4 records)
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     int last_kind = -1;
     static constexpr int kGlobalRecheckCap = 1 << 21;
     void release()
     {
-        for (DevBuf* b : {&ctrl, &hist, &start, &off, &q_T, &q_nt, &q_g, &q_status, &q_word, &q_sorted, &gq})
+        for (DevBuf* b : {&ctrl, &hist, &start, &off, &q_T, &q_nt, &q_g, &q_chunk, &q_status, &q_word, &q_sorted, &gq})
             b->release();
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
@@ -74,18 +74,49 @@ struct Scratch {
     }
     size_t bytes() const
     {
-        return ctrl.cap + hist.cap + start.cap + off.cap + q_T.cap + q_nt.cap + q_g.cap + q_status.cap +
-               q_word.cap + q_sorted.cap + gq.cap;
+        return ctrl.cap + hist.cap + start.cap + off.cap + q_T.cap + q_nt.cap + q_g.cap + q_chunk.cap +
+               q_status.cap + q_word.cap + q_sorted.cap + gq.cap;
     }
 };
 
 void ensure_scratch(Scratch& sc, size_t bins, size_t queries);
 
-// Queue one call (device arrays) on `stream` using scratch `sc`.  Caller holds
-// serve_handle_mutex(ctx) while the team/environment handles are read.
-void serve_run_call(mrv_ctx ctx, Scratch& sc, int team, int env, int kind, uint32_t flags,
-                    const long long* wp_begin, const int* wp_t, const double* wp_q, long long n_wp,
-                    int n_queries, int dof_stride, long long max_T, void* out_dev, hipStream_t stream);
+// Path arrays of one call (device pointers).
+struct DevPaths {
+    const long long* wp_begin;
+    const int* wp_t;
+    const double* wp_q;
+    long long n_wp;
+    int n_queries;
+    int dof_stride;
+};
+
+// Everything one validation call needs besides scratch and output.
+struct CallPlan {
+    int kind;
+    uint32_t flags;
+    DevPaths dp;
+    const TeamDev* team0;              // team of every query when q_team is null
+    const TeamDev* const* q_team;      // device array, one per query, or null
+    const EnvDev* env0;                // null: no obstacles
+    const EnvDev* const* q_env;        // device array, one per query, or null
+    const long long* q_pathoff;        // device array: first path of each query, or null
+    long long max_T;                   // bound on every query's horizon
+    int min_chunk;                     // smallest timesteps-per-tile among the queries' teams
+    size_t lds;                        // dynamic LDS: max over the queries' teams
+    int wg_per_cu;                     // 0 = occupancy limit
+};
+
+// Device-side descriptors a served request needs, resolved at submit time.
+struct ServeRefs {
+    const TeamDev* team;
+    const EnvDev* env;
+    int n_robots;
+    int chunk;
+    size_t lds;
+};
+
+void serve_run_plan(mrv_ctx ctx, Scratch& sc, const CallPlan& pl, void* out_dev, hipStream_t stream);
 void serve_release_handles(mrv_ctx ctx, int team, int env, int kind);
 std::mutex& serve_handle_mutex(mrv_ctx ctx);
 
@@ -94,7 +125,7 @@ class ServeLoop {
 public:
     ServeLoop(mrv_ctx ctx, int device, int max_inflight, size_t budget_bytes);
     ~ServeLoop();
-    mrv_status submit(const mrv_request& req, int n_robots, uint64_t* ticket);
+    mrv_status submit(const mrv_request& req, const ServeRefs& refs, uint64_t* ticket);
     // timeout_ms: 0 = do not wait, < 0 = wait forever
     mrv_status poll(uint64_t ticket, void* out, int timeout_ms, std::string* msg);
     mrv_status cancel(uint64_t ticket);

@@ -1,18 +1,452 @@
-// Serving loop behind mrv_submit / mrv_poll.
+// Serving loop behind mrv_submit / mrv_poll / mrv_wait / mrv_cancel.
+//
+// Requests are copied at submit time into host memory and queued.  One serve
+// thread owns a few slots; each slot has its own HIP stream, scratch set, device
+// buffers and pinned staging memory.  Whenever a slot is free and requests wait,
+// the thread merges the waiting requests that share (kind, flags) with the oldest
+// one into a single call -- requests of different teams and environments mix,
+// each query carrying its own team and environment descriptor -- as many as fit
+// the slot's share of the device-memory budget, stages their paths in pinned
+// memory, and queues one upload, the validation kernels and the download on the
+// slot stream.  Batches on different
+// slots overlap on the device, and requests that arrive while others run are
+// admitted as soon as a slot and its memory free up (continuous batching).
+// Completion is detected with HIP events; results are handed to the waiting
+// pollers through a condition variable.
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
 #include "mrv_runtime.hpp"
 
 namespace mrv {
 
-struct ServeLoop::Impl {};
+namespace {
 
-ServeLoop::ServeLoop(mrv_ctx, int, int, size_t) : impl_(nullptr) {}
-ServeLoop::~ServeLoop() {}
-mrv_status ServeLoop::submit(const mrv_request&, int, uint64_t*) { return MRV_E_INVALID; }
-mrv_status ServeLoop::poll(uint64_t, void*, int, std::string* msg)
+enum ReqState { RS_QUEUED = 0, RS_RUNNING = 1, RS_DONE = 2, RS_ERROR = 3, RS_CANCELLED = 4 };
+
+struct Req {
+    uint64_t id = 0;
+    int kind = 0, team = 0, env = -1;
+    ServeRefs refs{};
+    uint32_t flags = 0;
+    int n_queries = 0, n_robots = 0, dof_stride = 0;
+    long long max_T = 1;
+    std::vector<long long> wp_begin;   // relative to this request's waypoints
+    std::vector<int> wp_t;
+    std::vector<double> wp_q;
+    std::vector<unsigned char> result;  // uint8[n] (MV) or int32[3n] (FFC)
+    int state = RS_QUEUED;
+    bool cancel_requested = false;
+    mrv_status err = MRV_OK;
+    std::string msg;
+    size_t bytes() const
+    {
+        return wp_begin.size() * 8 + wp_t.size() * 4 + wp_q.size() * 8 + (size_t)n_queries * (7 * 4 + 12 + 24);
+    }
+};
+
+struct PinnedBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+    void ensure(size_t bytes)
+    {
+        if (bytes <= cap) return;
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        cap = 0;
+        const size_t want = std::max<size_t>(bytes, 4096);
+        if (hipHostMalloc(&p, want, hipHostMallocDefault) != hipSuccess) {
+            p = nullptr;
+            throw Err{MRV_E_NOMEM, "pinned host allocation failed"};
+        }
+        cap = want;
+    }
+    void release()
+    {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    Scratch sc;
+    DevBuf d_in, d_out;
+    PinnedBuf h_in, h_out;
+    std::vector<std::shared_ptr<Req>> batch;
+    std::vector<int> q_off;   // first query of each request in the batch
+    int kind = 0;
+    bool busy = false;
+    int unresolved = 0;       // host copy of the scratch's unresolved-query count
+};
+
+}  // namespace
+
+struct ServeLoop::Impl {
+    mrv_ctx ctx;
+    int device;
+    int max_inflight;
+    size_t budget;
+    std::mutex mu;
+    std::condition_variable cv_work;    // serve thread waits here when idle
+    std::condition_variable cv_done;    // pollers wait here
+    std::deque<std::shared_ptr<Req>> queue;
+    std::unordered_map<uint64_t, std::shared_ptr<Req>> tickets;
+    uint64_t next_id = 1;
+    int inflight = 0;                   // queued + running requests
+    bool stop = false;
+    std::vector<Slot> slots;
+    std::thread th;
+
+    static constexpr int kSlots = 4;
+    static constexpr int kMaxBatchQueries = 1 << 16;
+
+    Impl(mrv_ctx c, int dev, int mi, size_t b) : ctx(c), device(dev), max_inflight(mi), budget(b)
+    {
+        HIPCHK(hipSetDevice(device));
+        slots.resize(kSlots);
+        for (Slot& s : slots) {
+            HIPCHK(hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking));
+            HIPCHK(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
+        }
+        th = std::thread([this] { run(); });
+    }
+
+    ~Impl()
+    {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            stop = true;
+        }
+        cv_work.notify_all();
+        if (th.joinable()) th.join();
+        (void)hipSetDevice(device);
+        for (Slot& s : slots) {
+            if (s.stream) (void)hipStreamSynchronize(s.stream);
+            for (auto& r : s.batch) serve_release_handles(ctx, r->team, r->env, r->kind);
+            s.sc.release();
+            for (DevBuf* b : {&s.d_in, &s.d_out}) b->release();
+            s.h_in.release();
+            s.h_out.release();
+            if (s.done) (void)hipEventDestroy(s.done);
+            if (s.stream) (void)hipStreamDestroy(s.stream);
+        }
+        for (auto& r : queue) serve_release_handles(ctx, r->team, r->env, r->kind);
+        cv_done.notify_all();
+    }
+
+    // ---- serve thread
+    void run()
+    {
+        (void)hipSetDevice(device);
+        std::unique_lock<std::mutex> lk(mu);
+        for (;;) {
+            bool progress = false;
+            // completions
+            for (Slot& s : slots) {
+                if (!s.busy) continue;
+                if (hipEventQuery(s.done) != hipSuccess) continue;
+                complete(s);
+                progress = true;
+            }
+            // admissions
+            for (Slot& s : slots) {
+                if (stop) break;
+                if (s.busy) continue;
+                drop_cancelled();
+                if (queue.empty()) break;
+                launch(s, lk);
+                progress = true;
+            }
+            if (stop) {
+                bool any = false;
+                for (Slot& s : slots) any = any || s.busy;
+                if (!any) break;
+            }
+            if (progress) continue;
+            bool any_busy = false;
+            for (Slot& s : slots) any_busy = any_busy || s.busy;
+            if (any_busy) {
+                // a batch is on the device: poll its event shortly
+                lk.unlock();
+                std::this_thread::sleep_for(std::chrono::microseconds(20));
+                lk.lock();
+            } else {
+                cv_work.wait(lk, [this] { return stop || !queue.empty(); });
+            }
+        }
+    }
+
+    void drop_cancelled()
+    {
+        while (!queue.empty() && queue.front()->cancel_requested) {
+            auto r = queue.front();
+            queue.pop_front();
+            finish(r, RS_CANCELLED, MRV_E_CANCELLED, "cancelled");
+        }
+    }
+
+    void finish(const std::shared_ptr<Req>& r, int state, mrv_status err, const std::string& msg)
+    {
+        r->state = state;
+        r->err = err;
+        r->msg = msg;
+        r->wp_begin.clear();
+        r->wp_t.clear();
+        r->wp_q.clear();
+        r->wp_begin.shrink_to_fit();
+        r->wp_t.shrink_to_fit();
+        r->wp_q.shrink_to_fit();
+        inflight--;
+        serve_release_handles(ctx, r->team, r->env, r->kind);
+        cv_done.notify_all();
+    }
+
+    // Form a batch from the queue head and queue it on slot s.  Called with mu held;
+    // the staging copies and launches run with mu released.
+    void launch(Slot& s, std::unique_lock<std::mutex>& lk)
+    {
+        std::vector<std::shared_ptr<Req>> batch;
+        const std::shared_ptr<Req> head = queue.front();
+        const size_t slot_budget = std::max<size_t>(budget / kSlots, 1);
+        size_t bytes = 0;
+        int nq = 0;
+        for (auto it = queue.begin(); it != queue.end();) {
+            const auto& r = *it;
+            const bool same = r->kind == head->kind && r->flags == head->flags && r->dof_stride == head->dof_stride &&
+                              !r->cancel_requested;
+            if (same && (batch.empty() || (bytes + r->bytes() <= slot_budget && nq + r->n_queries <= kMaxBatchQueries))) {
+                bytes += r->bytes();
+                nq += r->n_queries;
+                r->state = RS_RUNNING;
+                batch.push_back(r);
+                it = queue.erase(it);
+            } else {
+                ++it;
+            }
+        }
+        s.busy = true;
+        s.batch = batch;
+        s.kind = head->kind;
+        lk.unlock();
+        mrv_status err = MRV_OK;
+        std::string msg;
+        try {
+            stage_and_run(s);
+        } catch (const Err& e) {
+            err = e.s;
+            msg = e.msg;
+        } catch (...) {
+            err = MRV_E_DEVICE;
+            msg = "serving launch failed";
+        }
+        lk.lock();
+        if (err != MRV_OK) {
+            (void)hipStreamSynchronize(s.stream);
+            for (auto& r : s.batch) finish(r, RS_ERROR, err, msg);
+            s.batch.clear();
+            s.busy = false;
+        }
+    }
+
+    void stage_and_run(Slot& s)
+    {
+        const auto& head = s.batch.front();
+        const int stride = head->dof_stride;
+        long long n_wp = 0, max_T = 1, n_paths = 0;
+        int nq = 0, min_chunk = 1 << 30;
+        size_t lds = 0;
+        s.q_off.clear();
+        for (auto& r : s.batch) {
+            s.q_off.push_back(nq);
+            nq += r->n_queries;
+            n_wp += (long long)r->wp_t.size();
+            n_paths += (long long)r->n_queries * r->n_robots;
+            max_T = std::max(max_T, r->max_T);
+            min_chunk = std::min(min_chunk, r->refs.chunk);
+            lds = std::max(lds, r->refs.lds);
+        }
+        // one pinned block: wp_begin | wp_t | wp_q | q_team | q_env | q_pathoff
+        auto align = [](size_t v) { return (v + 255) & ~size_t(255); };
+        const size_t nb = (size_t)(n_paths + 1) * sizeof(long long);
+        const size_t nt = (size_t)n_wp * sizeof(int);
+        const size_t nqb = (size_t)n_wp * stride * sizeof(double);
+        const size_t o_t = align(nb), o_q = align(o_t + nt), o_team = align(o_q + nqb);
+        const size_t o_env = align(o_team + (size_t)nq * 8), o_po = align(o_env + (size_t)nq * 8);
+        const size_t total = o_po + (size_t)nq * 8;
+        const size_t nout = s.kind == 0 ? (size_t)nq : (size_t)nq * 12;
+        s.h_in.ensure(total);
+        s.h_out.ensure(nout + 64);
+        char* h = (char*)s.h_in.p;
+        long long* hb = (long long*)h;
+        int* ht = (int*)(h + o_t);
+        double* hq = (double*)(h + o_q);
+        const TeamDev** hteam = (const TeamDev**)(h + o_team);
+        const EnvDev** henv = (const EnvDev**)(h + o_env);
+        long long* hpo = (long long*)(h + o_po);
+        long long wbase = 0, pbase = 0;
+        int qi = 0;
+        for (auto& r : s.batch) {
+            const size_t np = (size_t)r->n_queries * r->n_robots;
+            for (size_t i = 0; i < np; ++i) hb[pbase + i] = r->wp_begin[i] + wbase;
+            for (int k = 0; k < r->n_queries; ++k, ++qi) {
+                hteam[qi] = r->refs.team;
+                henv[qi] = r->refs.env;
+                hpo[qi] = pbase + (long long)k * r->n_robots;
+            }
+            std::memcpy(ht + wbase, r->wp_t.data(), r->wp_t.size() * sizeof(int));
+            std::memcpy(hq + wbase * stride, r->wp_q.data(), r->wp_q.size() * sizeof(double));
+            pbase += (long long)np;
+            wbase += (long long)r->wp_t.size();
+        }
+        hb[pbase] = wbase;
+        s.d_in.ensure(total);
+        s.d_out.ensure(nout);
+        char* d = (char*)s.d_in.p;
+        HIPCHK(hipSetDevice(device));
+        HIPCHK(hipMemcpyAsync(d, h, total, hipMemcpyHostToDevice, s.stream));
+        CallPlan pl{};
+        pl.kind = s.kind;
+        pl.flags = head->flags;
+        pl.dp = DevPaths{(const long long*)d, (const int*)(d + o_t), (const double*)(d + o_q), n_wp, nq, stride};
+        pl.team0 = head->refs.team;
+        pl.q_team = (const TeamDev* const*)(d + o_team);
+        pl.env0 = nullptr;
+        pl.q_env = (const EnvDev* const*)(d + o_env);
+        pl.q_pathoff = (const long long*)(d + o_po);
+        pl.max_T = max_T;
+        pl.min_chunk = min_chunk;
+        pl.lds = lds;
+        pl.wg_per_cu = 0;
+        serve_run_plan(ctx, s.sc, pl, s.d_out.p, s.stream);
+        HIPCHK(hipMemcpyAsync(s.h_out.p, s.d_out.p, nout, hipMemcpyDeviceToHost, s.stream));
+        HIPCHK(hipMemcpyAsync((char*)s.h_out.p + nout, (int*)s.sc.ctrl.p + 1, sizeof(int), hipMemcpyDeviceToHost,
+                              s.stream));
+        HIPCHK(hipEventRecord(s.done, s.stream));
+    }
+
+    void complete(Slot& s)
+    {
+        const size_t per = s.kind == 0 ? 1 : 12;
+        int total = 0;
+        for (auto& r : s.batch) total += r->n_queries;
+        const size_t nout = (size_t)total * per;
+        int unresolved = 0;
+        std::memcpy(&unresolved, (char*)s.h_out.p + nout, sizeof(int));
+        for (size_t k = 0; k < s.batch.size(); ++k) {
+            auto& r = s.batch[k];
+            const size_t off = (size_t)s.q_off[k] * per;
+            r->result.assign((unsigned char*)s.h_out.p + off, (unsigned char*)s.h_out.p + off + (size_t)r->n_queries * per);
+            bool bad = false;
+            if (unresolved) {
+                for (int i = 0; i < r->n_queries && !bad; ++i) {
+                    if (s.kind == 0) bad = r->result[i] == 3;
+                    else bad = ((const int*)r->result.data())[3 * i] == -3;
+                }
+            }
+            if (r->cancel_requested) finish(r, RS_CANCELLED, MRV_E_CANCELLED, "cancelled");
+            else if (bad) finish(r, RS_ERROR, MRV_E_NOMEM, "near-contact re-evaluation queue overflow");
+            else finish(r, RS_DONE, MRV_OK, "");
+        }
+        s.batch.clear();
+        s.busy = false;
+    }
+};
+
+ServeLoop::ServeLoop(mrv_ctx ctx, int device, int max_inflight, size_t budget_bytes)
+    : impl_(new Impl(ctx, device, max_inflight, budget_bytes))
 {
-    if (msg) *msg = "unknown ticket";
-    return MRV_E_HANDLE;
 }
-mrv_status ServeLoop::cancel(uint64_t) { return MRV_E_HANDLE; }
+
+ServeLoop::~ServeLoop() { delete impl_; }
+
+mrv_status ServeLoop::submit(const mrv_request& req, const ServeRefs& refs, uint64_t* ticket)
+{
+    auto r = std::make_shared<Req>();
+    r->kind = req.kind;
+    r->team = req.team;
+    r->env = req.kind == 0 ? req.env : -1;
+    r->refs = refs;
+    r->flags = req.flags;
+    r->n_queries = req.paths.n_queries;
+    r->n_robots = refs.n_robots;
+    const int n_robots = refs.n_robots;
+    r->dof_stride = req.paths.dof_stride;
+    const size_t np = (size_t)req.paths.n_queries * n_robots;
+    if (req.paths.n_queries > 0) {
+        r->wp_begin.assign(req.paths.wp_begin, req.paths.wp_begin + np + 1);
+        r->wp_t.assign(req.paths.wp_t, req.paths.wp_t + req.paths.n_wp);
+        r->wp_q.assign(req.paths.wp_q, req.paths.wp_q + (size_t)req.paths.n_wp * req.paths.dof_stride);
+        for (size_t i = 0; i < np; ++i)
+            r->max_T = std::max<long long>(r->max_T, (long long)r->wp_t[r->wp_begin[i + 1] - 1] + 1);
+    }
+    if (r->bytes() > impl_->budget) return MRV_E_NOMEM;
+    std::lock_guard<std::mutex> lk(impl_->mu);
+    if (impl_->inflight >= impl_->max_inflight) return MRV_E_BUSY;
+    r->id = impl_->next_id++;
+    impl_->inflight++;
+    impl_->tickets[r->id] = r;
+    if (r->n_queries == 0) {
+        r->state = RS_DONE;
+        impl_->inflight--;
+        serve_release_handles(impl_->ctx, r->team, r->env, r->kind);
+    } else {
+        impl_->queue.push_back(r);
+        impl_->cv_work.notify_one();
+    }
+    *ticket = r->id;
+    return MRV_OK;
+}
+
+mrv_status ServeLoop::poll(uint64_t ticket, void* out, int timeout_ms, std::string* msg)
+{
+    std::unique_lock<std::mutex> lk(impl_->mu);
+    auto it = impl_->tickets.find(ticket);
+    if (it == impl_->tickets.end()) {
+        if (msg) *msg = "unknown ticket";
+        return MRV_E_HANDLE;
+    }
+    std::shared_ptr<Req> r = it->second;
+    auto finished = [&] { return r->state >= RS_DONE; };
+    if (!finished() && timeout_ms != 0) {
+        if (timeout_ms < 0) impl_->cv_done.wait(lk, [&] { return finished() || impl_->stop; });
+        else impl_->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), finished);
+    }
+    if (!finished()) return MRV_PENDING;
+    impl_->tickets.erase(r->id);
+    if (r->state == RS_DONE) {
+        if (out && !r->result.empty()) std::memcpy(out, r->result.data(), r->result.size());
+        return MRV_OK;
+    }
+    if (msg) *msg = r->msg;
+    return r->err;
+}
+
+mrv_status ServeLoop::cancel(uint64_t ticket)
+{
+    std::lock_guard<std::mutex> lk(impl_->mu);
+    auto it = impl_->tickets.find(ticket);
+    if (it == impl_->tickets.end()) return MRV_E_HANDLE;
+    auto& r = it->second;
+    if (r->state >= RS_DONE) return MRV_OK;
+    r->cancel_requested = true;
+    if (r->state == RS_QUEUED) {
+        for (auto q = impl_->queue.begin(); q != impl_->queue.end(); ++q)
+            if ((*q)->id == r->id) {
+                impl_->queue.erase(q);
+                break;
+            }
+        impl_->finish(r, RS_CANCELLED, MRV_E_CANCELLED, "cancelled");
+    }
+    return MRV_OK;
+}
 
 }  // namespace mrv

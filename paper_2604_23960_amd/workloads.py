@@ -438,3 +438,55 @@ def ffc_workload(n_queries: int = 16384, seed: int = 2) -> Workload:
 
 def small(w_fn, n_queries: int, **kw) -> Workload:
     return w_fn(n_queries=n_queries, **kw)
+
+
+# ----------------------------------------------------------------------------
+# serving workload: many planner clients with resident teams
+
+@dataclass
+class ServeRequest:
+    client: int
+    kind: int            # 0 MV, 1 FFC
+    paths: Paths         # one query
+    horizon: int
+
+
+def serving_workload(n_requests: int, n_clients: int = 64, seed: int = 3, mv_fraction: float = 0.7,
+                     t_lo: int = 8, t_hi: int = 4096):
+    """Clients with teams of 2-8 robots drawn from the arm models (distinct corners)
+    and SE(2) rectangles, the cube obstacles, and single-query requests:
+    MV straight-line motions with T ~ round(log-uniform[t_lo, t_hi]) states, FFC
+    timed paths with per-robot lengths U[ceil(T/2), T] (one robot exactly T).
+    Returns (teams, env, requests)."""
+    rng_t = _rng(seed, STREAM_TEAM)
+    models = arm_models(1)
+    teams = []
+    for _ in range(n_clients):
+        n = int(rng_t.integers(2, 9))
+        n_arms = int(rng_t.integers(0, min(4, n) + 1))
+        corners = rng_t.permutation(4)[:n_arms]
+        team = []
+        for k, c in enumerate(corners):
+            x, y = CORNERS[int(c)]
+            team.append(models[int(c)].with_base(arm_base(x, y), f"arm{k}"))
+        for k in range(n - n_arms):
+            team.append(se2_rect(0.5, f"rect{k}"))
+        teams.append(team)
+    env = cube_env(1)
+    rng = _rng(seed, STREAM_WORK)
+    reqs = []
+    for _ in range(n_requests):
+        client = int(rng.integers(0, n_clients))
+        team = teams[client]
+        T = int(round(math.exp(rng.uniform(math.log(t_lo), math.log(t_hi)))))
+        if rng.random() < mv_fraction:
+            s = sample_configs(rng, team, 1, 7)[0]
+            g = sample_configs(rng, team, 1, 7)[0]
+            rows = [(np.array([0, T - 1]), np.stack([s[r, :rob.dof], g[r, :rob.dof]])) for r, rob in enumerate(team)]
+            reqs.append(ServeRequest(client, 0, paths_from_lists([rows], 7), T))
+        else:
+            lengths = rng.integers((T + 1) // 2, T + 1, (1, len(team)))
+            lengths[0, int(rng.integers(0, len(team)))] = T
+            p = random_timed_paths(rng, team, 1, 0, 0, 2, 4, 7, lengths=lengths)
+            reqs.append(ServeRequest(client, 1, p, T))
+    return teams, env, reqs
