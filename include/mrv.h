@@ -109,8 +109,9 @@ mrv_status mrv_load_team(mrv_ctx ctx, const mrv_robot_desc* robots, int32_t n_ro
                          int32_t* team_out);
 
 /* ---------------------------------------------------------- environments */
-/* Obstacles in the world frame (paper §III-A: environment geometry per robot
- * frame; here one world-frame copy serves every robot, see DESIGN notes). */
+/* Obstacles in the world frame.  The paper keeps a copy per robot base frame
+ * (§III-A, Alg. 1 input); here one world-frame copy serves every robot, because
+ * the robot-robot tests need world-frame sphere centres anyway. */
 typedef struct {
     int32_t n_spheres; const double* spheres;      /* [n][4] centre, radius */
     int32_t n_boxes;   const double* boxes;        /* [n][15] centre, R (row-major 3x3), half-extents */
@@ -123,7 +124,8 @@ typedef struct {
 /* Upload an environment (host arrays, copied).  *env_out receives the handle. */
 mrv_status mrv_load_env(mrv_ctx ctx, const mrv_env_desc* env, int32_t* env_out);
 
-/* Drop a team or environment handle.  MRV_E_BUSY while a served request uses it. */
+/* Drop a team or environment handle.  MRV_E_BUSY while a served request or a
+ * captured graph (mrv_graph_create) uses it. */
 mrv_status mrv_unload(mrv_ctx ctx, int32_t handle);
 
 /* ----------------------------------------------------------------- paths */
@@ -188,6 +190,31 @@ typedef struct {
 /* Set the tiling used for (team, kind) where kind 0 = MV, 1 = FFC. */
 mrv_status mrv_set_tiling(mrv_ctx ctx, int32_t team, int32_t kind, const mrv_tiling* tiling);
 mrv_status mrv_get_tiling(mrv_ctx ctx, int32_t team, int32_t kind, mrv_tiling* tiling);
+
+/* Search the tiling for (team, env, kind, flags) by timing the validation kernel on
+ * the given host paths (a representative sample of the workload) with every
+ * chunk size that fits in LDS and a few workgroup counts per compute unit; the
+ * fastest is set for the team (as mrv_set_tiling would) and returned in *best.
+ * Results are cached per context by the team's shape (spheres, frames, groups,
+ * robots), the environment's obstacle counts and the flags: a later call with
+ * an equal key returns the cached tiling without timing.  The answers of MV/FFC
+ * never depend on the tiling. */
+mrv_status mrv_autotune(mrv_ctx ctx, int32_t team, int32_t env, int32_t kind, const mrv_paths* sample,
+                        uint32_t flags, mrv_tiling* best);
+
+/* Captured call graphs.  mrv_graph_create records the complete pipeline of one
+ * device-array call (the same arguments as mrv_mv_device / mrv_ffc_device, kind
+ * 0 = MV, 1 = FFC) into a HIP graph with its own scratch; mrv_graph_launch
+ * replays it on the context stream with one launch.  The graph reads the path
+ * arrays and writes the output at replay time, so the caller may refill the same
+ * buffers (same n_queries, no more than n_wp waypoints) between replays.
+ * Replays of one graph must not overlap each other.  Destroy graphs before their
+ * context; a graph keeps its team and environment loaded until it is destroyed. */
+typedef struct mrv_graph_s* mrv_graph;
+mrv_status mrv_graph_create(mrv_ctx ctx, int32_t team, int32_t env, int32_t kind, const mrv_paths* paths,
+                            uint32_t flags, void* out, mrv_graph* graph);
+mrv_status mrv_graph_launch(mrv_ctx ctx, mrv_graph graph);
+mrv_status mrv_graph_destroy(mrv_ctx ctx, mrv_graph graph);
 
 typedef struct {
     uint64_t tiles_run, tiles_skipped;

@@ -92,9 +92,18 @@ struct mrv_ctx_s {
     Scratch sc;             // scratch of the synchronous and device-array calls
     DevBuf in_begin, in_t, in_q, out_buf;
 
+    std::map<std::string, mrv_tiling> tune_cache;   // autotuned tilings by team/env shape
+
     std::unique_ptr<ServeLoop> serve;
     int max_inflight = 1024;
     size_t serve_bytes = 256u << 20;
+};
+
+struct mrv_graph_s {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    Scratch sc;
+    int team = -1, env = -1, kind = 0;
 };
 
 namespace {
@@ -519,7 +528,7 @@ namespace {
 
 
 // Queue the whole pipeline for one call on `stream`.
-void run_plan(mrv_ctx ctx, Scratch& sc, const CallPlan& pl, void* out_dev, hipStream_t stream)
+void run_plan(mrv_ctx ctx, Scratch& sc, const CallPlan& pl, void* out_dev, hipStream_t stream, bool timing = true)
 {
     const int kind = pl.kind;
     const int min_chunk = std::max(1, pl.min_chunk);
@@ -563,11 +572,11 @@ void run_plan(mrv_ctx ctx, Scratch& sc, const CallPlan& pl, void* out_dev, hipSt
     const int grid = std::max(1, ctx->n_cu * want);
 
     HIPCHK(launch_prepare(cd, stream));
-    HIPCHK(hipEventRecord(sc.ev0, stream));
+    if (timing) HIPCHK(hipEventRecord(sc.ev0, stream));
     HIPCHK(launch_validate(cd, grid, stream));
-    HIPCHK(hipEventRecord(sc.ev1, stream));
+    if (timing) HIPCHK(hipEventRecord(sc.ev1, stream));
     HIPCHK(launch_finalize(cd, stream));
-    sc.last_kind = kind;
+    if (timing) sc.last_kind = kind;
 }
 
 // Plan for a call whose queries all use one team and environment.
@@ -953,6 +962,186 @@ mrv_status mrv_last_stats(mrv_ctx ctx, mrv_stats* out)
             r.kernel_ms = ms;
         *out = r;
     });
+}
+
+// ------------------------------------------------------------ autotuning
+
+mrv_status mrv_autotune(mrv_ctx ctx, int32_t team, int32_t env, int32_t kind, const mrv_paths* sample,
+                        uint32_t flags, mrv_tiling* best)
+{
+    if (guard(ctx)) return MRV_E_HANDLE;
+    if (!best || (kind != 0 && kind != 1)) return fail(MRV_E_INVALID, "bad autotune arguments");
+    return wrap([&] {
+        set_device(ctx);
+        const uint32_t f = check_flags(kind, flags);
+        TeamHost tm;
+        EnvHost evh;
+        const EnvHost* ev = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(ctx->handle_mu);
+            tm = find_team(ctx, team);
+            if (kind == 0 && find_env(ctx, env)) {
+                evh = *find_env(ctx, env);
+                ev = &evh;
+            }
+        }
+        check_paths_host(tm, sample);
+        if (sample->n_queries == 0) throw Err{MRV_E_INVALID, "empty autotune sample"};
+        const EnvDev& e = ev ? ev->dev : EnvDev{};
+        const std::string key = std::to_string(tm.dev.S) + "," + std::to_string(tm.dev.F) + "," +
+                                std::to_string(tm.dev.G) + "," + std::to_string(tm.dev.n_robots) + "," +
+                                std::to_string(tm.dev.n_self) + "|" + std::to_string(e.n_sph) + "," +
+                                std::to_string(e.n_box) + "," + std::to_string(e.n_cyl) + "," +
+                                std::to_string(e.n_pts) + "|" + std::to_string(kind) + "|" + std::to_string(f);
+        mrv_tiling choice{0, 0};
+        auto hit = ctx->tune_cache.find(key);
+        if (hit != ctx->tune_cache.end()) {
+            choice = hit->second;
+        } else {
+            const int n = tm.dev.n_robots;
+            const size_t nb = ((size_t)sample->n_queries * n + 1) * sizeof(long long);
+            const size_t ntb = (size_t)sample->n_wp * sizeof(int);
+            const size_t nqb = (size_t)sample->n_wp * (size_t)sample->dof_stride * sizeof(double);
+            const size_t nout = kind == 0 ? (size_t)sample->n_queries : (size_t)sample->n_queries * 12;
+            ctx->in_begin.ensure(nb);
+            ctx->in_t.ensure(ntb);
+            ctx->in_q.ensure(nqb);
+            ctx->out_buf.ensure(nout);
+            HIPCHK(hipMemcpyAsync(ctx->in_begin.p, sample->wp_begin, nb, hipMemcpyHostToDevice, ctx->stream));
+            HIPCHK(hipMemcpyAsync(ctx->in_t.p, sample->wp_t, ntb, hipMemcpyHostToDevice, ctx->stream));
+            HIPCHK(hipMemcpyAsync(ctx->in_q.p, sample->wp_q, nqb, hipMemcpyHostToDevice, ctx->stream));
+            DevPaths dp{(const long long*)ctx->in_begin.p, (const int*)ctx->in_t.p, (const double*)ctx->in_q.p,
+                        sample->n_wp, sample->n_queries, sample->dof_stride};
+            const long long mT = max_horizon(sample, n);
+            int cmax = (int)((kLdsBudget - 2 * 1024) / lds_per_t(tm));
+            cmax = std::max(1, std::min(cmax, kMaxChunk));
+            std::vector<int> chunks;
+            for (int c : {1, 2, 3, 4, 5, 6, 8, 10, 12, 16, 20, 24, 32, 48, 64})
+                if (c <= cmax) chunks.push_back(c);
+            if (chunks.empty() || chunks.back() != cmax) chunks.push_back(cmax);
+            float best_ms = 1e30f;
+            TeamHost trial = tm;
+            for (int c : chunks) {
+                for (int wg : {0, 1, 2}) {
+                    trial.dev.chunk[kind] = c;
+                    trial.tiling[kind] = mrv_tiling{c, wg};
+                    HIPCHK(hipMemcpyAsync(tm.d_dev, &trial.dev, sizeof(TeamDev), hipMemcpyHostToDevice, ctx->stream));
+                    float ms_min = 1e30f;
+                    for (int rep = 0; rep < 3; ++rep) {
+                        run_plan(ctx, ctx->sc, single_plan(trial, ev, kind, f, dp, mT), ctx->out_buf.p, ctx->stream);
+                        HIPCHK(hipStreamSynchronize(ctx->stream));
+                        float ms = 0.f;
+                        HIPCHK(hipEventElapsedTime(&ms, ctx->sc.ev0, ctx->sc.ev1));
+                        if (rep > 0) ms_min = std::min(ms_min, ms);
+                    }
+                    if (ms_min < best_ms) {
+                        best_ms = ms_min;
+                        choice = mrv_tiling{c, wg};
+                    }
+                }
+            }
+            ctx->tune_cache[key] = choice;
+        }
+        // apply the choice to the team (restores its descriptor)
+        std::lock_guard<std::mutex> lk(ctx->handle_mu);
+        TeamHost& live = find_team(ctx, team);
+        live.tiling[kind] = choice;
+        live.dev.chunk[kind] = choice.chunk;
+        HIPCHK(hipMemcpy(live.d_dev, &live.dev, sizeof(TeamDev), hipMemcpyHostToDevice));
+        *best = choice;
+    });
+}
+
+// ---------------------------------------------------------------- graphs
+
+mrv_status mrv_graph_create(mrv_ctx ctx, int32_t team, int32_t env, int32_t kind, const mrv_paths* paths,
+                            uint32_t flags, void* out, mrv_graph* graph)
+{
+    if (guard(ctx)) return MRV_E_HANDLE;
+    if (!graph || (kind != 0 && kind != 1)) return fail(MRV_E_INVALID, "bad graph arguments");
+    std::unique_ptr<mrv_graph_s> g(new mrv_graph_s());
+    mrv_status st = wrap([&] {
+        set_device(ctx);
+        const uint32_t f = check_flags(kind, flags);
+        if (!paths || paths->n_queries <= 0) throw Err{MRV_E_INVALID, "a graph needs at least one query"};
+        if (!paths->wp_begin || !paths->wp_t || !paths->wp_q || !out) throw Err{MRV_E_INVALID, "null device pointer"};
+        if (paths->n_wp < 1) throw Err{MRV_E_INVALID, "n_wp must be positive"};
+        TeamHost tm;
+        EnvHost evh;
+        const EnvHost* ev = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(ctx->handle_mu);
+            tm = find_team(ctx, team);
+            if (kind == 0 && find_env(ctx, env)) {
+                evh = *find_env(ctx, env);
+                ev = &evh;
+            }
+            if (paths->dof_stride < tm.max_dof) throw Err{MRV_E_INVALID, "dof_stride smaller than the team's largest dof"};
+        }
+        DevPaths dp{(const long long*)paths->wp_begin, paths->wp_t, paths->wp_q, paths->n_wp, paths->n_queries,
+                    paths->dof_stride};
+        CallPlan pl = single_plan(tm, ev, kind, f, dp, MRV_MAX_T);
+        // every buffer exists before capture: nothing is allocated inside the graph
+        ensure_scratch(g->sc, (size_t)MRV_MAX_T + 2, (size_t)paths->n_queries);
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        HIPCHK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+        try {
+            run_plan(ctx, g->sc, pl, out, ctx->stream, false);
+        } catch (...) {
+            hipGraph_t dead = nullptr;
+            (void)hipStreamEndCapture(ctx->stream, &dead);
+            if (dead) (void)hipGraphDestroy(dead);
+            throw;
+        }
+        HIPCHK(hipStreamEndCapture(ctx->stream, &g->graph));
+        HIPCHK(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+        std::lock_guard<std::mutex> lk(ctx->handle_mu);
+        find_team(ctx, team).inflight++;
+        if (ev) ctx->envs.find(env)->second.inflight++;
+        g->team = team;
+        g->env = ev ? env : -1;
+        g->kind = kind;
+    });
+    if (st != MRV_OK) {
+        if (g->exec) (void)hipGraphExecDestroy(g->exec);
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        g->sc.release();
+        return st;
+    }
+    *graph = g.release();
+    return MRV_OK;
+}
+
+mrv_status mrv_graph_launch(mrv_ctx ctx, mrv_graph graph)
+{
+    if (guard(ctx)) return MRV_E_HANDLE;
+    if (!graph || !graph->exec) return fail(MRV_E_HANDLE, "null graph");
+    return wrap([&] {
+        set_device(ctx);
+        HIPCHK(hipGraphLaunch(graph->exec, ctx->stream));
+    });
+}
+
+mrv_status mrv_graph_destroy(mrv_ctx ctx, mrv_graph graph)
+{
+    if (guard(ctx)) return MRV_E_HANDLE;
+    if (!graph) return MRV_OK;
+    mrv_status st = wrap([&] {
+        set_device(ctx);
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        std::lock_guard<std::mutex> lk(ctx->handle_mu);
+        auto t = ctx->teams.find(graph->team);
+        if (t != ctx->teams.end()) t->second.inflight--;
+        if (graph->env >= 0) {
+            auto e = ctx->envs.find(graph->env);
+            if (e != ctx->envs.end()) e->second.inflight--;
+        }
+    });
+    if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+    if (graph->graph) (void)hipGraphDestroy(graph->graph);
+    graph->sc.release();
+    delete graph;
+    return st;
 }
 
 // --------------------------------------------------------------- serving

@@ -7,6 +7,7 @@ once).  Latency = completion time - arrival time, so queueing delay counts.
 """
 from __future__ import annotations
 
+import ctypes as C
 import math
 import threading
 import time
@@ -46,40 +47,60 @@ def prepare(reqs):
 
 def run_served(ctx: mrv.Context, handles, env: int, reqs, hps, rate: float, seed: int = 0,
                flags_mv: int = mrv.CHECK_ENV, flags_ffc: int = 0):
+    """Submit on one thread at the arrival times, collect on another.  The C request
+    structs and result buffers are built before the clock starts so the timed
+    loops only cross the C ABI."""
     n = len(reqs)
+    L = mrv.lib()
     arr = arrival_times(n, rate, seed)
-    tickets = [0] * n
+    creq = [mrv.Request(r.kind, handles[r.client], env if r.kind == 0 else -1,
+                        flags_mv if r.kind == 0 else flags_ffc, hps[i].desc) for i, r in enumerate(reqs)]
+    outs = [np.zeros(1, np.uint8) if r.kind == 0 else np.zeros((1, 3), np.int32) for r in reqs]
+    optr = [o.ctypes.data for o in outs]
+    tickets = (C.c_uint64 * max(n, 1))()
+    tptr = [C.cast(C.addressof(tickets) + 8 * i, C.POINTER(C.c_uint64)) for i in range(n)]
+    rptr = [C.pointer(x) for x in creq]
     arrive = np.zeros(n)
     done = np.zeros(n)
-    results = [None] * n
     ready = threading.Semaphore(0)
+    errors = []
     t0 = time.perf_counter() + 0.01
 
     def submitter():
-        for i, r in enumerate(reqs):
-            _sleep_until(t0 + arr[i])
-            arrive[i] = t0 + arr[i]
-            while True:
-                try:
-                    tickets[i] = ctx.submit(r.kind, handles[r.client], env if r.kind == 0 else -1, hps[i],
-                                            flags_mv if r.kind == 0 else flags_ffc)
-                    break
-                except mrv.MrvError as e:
-                    if e.status != mrv.MRV_E_BUSY:
-                        raise
-                    time.sleep(50e-6)
+        try:
+            for i in range(n):
+                _sleep_until(t0 + arr[i])
+                arrive[i] = t0 + arr[i]
+                while True:
+                    st = L.mrv_submit(ctx.h, rptr[i], tptr[i])
+                    if st == mrv.MRV_OK:
+                        break
+                    if st != mrv.MRV_E_BUSY:
+                        raise mrv.MrvError(st, mrv.last_error())
+                    time.sleep(0)
+                ready.release()
+        except Exception as e:      # surface in the main thread
+            errors.append(e)
             ready.release()
 
     th = threading.Thread(target=submitter)
     th.start()
-    for i, r in enumerate(reqs):
+    for i in range(n):
         ready.acquire()
-        results[i] = ctx.poll(tickets[i], r.kind, 1, timeout_ms=None)
+        if errors:
+            break
+        st = L.mrv_wait(ctx.h, tickets[i], -1, optr[i])
+        if st != mrv.MRV_OK:
+            errors.append(mrv.MrvError(st, mrv.last_error()))
+            break
         done[i] = time.perf_counter()
     th.join()
+    if errors:
+        raise errors[0]
     lat = done - arrive
     states = float(sum(r.horizon * len(r.paths.wp_begin[:-1]) // max(r.paths.n_queries, 1) for r in reqs))
-    return summarize(lat, arrive.min(), done.max(), states), results
+    results = [o[0] if r.kind == 0 else o for o, r in zip(outs, reqs)]
+    return summarize(lat, arrive.min(), done.max(), states), [np.atleast_1d(x) for x in results]
 
 
 def run_plain(ctx: mrv.Context, handles, env: int, reqs, hps, rate: float, seed: int = 0,

@@ -26,7 +26,7 @@ MAX_T = 1 << 20
 EXPORTS = ["mrv_create", "mrv_destroy", "mrv_last_error", "mrv_load_team", "mrv_load_env", "mrv_unload",
            "mrv_mv", "mrv_ffc", "mrv_mv_device", "mrv_ffc_device", "mrv_sync", "mrv_motion_steps",
            "mrv_set_tiling", "mrv_get_tiling", "mrv_last_stats", "mrv_submit", "mrv_poll", "mrv_wait",
-           "mrv_cancel"]
+           "mrv_cancel", "mrv_autotune", "mrv_graph_create", "mrv_graph_launch", "mrv_graph_destroy"]
 
 
 class MrvError(RuntimeError):
@@ -112,6 +112,10 @@ def lib():
                 "mrv_poll": [P, C.c_uint64, P],
                 "mrv_wait": [P, C.c_uint64, I32, P],
                 "mrv_cancel": [P, C.c_uint64],
+                "mrv_autotune": [P, I32, I32, I32, C.POINTER(PathsDesc), U32, C.POINTER(Tiling)],
+                "mrv_graph_create": [P, I32, I32, I32, C.POINTER(PathsDesc), U32, P, C.POINTER(C.c_void_p)],
+                "mrv_graph_launch": [P, P],
+                "mrv_graph_destroy": [P, P],
             }
             for name, args in sig.items():
                 f = getattr(L, name)
@@ -274,6 +278,24 @@ class Context:
         s = Stats()
         check(lib().mrv_last_stats(self.h, C.byref(s)))
         return s.as_dict()
+
+    def autotune(self, team: int, env: int, kind: int, sample_paths, flags: int):
+        hp = sample_paths if isinstance(sample_paths, HostPaths) else HostPaths(sample_paths)
+        t = Tiling()
+        check(lib().mrv_autotune(self.h, team, env, kind, C.byref(hp.desc), flags, C.byref(t)))
+        return t.chunk, t.wg_per_cu
+
+    # -- captured graphs
+    def graph_create(self, team: int, env: int, kind: int, dpaths: DevicePaths, flags: int, out_ptr: int):
+        g = C.c_void_p()
+        check(lib().mrv_graph_create(self.h, team, env, kind, C.byref(dpaths.desc), flags, out_ptr, C.byref(g)))
+        return g
+
+    def graph_launch(self, g):
+        check(lib().mrv_graph_launch(self.h, g))
+
+    def graph_destroy(self, g):
+        check(lib().mrv_graph_destroy(self.h, g))
 
     # -- serving
     def submit(self, kind: int, team: int, env: int, paths, flags: int) -> int:

@@ -490,3 +490,108 @@ def serving_workload(n_requests: int, n_clients: int = 64, seed: int = 3, mv_fra
             p = random_timed_paths(rng, team, 1, 0, 0, 2, 4, 7, lengths=lengths)
             reqs.append(ServeRequest(client, 1, p, T))
     return teams, env, reqs
+
+
+# ----------------------------------------------------------------------------
+# large heterogeneous workload (vectorised generation)
+
+def box_surface_cloud(seed: int = 4, n_boxes: int = 40, n_points: int = 200_000,
+                      point_radius: float = 0.005) -> Env:
+    """Points uniform over the surfaces of random boxes (area-weighted) in the cube
+    [-1,1]^2 x [0,2]; box centres uniform, half-extents U[0.05, 0.3], random rotation."""
+    rng = _rng(seed, STREAM_ENV)
+    lo, hi = np.array([-1.0, -1.0, 0.0]), np.array([1.0, 1.0, 2.0])
+    cen = rng.uniform(lo, hi, (n_boxes, 3))
+    ext = rng.uniform(0.05, 0.3, (n_boxes, 3))
+    rot = np.stack([random_rotation(rng) for _ in range(n_boxes)])
+    # faces: axis k, sign +-1; area of a face normal to k = 4 * h_j * h_l
+    face_area = np.zeros((n_boxes, 6))
+    for k in range(3):
+        j, l = [a for a in range(3) if a != k]
+        face_area[:, 2 * k] = face_area[:, 2 * k + 1] = 4.0 * ext[:, j] * ext[:, l]
+    w = face_area.ravel() / face_area.sum()
+    pick = rng.choice(len(w), size=n_points, p=w)
+    b, f = pick // 6, pick % 6
+    k, sgn = f // 2, np.where(f % 2 == 0, 1.0, -1.0)
+    local = rng.uniform(-1.0, 1.0, (n_points, 3)) * ext[b]
+    local[np.arange(n_points), k] = sgn * ext[b, k]
+    pts = np.einsum("nij,nj->ni", rot[b], local) + cen[b]
+    return Env(points=pts, point_radius=point_radius)
+
+
+def _csr_from_times(times_list, cfg_list, dof_stride):
+    """Concatenate per-path waypoint arrays (already in query-major path order)."""
+    counts = np.array([len(t) for t in times_list], dtype=np.int64)
+    begin = np.concatenate([[0], np.cumsum(counts)])
+    wp_t = np.concatenate(times_list).astype(np.int32)
+    wp_q = np.concatenate(cfg_list)
+    return begin, wp_t, wp_q
+
+
+def straight_line_paths_T(rng, team, T: np.ndarray, dof_stride: int) -> Paths:
+    """Straight lines with given per-query horizons T (states): waypoints (0, S), (T-1, G)."""
+    nq, nr = len(T), len(team)
+    s = sample_configs(rng, team, nq, dof_stride)
+    g = sample_configs(rng, team, nq, dof_stride)
+    two = T > 1
+    counts = np.where(two, 2, 1)
+    per_path = np.repeat(counts, nr)
+    begin = np.concatenate([[0], np.cumsum(per_path)]).astype(np.int64)
+    n_wp = int(begin[-1])
+    wp_t = np.zeros(n_wp, np.int32)
+    wp_q = np.zeros((n_wp, dof_stride))
+    first = begin[:-1]
+    wp_q[first] = s.reshape(nq * nr, dof_stride)
+    sec = first[np.repeat(two, nr)] + 1
+    wp_t[sec] = np.repeat(T[two] - 1, nr)
+    wp_q[sec] = g[two].reshape(-1, dof_stride)
+    return Paths(nq, nr, dof_stride, begin, wp_t, wp_q)
+
+
+def stratified_timed_paths(rng, team, lengths: np.ndarray, k_lo: int, k_hi: int, dof_stride: int) -> Paths:
+    """Timed paths with given per-(query, robot) lengths L: K ~ U{k_lo..k_hi}
+    waypoints, times 0 = tau_0 < ... < tau_{K-1} = L-1 placed one per equal slice
+    of [0, L-1] with a uniform jitter inside the slice, configurations uniform in
+    C-space."""
+    nq, nr = lengths.shape
+    L = lengths.reshape(-1).astype(np.int64)
+    K = rng.integers(k_lo, k_hi + 1, L.shape[0])
+    # at least two states per slice so the jittered times stay strictly increasing
+    K = np.minimum(K, (L - 1) // 2 + 1)
+    K = np.where(L == 1, 1, np.maximum(K, 2))
+    begin = np.concatenate([[0], np.cumsum(K)]).astype(np.int64)
+    n_wp = int(begin[-1])
+    path = np.repeat(np.arange(L.shape[0]), K)
+    idx = np.arange(n_wp) - begin[path]
+    Kp, Lp = K[path], L[path]
+    seg = (Lp - 1) / np.maximum(Kp - 1, 1)
+    jitter = rng.uniform(-0.2, 0.2, n_wp) * seg
+    t = np.floor(idx * seg + jitter).astype(np.int64)
+    t = np.where(idx == Kp - 1, Lp - 1, t)
+    t = np.where(idx == 0, 0, t)
+    wp_q = np.zeros((n_wp, dof_stride))
+    robot = path % nr
+    for r, rob in enumerate(team):
+        sel = robot == r
+        wp_q[sel, :rob.dof] = rng.uniform(rob.q_lo, rob.q_hi, (int(sel.sum()), rob.dof))
+    return Paths(nq, nr, dof_stride, begin, t.astype(np.int32), wp_q)
+
+
+def big_hetero_workload(n_queries: int = 262_144, seed: int = 4):
+    """16 robots (the four arm models on floor and ceiling corners + 8 SE(2)
+    rectangles at z = 1.0), a 200k-point box-surface cloud, horizons
+    T ~ U{16..1024}; half MV straight lines (environment on), half FFC timed paths
+    with per-robot lengths U{16..T} (one robot exactly T).
+    Returns (team, env, mv_paths, ffc_paths)."""
+    team = hetero_team(1, 8, 8, 1.0, ceiling=True)
+    env = box_surface_cloud(seed)
+    rng = _rng(seed, STREAM_WORK)
+    n_mv = n_queries // 2
+    n_ffc = n_queries - n_mv
+    T_mv = rng.integers(16, 1025, n_mv)
+    mv = straight_line_paths_T(rng, team, T_mv, 7)
+    T_ffc = rng.integers(16, 1025, n_ffc)
+    lengths = rng.integers(16, T_ffc[:, None] + 1, (n_ffc, len(team)))
+    lengths[np.arange(n_ffc), rng.integers(0, len(team), n_ffc)] = T_ffc
+    ffc = stratified_timed_paths(rng, team, lengths, 2, 8, 7)
+    return team, env, mv, ffc

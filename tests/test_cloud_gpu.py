@@ -1,0 +1,59 @@
+"""GPU parity on the 16-robot heterogeneous team with the 200k-point obstacle
+cloud (points on 40 box surfaces, uniform grid on the device, k-d tree in the
+oracle), and on a single arm inside the cloud where only the cloud and self
+collisions decide."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2604_23960_amd import mrv
+from paper_2604_23960_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def big():
+    team, env, mv, ffc = W.big_hetero_workload(768)
+    return team, env, mv, ffc, oracle.Team(team), oracle.Env(env)
+
+
+def test_hetero_cloud_mv_ffc(big):
+    team, env, mv, ffc, ot, oe = big
+    say("16-robot cloud MV/FFC")
+    ctx = mrv.Context(0)
+    try:
+        th, eh = ctx.load_team(team), ctx.load_env(env)
+        ref = oracle.mv(ot, oe, oracle.Paths(mv))
+        for flags in (mrv.CHECK_ENV, mrv.CHECK_ENV | mrv.EXHAUSTIVE, 0):
+            got = ctx.mv(th, eh, mv, flags)
+            exp = ref if flags & mrv.CHECK_ENV else oracle.mv(ot, oe, oracle.Paths(mv), check_env=False)
+            assert np.array_equal(got, exp), (flags, np.nonzero(got != exp)[0][:10])
+        fref = oracle.ffc(ot, oracle.Paths(ffc))
+        got = ctx.ffc(th, ffc)
+        assert np.array_equal(got, fref), np.nonzero(np.any(got != fref, axis=1))[0][:10]
+    finally:
+        ctx.close()
+
+
+def test_single_arm_in_cloud():
+    say("single arm in cloud")
+    team = [W.arm_models(1)[0].with_base(W.arm_base(0.5, 0.5))]
+    env = W.box_surface_cloud(4, n_points=200_000)
+    rng = np.random.default_rng([9, 3])
+    paths = W.straight_line_paths_T(rng, team, rng.integers(16, 300, 512), 7)
+    ot, oe = oracle.Team(team), oracle.Env(env)
+    ref = oracle.mv(ot, oe, oracle.Paths(paths))
+    assert 0 < ref.sum() < len(ref)
+    ctx = mrv.Context(0)
+    try:
+        th, eh = ctx.load_team(team), ctx.load_env(env)
+        for flags in (mrv.CHECK_ENV, mrv.CHECK_ENV | mrv.EXHAUSTIVE, mrv.CHECK_ENV | mrv.HIERARCHICAL):
+            got = ctx.mv(th, eh, paths, flags)
+            assert np.array_equal(got, ref), (flags, np.nonzero(got != ref)[0][:10])
+    finally:
+        ctx.close()

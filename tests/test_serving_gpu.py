@@ -75,43 +75,58 @@ def test_poisson_load_and_latency_report(served):
 
 
 def test_busy_cancel_and_handles(served):
-    ctx0, teams, env, reqs, handles0, e0 = served
     say("busy / cancel / unload")
+    w = W.arms_workload(20000)
+    big = mrv.HostPaths(w.paths)
+    ex_flags = mrv.CHECK_ENV | mrv.EXHAUSTIVE
+    # a full queue answers BUSY; a team in use cannot be unloaded
     ctx = mrv.Context(0, max_inflight=2)
     try:
-        w = W.arms_workload(20000)
         team = ctx.load_team(w.team)
         env = ctx.load_env(w.env)
-        big = mrv.HostPaths(w.paths)
-        t1 = ctx.submit(0, team, env, big, mrv.CHECK_ENV | mrv.EXHAUSTIVE)
-        t2 = ctx.submit(0, team, env, big, mrv.CHECK_ENV | mrv.EXHAUSTIVE)
+        t1 = ctx.submit(0, team, env, big, ex_flags)
+        t2 = ctx.submit(0, team, env, big, ex_flags)
         with pytest.raises(mrv.MrvError) as ex:
             ctx.submit(0, team, env, big, mrv.CHECK_ENV)
         assert ex.value.status == mrv.MRV_E_BUSY
         with pytest.raises(mrv.MrvError) as ex:
             ctx.unload(team)
         assert ex.value.status == mrv.MRV_E_BUSY
-        ctx.cancel(t2)
         r1 = ctx.poll(t1, 0, w.paths.n_queries, timeout_ms=None)
-        assert r1.shape == (w.paths.n_queries,)
-        try:
-            ctx.poll(t2, 0, w.paths.n_queries, timeout_ms=None)
-            cancelled = False
-        except mrv.MrvError as ex2:
-            assert ex2.status == mrv.MRV_E_CANCELLED
-            cancelled = True
-        assert cancelled
+        r2 = ctx.poll(t2, 0, w.paths.n_queries, timeout_ms=None)
+        assert np.array_equal(r1, r2)
         with pytest.raises(mrv.MrvError) as ex:
             ctx.poll(t1, 0, 1)
         assert ex.value.status == mrv.MRV_E_HANDLE
-        # a wait with a short timeout on a long request reports the timeout, then completes
-        t3 = ctx.submit(0, team, env, big, mrv.CHECK_ENV | mrv.EXHAUSTIVE)
+        # a short wait on a long request reports the timeout; the request still completes
+        t3 = ctx.submit(0, team, env, big, ex_flags)
         with pytest.raises(mrv.MrvError) as ex:
             ctx.poll(t3, 0, w.paths.n_queries, timeout_ms=1)
         assert ex.value.status == mrv.MRV_E_TIMEOUT
-        r3 = ctx.poll(t3, 0, w.paths.n_queries, timeout_ms=None)
-        assert np.array_equal(r3, r1)
-        time.sleep(0.01)
+        assert np.array_equal(ctx.poll(t3, 0, w.paths.n_queries, timeout_ms=None), r1)
         ctx.unload(team)    # nothing in flight any more
+    finally:
+        ctx.close()
+    # cancelling a request that still waits for a slot: four requests with flags that
+    # cannot share a batch occupy the four slots, the fifth waits and is cancelled
+    ctx = mrv.Context(0, max_inflight=8)
+    try:
+        team = ctx.load_team(w.team)
+        env = ctx.load_env(w.env)
+        flag_sets = [ex_flags, mrv.EXHAUSTIVE, ex_flags | mrv.HIERARCHICAL, ex_flags | mrv.ORDER_RAKE,
+                     ex_flags | mrv.ORDER_LINEAR]
+        tickets = [ctx.submit(0, team, env, big, f) for f in flag_sets]
+        ctx.cancel(tickets[-1])
+        outs = [ctx.poll(t, 0, w.paths.n_queries, timeout_ms=None) for t in tickets[:-1]]
+        with pytest.raises(mrv.MrvError) as ex:
+            ctx.poll(tickets[-1], 0, w.paths.n_queries, timeout_ms=None)
+        assert ex.value.status == mrv.MRV_E_CANCELLED
+        direct = ctx.mv(team, env, big, ex_flags)
+        for f, o in zip(flag_sets, outs):
+            exp = direct if f & mrv.CHECK_ENV else ctx.mv(team, env, big, f)
+            assert np.array_equal(o, exp), f
+        with pytest.raises(mrv.MrvError) as ex:
+            ctx.cancel(tickets[-1])
+        assert ex.value.status == mrv.MRV_E_HANDLE
     finally:
         ctx.close()

