@@ -177,6 +177,15 @@ mrv_status mrv_ffc_device(mrv_ctx ctx, int32_t team, const mrv_paths* paths, uin
 /* Wait for the context stream; report device-side input errors since the last sync. */
 mrv_status mrv_sync(mrv_ctx ctx);
 
+/* FP32 world-frame sphere centres of the team at n_states (query, timestep)
+ * pairs of host paths, as the validation kernels compute them (paper §III-A,
+ * SpheresFK): out[k][s] = (x, y, z, radius) for sphere s of the flattened team
+ * (robots in order), k < n_states; out holds n_states * S * 4 floats, S = the
+ * team's total sphere count.  state_query[k] must index a query of paths and
+ * state_t[k] >= 0 (timesteps past a path's end give its last configuration). */
+mrv_status mrv_spheres(mrv_ctx ctx, int32_t team, const mrv_paths* paths, int32_t n_states,
+                       const int32_t* state_query, const int32_t* state_t, float* out);
+
 /* Timesteps for a straight-line motion dq: ceil(|dq| / step) with the L2
  * (metric 0) or L-infinity (metric 1) norm (paper §IV-A: bounded C-space motion
  * per timestep).  Returns -1 on invalid arguments. */

@@ -964,6 +964,65 @@ mrv_status mrv_last_stats(mrv_ctx ctx, mrv_stats* out)
     });
 }
 
+mrv_status mrv_spheres(mrv_ctx ctx, int32_t team, const mrv_paths* paths, int32_t n_states,
+                       const int32_t* state_query, const int32_t* state_t, float* out)
+{
+    if (guard(ctx)) return MRV_E_HANDLE;
+    return wrap([&] {
+        set_device(ctx);
+        TeamHost tm;
+        {
+            std::lock_guard<std::mutex> lk(ctx->handle_mu);
+            tm = find_team(ctx, team);
+        }
+        check_paths_host(tm, paths);
+        if (n_states < 0 || (n_states > 0 && (!state_query || !state_t || !out)))
+            throw Err{MRV_E_INVALID, "bad state arrays"};
+        for (int k = 0; k < n_states; ++k)
+            if (state_query[k] < 0 || state_query[k] >= paths->n_queries || state_t[k] < 0 || state_t[k] >= MRV_MAX_T)
+                throw Err{MRV_E_INVALID, "state " + std::to_string(k) + " out of range"};
+        if (n_states == 0) return;
+        const int n = tm.dev.n_robots, S = tm.dev.S;
+        const size_t nb = ((size_t)paths->n_queries * n + 1) * sizeof(long long);
+        const size_t ntb = (size_t)paths->n_wp * sizeof(int);
+        const size_t nqb = (size_t)paths->n_wp * (size_t)paths->dof_stride * sizeof(double);
+        const size_t nout = (size_t)n_states * S * 16;
+        ctx->in_begin.ensure(nb);
+        ctx->in_t.ensure(ntb);
+        ctx->in_q.ensure(nqb);
+        DevBuf st, o;
+        st.ensure((size_t)n_states * 8);
+        o.ensure(nout);
+        try {
+            HIPCHK(hipMemcpyAsync(ctx->in_begin.p, paths->wp_begin, nb, hipMemcpyHostToDevice, ctx->stream));
+            HIPCHK(hipMemcpyAsync(ctx->in_t.p, paths->wp_t, ntb, hipMemcpyHostToDevice, ctx->stream));
+            HIPCHK(hipMemcpyAsync(ctx->in_q.p, paths->wp_q, nqb, hipMemcpyHostToDevice, ctx->stream));
+            HIPCHK(hipMemcpyAsync(st.p, state_query, (size_t)n_states * 4, hipMemcpyHostToDevice, ctx->stream));
+            HIPCHK(hipMemcpyAsync((char*)st.p + (size_t)n_states * 4, state_t, (size_t)n_states * 4,
+                                  hipMemcpyHostToDevice, ctx->stream));
+            CallDev cd{};
+            cd.n_queries = paths->n_queries;
+            cd.dof_stride = paths->dof_stride;
+            cd.team0 = tm.d_dev;
+            cd.n_wp = paths->n_wp;
+            cd.wp_begin = (const long long*)ctx->in_begin.p;
+            cd.wp_t = (const int*)ctx->in_t.p;
+            cd.wp_q = (const double*)ctx->in_q.p;
+            HIPCHK(launch_spheres(cd, (const int*)st.p, (const int*)st.p + n_states, n_states, (float4*)o.p, S,
+                                  tm.dev.F, ctx->stream));
+            HIPCHK(hipMemcpyAsync(out, o.p, nout, hipMemcpyDeviceToHost, ctx->stream));
+            HIPCHK(hipStreamSynchronize(ctx->stream));
+        } catch (...) {
+            (void)hipStreamSynchronize(ctx->stream);
+            st.release();
+            o.release();
+            throw;
+        }
+        st.release();
+        o.release();
+    });
+}
+
 // ------------------------------------------------------------ autotuning
 
 mrv_status mrv_autotune(mrv_ctx ctx, int32_t team, int32_t env, int32_t kind, const mrv_paths* sample,

@@ -131,6 +131,8 @@ hipError_t launch_prepare(const CallDev& cd, hipStream_t stream);
 hipError_t launch_validate(const CallDev& cd, int grid, hipStream_t stream);
 hipError_t launch_finalize(const CallDev& cd, hipStream_t stream);
 hipError_t fill_u32(void* p, unsigned v, size_t n, hipStream_t stream);
+hipError_t launch_spheres(const CallDev& cd, const int* st_q, const int* st_t, int n_states, float4* out, int S,
+                          int F, hipStream_t stream);
 // Occupancy-derived workgroups per CU for the validation kernel.
 int validate_blocks_per_cu(int kind, size_t lds_bytes);
 

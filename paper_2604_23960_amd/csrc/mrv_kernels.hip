@@ -22,6 +22,7 @@
 // queued and re-evaluated in FP64 from the FP64 waypoints and model.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cfloat>
 #include <cmath>
 
@@ -512,6 +513,89 @@ __device__ __forceinline__ int classify(float d2, float R, float eps)
     return d2 < lo * lo ? 1 : 2;
 }
 
+// FP32 frames of robot r at timestep t: the configuration is interpolated in FP64
+// from path waypoints [pb, pe) and rounded once; the chain Frame_k =
+// Frame_{k-1} F_k J_k(q_k) then runs in FP32 registers.  out receives
+// (n_joints + 1) frames as 3 float4 rows (R row, p) each, the base first.
+__device__ __forceinline__ void robot_frames32(const TeamDev& tm, const CallDev& cd, long long pb, long long pe,
+                                               int r, int t, float4* out)
+{
+    const long long kseg = find_segment(cd.wp_t, pb, pe, t);
+    const bool last = (kseg == pe - 1);
+    double sfrac = 0.0;
+    if (!last) sfrac = (double)(t - cd.wp_t[kseg]) / (double)(cd.wp_t[kseg + 1] - cd.wp_t[kseg]);
+    const int nj = tm.r_nj[r];
+    float qv[kMaxJoints];
+#pragma unroll
+    for (int j = 0; j < kMaxJoints; ++j) {
+        qv[j] = 0.f;
+        if (j < nj) {
+            double qa = cd.wp_q[kseg * cd.dof_stride + j];
+            double qj = qa;
+            if (!last) qj = qa + sfrac * (cd.wp_q[(kseg + 1) * cd.dof_stride + j] - qa);
+            qv[j] = (float)qj;
+        }
+    }
+    float Mx[12];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) Mx[i] = tm.r_base32[r * 12 + i];
+    out[0] = make_float4(Mx[0], Mx[1], Mx[2], Mx[3]);
+    out[1] = make_float4(Mx[4], Mx[5], Mx[6], Mx[7]);
+    out[2] = make_float4(Mx[8], Mx[9], Mx[10], Mx[11]);
+    const int j0 = tm.r_joint_off[r];
+#pragma unroll
+    for (int j = 0; j < kMaxJoints; ++j) {
+        if (j < nj) {
+            const float* Fj = tm.j_fixed32 + (long long)(j0 + j) * 12;
+            float A[12];
+#pragma unroll
+            for (int row = 0; row < 3; ++row) {
+#pragma unroll
+                for (int col = 0; col < 4; ++col) {
+                    float v = Mx[row * 4 + 0] * Fj[col] + Mx[row * 4 + 1] * Fj[4 + col] + Mx[row * 4 + 2] * Fj[8 + col];
+                    A[row * 4 + col] = (col == 3) ? v + Mx[row * 4 + 3] : v;
+                }
+            }
+            const int jt = tm.j_type[j0 + j];
+            if (jt == MRV_REV_Z) {
+                float sn, cs;
+                sincosf(qv[j], &sn, &cs);
+#pragma unroll
+                for (int row = 0; row < 3; ++row) {
+                    const float a0 = A[row * 4 + 0], a1 = A[row * 4 + 1];
+                    Mx[row * 4 + 0] = a0 * cs + a1 * sn;
+                    Mx[row * 4 + 1] = a1 * cs - a0 * sn;
+                    Mx[row * 4 + 2] = A[row * 4 + 2];
+                    Mx[row * 4 + 3] = A[row * 4 + 3];
+                }
+            } else {
+                const int ax = jt - 1;
+#pragma unroll
+                for (int row = 0; row < 3; ++row) {
+                    const float axv = ax == 0 ? A[row * 4 + 0] : (ax == 1 ? A[row * 4 + 1] : A[row * 4 + 2]);
+                    Mx[row * 4 + 0] = A[row * 4 + 0];
+                    Mx[row * 4 + 1] = A[row * 4 + 1];
+                    Mx[row * 4 + 2] = A[row * 4 + 2];
+                    Mx[row * 4 + 3] = axv * qv[j] + A[row * 4 + 3];
+                }
+            }
+            float4* o = out + (j + 1) * 3;
+            o[0] = make_float4(Mx[0], Mx[1], Mx[2], Mx[3]);
+            o[1] = make_float4(Mx[4], Mx[5], Mx[6], Mx[7]);
+            o[2] = make_float4(Mx[8], Mx[9], Mx[10], Mx[11]);
+        }
+    }
+}
+
+// Sphere centre Frame c (radius passed through) from a frame's three rows.
+__device__ __forceinline__ float4 place32(const float4* Fp, float4 L)
+{
+    const float4 r0 = Fp[0], r1 = Fp[1], r2 = Fp[2];
+    return make_float4(fmaf(r0.x, L.x, fmaf(r0.y, L.y, fmaf(r0.z, L.z, r0.w))),
+                       fmaf(r1.x, L.x, fmaf(r1.y, L.y, fmaf(r1.z, L.z, r1.w))),
+                       fmaf(r2.x, L.x, fmaf(r2.y, L.y, fmaf(r2.z, L.z, r2.w))), L.w);
+}
+
 template <int KIND>
 __global__ __launch_bounds__(kWG) void k_validate(CallDev cd)
 {
@@ -630,77 +714,8 @@ __global__ __launch_bounds__(kWG) void k_validate(CallDev cd)
         for (int idx = tid; idx < nv * n; idx += kWG) {
             const int c = idx / n;
             const int r = idx - c * n;
-            const int t = s_t[c];
-            const long long pb = cd.wp_begin[qp0 + r];
-            const long long pe = cd.wp_begin[qp0 + r + 1];
-            const long long kseg = find_segment(cd.wp_t, pb, pe, t);
-            const bool last = (kseg == pe - 1);
-            double sfrac = 0.0;
-            if (!last) sfrac = (double)(t - cd.wp_t[kseg]) / (double)(cd.wp_t[kseg + 1] - cd.wp_t[kseg]);
-            const int nj = tm.r_nj[r];
-            float qv[kMaxJoints];
-#pragma unroll
-            for (int j = 0; j < kMaxJoints; ++j) {
-                qv[j] = 0.f;
-                if (j < nj) {
-                    double qa = cd.wp_q[kseg * cd.dof_stride + j];
-                    double qj = qa;
-                    if (!last) qj = qa + sfrac * (cd.wp_q[(kseg + 1) * cd.dof_stride + j] - qa);
-                    qv[j] = (float)qj;
-                }
-            }
-            float Mx[12];
-#pragma unroll
-            for (int i = 0; i < 12; ++i) Mx[i] = tm.r_base32[r * 12 + i];
-            const int f0 = tm.r_frame_off[r];
-            float4* out = fr + ((long long)c * F + f0) * 3;
-            out[0] = make_float4(Mx[0], Mx[1], Mx[2], Mx[3]);
-            out[1] = make_float4(Mx[4], Mx[5], Mx[6], Mx[7]);
-            out[2] = make_float4(Mx[8], Mx[9], Mx[10], Mx[11]);
-            const int j0 = tm.r_joint_off[r];
-#pragma unroll
-            for (int j = 0; j < kMaxJoints; ++j) {
-                if (j < nj) {
-                    const float* Fj = tm.j_fixed32 + (long long)(j0 + j) * 12;
-                    float A[12];
-#pragma unroll
-                    for (int row = 0; row < 3; ++row) {
-#pragma unroll
-                        for (int col = 0; col < 4; ++col) {
-                            float v = Mx[row * 4 + 0] * Fj[col] + Mx[row * 4 + 1] * Fj[4 + col] +
-                                      Mx[row * 4 + 2] * Fj[8 + col];
-                            A[row * 4 + col] = (col == 3) ? v + Mx[row * 4 + 3] : v;
-                        }
-                    }
-                    const int jt = tm.j_type[j0 + j];
-                    if (jt == MRV_REV_Z) {
-                        float sn, cs;
-                        sincosf(qv[j], &sn, &cs);
-#pragma unroll
-                        for (int row = 0; row < 3; ++row) {
-                            const float a0 = A[row * 4 + 0], a1 = A[row * 4 + 1];
-                            Mx[row * 4 + 0] = a0 * cs + a1 * sn;
-                            Mx[row * 4 + 1] = a1 * cs - a0 * sn;
-                            Mx[row * 4 + 2] = A[row * 4 + 2];
-                            Mx[row * 4 + 3] = A[row * 4 + 3];
-                        }
-                    } else {
-                        const int ax = jt - 1;
-#pragma unroll
-                        for (int row = 0; row < 3; ++row) {
-                            const float axv = ax == 0 ? A[row * 4 + 0] : (ax == 1 ? A[row * 4 + 1] : A[row * 4 + 2]);
-                            Mx[row * 4 + 0] = A[row * 4 + 0];
-                            Mx[row * 4 + 1] = A[row * 4 + 1];
-                            Mx[row * 4 + 2] = A[row * 4 + 2];
-                            Mx[row * 4 + 3] = axv * qv[j] + A[row * 4 + 3];
-                        }
-                    }
-                    float4* o = out + (j + 1) * 3;
-                    o[0] = make_float4(Mx[0], Mx[1], Mx[2], Mx[3]);
-                    o[1] = make_float4(Mx[4], Mx[5], Mx[6], Mx[7]);
-                    o[2] = make_float4(Mx[8], Mx[9], Mx[10], Mx[11]);
-                }
-            }
+            robot_frames32(tm, cd, cd.wp_begin[qp0 + r], cd.wp_begin[qp0 + r + 1], r, s_t[c],
+                           fr + ((long long)c * F + tm.r_frame_off[r]) * 3);
         }
         __syncthreads();
 
@@ -708,12 +723,7 @@ __global__ __launch_bounds__(kWG) void k_validate(CallDev cd)
         for (int idx = tid; idx < nv * S; idx += kWG) {
             const int c = idx / S;
             const int s = idx - c * S;
-            const float4 L = tm.s_local32[s];
-            const float4* Fp = fr + ((long long)c * F + tm.s_slot[s]) * 3;
-            const float4 r0 = Fp[0], r1 = Fp[1], r2 = Fp[2];
-            rec[idx] = make_float4(fmaf(r0.x, L.x, fmaf(r0.y, L.y, fmaf(r0.z, L.z, r0.w))),
-                                   fmaf(r1.x, L.x, fmaf(r1.y, L.y, fmaf(r1.z, L.z, r1.w))),
-                                   fmaf(r2.x, L.x, fmaf(r2.y, L.y, fmaf(r2.z, L.z, r2.w))), L.w);
+            rec[idx] = place32(fr + ((long long)c * F + tm.s_slot[s]) * 3, tm.s_local32[s]);
         }
         __syncthreads();
         // --- group centres: mean of the group's sphere centres
@@ -1003,6 +1013,25 @@ __global__ __launch_bounds__(kWG) void k_validate(CallDev cd)
     }
 }
 
+// FP32 sphere centres of requested (query, timestep) states, computed by the same
+// device code as the validation kernel.  One workgroup per state; LDS holds the
+// frames of one timestep.
+__global__ void k_spheres(CallDev cd, const int* st_q, const int* st_t, int n_states, float4* out, int S_out)
+{
+    extern __shared__ float4 frames[];
+    for (int k = blockIdx.x; k < n_states; k += gridDim.x) {
+        const int q = st_q[k];
+        const TeamDev& tm = *team_of(cd, q);
+        const long long p0 = path_of(cd, tm.n_robots, q);
+        for (int r = threadIdx.x; r < tm.n_robots; r += blockDim.x)
+            robot_frames32(tm, cd, cd.wp_begin[p0 + r], cd.wp_begin[p0 + r + 1], r, st_t[k], frames + tm.r_frame_off[r] * 3);
+        __syncthreads();
+        for (int s = threadIdx.x; s < tm.S; s += blockDim.x)
+            out[(long long)k * S_out + s] = place32(frames + tm.s_slot[s] * 3, tm.s_local32[s]);
+        __syncthreads();
+    }
+}
+
 // FP64 re-evaluation of the near-contact tests that did not fit a tile's queue.
 __global__ void k_recheck(CallDev cd)
 {
@@ -1061,6 +1090,15 @@ hipError_t launch_finalize(const CallDev& cd, hipStream_t stream)
     hipLaunchKernelGGL(k_recheck, dim3(256), dim3(256), 0, stream, cd);
     const unsigned blocks = (unsigned)((cd.n_queries + 255) / 256);
     hipLaunchKernelGGL(k_finalize, dim3(blocks), dim3(256), 0, stream, cd);
+    return hipGetLastError();
+}
+
+hipError_t launch_spheres(const CallDev& cd, const int* st_q, const int* st_t, int n_states, float4* out, int S,
+                          int F, hipStream_t stream)
+{
+    if (n_states <= 0) return hipSuccess;
+    const unsigned blocks = (unsigned)std::min(n_states, 4096);
+    hipLaunchKernelGGL(k_spheres, dim3(blocks), dim3(64), (size_t)F * 48, stream, cd, st_q, st_t, n_states, out, S);
     return hipGetLastError();
 }
 

@@ -26,7 +26,8 @@ MAX_T = 1 << 20
 EXPORTS = ["mrv_create", "mrv_destroy", "mrv_last_error", "mrv_load_team", "mrv_load_env", "mrv_unload",
            "mrv_mv", "mrv_ffc", "mrv_mv_device", "mrv_ffc_device", "mrv_sync", "mrv_motion_steps",
            "mrv_set_tiling", "mrv_get_tiling", "mrv_last_stats", "mrv_submit", "mrv_poll", "mrv_wait",
-           "mrv_cancel", "mrv_autotune", "mrv_graph_create", "mrv_graph_launch", "mrv_graph_destroy"]
+           "mrv_cancel", "mrv_autotune", "mrv_graph_create", "mrv_graph_launch", "mrv_graph_destroy",
+           "mrv_spheres"]
 
 
 class MrvError(RuntimeError):
@@ -116,6 +117,7 @@ def lib():
                 "mrv_graph_create": [P, I32, I32, I32, C.POINTER(PathsDesc), U32, P, C.POINTER(C.c_void_p)],
                 "mrv_graph_launch": [P, P],
                 "mrv_graph_destroy": [P, P],
+                "mrv_spheres": [P, I32, C.POINTER(PathsDesc), I32, P, P, P],
             }
             for name, args in sig.items():
                 f = getattr(L, name)
@@ -263,6 +265,16 @@ class Context:
 
     def sync(self):
         check(lib().mrv_sync(self.h))
+
+    def spheres(self, team: int, paths, state_query, state_t, total_spheres: int) -> np.ndarray:
+        """FP32 world sphere centres/radii [n_states, S, 4] as the kernels compute them."""
+        hp = paths if isinstance(paths, HostPaths) else HostPaths(paths)
+        sq = _c(state_query, np.int32)
+        st = _c(state_t, np.int32)
+        out = np.zeros((max(len(sq), 1), total_spheres, 4), np.float32)
+        check(lib().mrv_spheres(self.h, team, C.byref(hp.desc), len(sq), sq.ctypes.data, st.ctypes.data,
+                                out.ctypes.data))
+        return out[:len(sq)]
 
     # -- tuning / stats
     def set_tiling(self, team: int, kind: int, chunk: int = 0, wg_per_cu: int = 0):
