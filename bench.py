@@ -123,6 +123,76 @@ def serving_bench(log, n_requests=3000, n_plain=400):
                 served_over_plain_throughput=served_sat["qps"] / plain_sat["qps"])
 
 
+def cloud_bench(log, n_queries=262_144, tune_sample=2048, exhaustive_queries=8192):
+    """16-robot team in a 200k-point cloud: early-exit MV and FFC over the whole
+    batch, exhaustive MV on a slice, default vs autotuned tiling, and one-launch
+    graph replay vs the plain multi-kernel launch for small batches."""
+    import torch
+    from paper_2604_23960_amd import mrv
+    from paper_2604_23960_amd import workloads as W
+    team, env, mvp, ffcp = W.big_hetero_workload(n_queries)
+    ctx = mrv.Context(0)
+    th, eh = ctx.load_team(team), ctx.load_env(env)
+    res = dict(queries=n_queries, robots=len(team), spheres=sum(r.n_spheres for r in team),
+               points=len(env.points))
+    dmv, dffc = mrv.DevicePaths(mvp), mrv.DevicePaths(ffcp)
+    o_mv = torch.zeros(mvp.n_queries, dtype=torch.uint8, device="cuda")
+    o_ffc = torch.zeros((ffcp.n_queries, 3), dtype=torch.int32, device="cuda")
+    sub = mvp.subset(np.arange(exhaustive_queries))
+    dsub = mrv.DevicePaths(sub)
+    o_sub = torch.zeros(sub.n_queries, dtype=torch.uint8, device="cuda")
+
+    def measure(tag):
+        out = {}
+        w1, _, s1 = run_device(ctx, th, eh, dmv, 0, mrv.CHECK_ENV, o_mv, 3, 1)
+        out["mv_early_exit"] = dict(ms_per_call=w1 / 3 * 1e3, covered_states_per_s=s1["states_covered"] * 3 / w1)
+        w2, _, s2 = run_device(ctx, th, -1, dffc, 1, 0, o_ffc, 3, 1)
+        out["ffc"] = dict(ms_per_call=w2 / 3 * 1e3, covered_states_per_s=s2["states_covered"] * 3 / w2,
+                          evaluated_states_per_s=s2["states_evaluated"] * 3 / w2)
+        w3, k3, s3 = run_device(ctx, th, eh, dsub, 0, mrv.CHECK_ENV | mrv.EXHAUSTIVE, o_sub, 2, 1)
+        out["mv_exhaustive_slice"] = dict(queries=sub.n_queries, ms_per_call=w3 / 2 * 1e3,
+                                          kernel_ms=float(np.mean(k3)),
+                                          states_per_s=s3["states_evaluated"] * 2 / w3)
+        out["tiling"] = dict(mv=ctx.get_tiling(th, 0), ffc=ctx.get_tiling(th, 1))
+        log(f"cloud {tag}: {out['mv_exhaustive_slice']['states_per_s']:.3g} states/s exhaustive")
+        return out
+
+    res["default_tiling"] = measure("default")
+    t0 = time.perf_counter()
+    ctx.autotune(th, eh, 0, sub.subset(np.arange(tune_sample)), mrv.CHECK_ENV | mrv.EXHAUSTIVE)
+    ctx.autotune(th, -1, 1, ffcp.subset(np.arange(tune_sample)), 0)
+    res["autotune_seconds"] = time.perf_counter() - t0
+    res["autotuned"] = measure("autotuned")
+    # graph replay vs plain launch on small batches
+    lat = {}
+    for nq in (16, 256):
+        small = mvp.subset(np.arange(nq))
+        ds = mrv.DevicePaths(small)
+        o = torch.zeros(nq, dtype=torch.uint8, device="cuda")
+        g = ctx.graph_create(th, eh, 0, ds, mrv.CHECK_ENV, o.data_ptr())
+        plain, graph = [], []
+        for _ in range(5):
+            ctx.mv_device(th, eh, ds, mrv.CHECK_ENV, o.data_ptr())
+            ctx.graph_launch(g)
+        ctx.sync()
+        for _ in range(50):
+            t1 = time.perf_counter()
+            ctx.mv_device(th, eh, ds, mrv.CHECK_ENV, o.data_ptr())
+            ctx.sync()
+            plain.append(time.perf_counter() - t1)
+            t1 = time.perf_counter()
+            ctx.graph_launch(g)
+            ctx.sync()
+            graph.append(time.perf_counter() - t1)
+        ctx.graph_destroy(g)
+        lat[str(nq)] = dict(plain_p50_ms=float(np.median(plain) * 1e3), graph_p50_ms=float(np.median(graph) * 1e3),
+                            plain_p99_ms=float(np.percentile(plain, 99) * 1e3),
+                            graph_p99_ms=float(np.percentile(graph, 99) * 1e3))
+    res["graph_vs_plain_launch"] = lat
+    ctx.close()
+    return res
+
+
 def cpu_baseline(w, max_queries):
     import oracle
     n = w.paths.n_queries
@@ -217,6 +287,8 @@ def main():
                                               states_per_s=st4["states_evaluated"] * 3 / wall4)
         log("serving loop vs plain launches")
         extra["serving"] = serving_bench(log)
+        log("16-robot point-cloud workload")
+        extra["cloud"] = cloud_bench(log)
     cpu = None
     if not args.no_cpu:
         log("timing the FP64 oracle on the host")

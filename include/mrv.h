@@ -72,6 +72,9 @@ typedef struct {
     double near_eps;       /* near-contact band in metres; <= 0 selects 1e-5 */
     int32_t max_inflight;  /* serving: queue capacity in requests; <= 0 selects 1024 */
     size_t serve_bytes;    /* serving: device bytes for admitted requests; 0 selects 256 MiB */
+    int64_t recheck_records; /* initial length of the near-contact re-evaluation queue in
+                              * 16-byte records; <= 0 selects 2^21.  Calls that overflow it
+                              * enlarge it, up to 2^27 (see mrv_mv, mrv_sync). */
     uint32_t flags;        /* reserved, must be 0 */
 } mrv_ctx_opts;
 
@@ -155,6 +158,14 @@ enum {
     MRV_ORDER_LINEAR = 16    /* MV tile order: consecutive timesteps (FFC always uses this) */
 };
 
+/* Near contact.  A test whose FP32 clearance lies within near_eps of zero is
+ * queued and re-evaluated in FP64.  A queued test whose outcome can no longer
+ * change the answer (MV: the query already collides; FFC: a conflict at an
+ * earlier or equal (t, i, j) is known) is dropped.  When the queue overflows,
+ * queries whose answer might still depend on a dropped test are unresolved:
+ * the synchronous calls enlarge the queue and run again; device calls report
+ * them as valid_out = 3 / t = -3 and through mrv_sync. */
+
 /* MV over host arrays; synchronous.  valid_out[q] = 1 valid, 0 invalid.
  * env = -1 runs without obstacles (self checks still run with MRV_CHECK_ENV). */
 mrv_status mrv_mv(mrv_ctx ctx, int32_t team, int32_t env, const mrv_paths* paths, uint32_t flags,
@@ -174,7 +185,10 @@ mrv_status mrv_mv_device(mrv_ctx ctx, int32_t team, int32_t env, const mrv_paths
                          uint32_t flags, uint8_t* valid_out);
 mrv_status mrv_ffc_device(mrv_ctx ctx, int32_t team, const mrv_paths* paths, uint32_t flags,
                           mrv_conflict* out);
-/* Wait for the context stream; report device-side input errors since the last sync. */
+/* Wait for the context stream; report device-side input errors since the last
+ * sync (MRV_E_INVALID), then unresolved queries (MRV_E_NOMEM; the queue is then
+ * enlarged to what the largest of those calls needed, so repeating them
+ * succeeds). */
 mrv_status mrv_sync(mrv_ctx ctx);
 
 /* FP32 world-frame sphere centres of the team at n_states (query, timestep)
@@ -217,6 +231,9 @@ mrv_status mrv_autotune(mrv_ctx ctx, int32_t team, int32_t env, int32_t kind, co
  * replays it on the context stream with one launch.  The graph reads the path
  * arrays and writes the output at replay time, so the caller may refill the same
  * buffers (same n_queries, no more than n_wp waypoints) between replays.
+ * The graph's near-contact queue keeps its size (the context's at creation):
+ * a replay that overflows it leaves valid_out = 3 / t = -3 for the queries
+ * concerned and reports nothing else.
  * Replays of one graph must not overlap each other.  Destroy graphs before their
  * context; a graph keeps its team and environment loaded until it is destroyed. */
 typedef struct mrv_graph_s* mrv_graph;

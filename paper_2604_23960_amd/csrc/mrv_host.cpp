@@ -97,6 +97,7 @@ struct mrv_ctx_s {
     std::unique_ptr<ServeLoop> serve;
     int max_inflight = 1024;
     size_t serve_bytes = 256u << 20;
+    size_t recheck_records = mrv::Scratch::kGlobalRecheckCap;
 };
 
 struct mrv_graph_s {
@@ -502,7 +503,7 @@ void ensure_scratch(Scratch& sc, size_t bins, size_t queries)
         HIPCHK(hipEventCreate(&sc.ev0));
         HIPCHK(hipEventCreate(&sc.ev1));
     }
-    sc.gq.ensure((size_t)Scratch::kGlobalRecheckCap * 16);
+    sc.gq.ensure(sc.gq_records * 16);
     if (bins > sc.bins) {
         sc.hist.release();
         sc.start.release();
@@ -520,7 +521,20 @@ void ensure_scratch(Scratch& sc, size_t bins, size_t queries)
     sc.q_chunk.ensure(Q * 4);
     sc.q_status.ensure(Q * 4);
     sc.q_word.ensure(Q * 4);
+    sc.q_drop.ensure(Q * 4);
     sc.q_sorted.ensure(Q * 4);
+}
+
+bool grow_recheck(Scratch& sc, size_t pushed)
+{
+    if (pushed <= sc.gq_records) return false;
+    size_t want = sc.gq_records;
+    while (want < pushed + pushed / 4) want <<= 1;
+    if (want > Scratch::kMaxRecheckCap) return false;
+    sc.gq.release();
+    sc.gq_records = want;
+    sc.gq.ensure(want * 16);
+    return true;
 }
 }  // namespace mrv
 
@@ -556,13 +570,14 @@ void run_plan(mrv_ctx ctx, Scratch& sc, const CallPlan& pl, void* out_dev, hipSt
     cd.q_chunk = (int*)sc.q_chunk.p;
     cd.status = (int*)sc.q_status.p;
     cd.word = (unsigned*)sc.q_word.p;
+    cd.drop = (unsigned*)sc.q_drop.p;
     cd.sorted_q = (int*)sc.q_sorted.p;
     cd.hist = (int*)sc.hist.p;
     cd.start = (int*)sc.start.p;
     cd.off = (int*)sc.off.p;
     cd.ctrl = (int*)sc.ctrl.p;
     cd.gq = (int4*)sc.gq.p;
-    cd.gq_cap = Scratch::kGlobalRecheckCap;
+    cd.gq_cap = (int)sc.gq_records;
     cd.stats = (unsigned long long*)((char*)sc.ctrl.p + 64);
     cd.valid_out = kind == 0 ? (unsigned char*)out_dev : nullptr;
     cd.conflict_out = kind == 1 ? (int*)out_dev : nullptr;
@@ -643,13 +658,23 @@ void host_call(mrv_ctx ctx, int team, int env, int kind, const mrv_paths* p, uin
     HIPCHK(hipMemcpyAsync(ctx->in_q.p, p->wp_q, nq, hipMemcpyHostToDevice, ctx->stream));
     DevPaths dp{(const long long*)ctx->in_begin.p, (const int*)ctx->in_t.p, (const double*)ctx->in_q.p,
                 p->n_wp, p->n_queries, p->dof_stride};
-    run_plan(ctx, ctx->sc, single_plan(tm, ev, kind, flags, dp, max_horizon(p, n)), ctx->out_buf.p, ctx->stream);
-    int unresolved = 0;
-    HIPCHK(hipMemcpyAsync(&unresolved, (int*)ctx->sc.ctrl.p + 1, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
-    if (unresolved)
-        throw Err{MRV_E_NOMEM, std::to_string(unresolved) +
-                                   " queries exceeded the near-contact re-evaluation queue; split the batch"};
+    const CallPlan pl = single_plan(tm, ev, kind, flags, dp, max_horizon(p, n));
+    // a call whose near tests overflow the queue runs again with a queue that fits
+    for (int attempt = 0;; ++attempt) {
+        run_plan(ctx, ctx->sc, pl, ctx->out_buf.p, ctx->stream);
+        int cnt[2] = {0, 0};   // unresolved queries, near tests pushed
+        HIPCHK(hipMemcpyAsync(cnt, (int*)ctx->sc.ctrl.p + 1, sizeof(cnt), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        if (!cnt[0]) break;
+        // this call's own overflow is handled here, not by the next mrv_sync
+        int since = 0;
+        HIPCHK(hipMemcpy(&since, (int*)ctx->sc.ctrl.p + 9, sizeof(int), hipMemcpyDeviceToHost));
+        since -= cnt[0];
+        HIPCHK(hipMemcpy((int*)ctx->sc.ctrl.p + 9, &since, sizeof(int), hipMemcpyHostToDevice));
+        if (attempt >= 2 || !grow_recheck(ctx->sc, (unsigned)cnt[1]))
+            throw Err{MRV_E_NOMEM, std::to_string(cnt[0]) +
+                                       " queries exceeded the near-contact re-evaluation queue; split the batch"};
+    }
     HIPCHK(hipMemcpyAsync(out_host, ctx->out_buf.p, nout, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
 }
@@ -739,6 +764,12 @@ mrv_status mrv_create(const mrv_ctx_opts* opts, mrv_ctx* out)
         if (!(c->eps < 1e-2)) throw Err{MRV_E_INVALID, "near_eps must be < 0.01 m"};
         if (opts && opts->max_inflight > 0) c->max_inflight = opts->max_inflight;
         if (opts && opts->serve_bytes > 0) c->serve_bytes = opts->serve_bytes;
+        if (opts && opts->recheck_records > 0) {
+            if ((uint64_t)opts->recheck_records > Scratch::kMaxRecheckCap)
+                throw Err{MRV_E_INVALID, "recheck_records above 2^27"};
+            c->recheck_records = (size_t)opts->recheck_records;
+        }
+        c->sc.gq_records = c->recheck_records;
         if (opts && opts->stream) {
             c->stream = (hipStream_t)opts->stream;
         } else {
@@ -867,21 +898,27 @@ mrv_status mrv_sync(mrv_ctx ctx)
 {
     if (guard(ctx)) return MRV_E_HANDLE;
     int bad = 0, unresolved = 0;
+    bool grown = false;
     mrv_status st = wrap([&] {
         set_device(ctx);
         HIPCHK(hipStreamSynchronize(ctx->stream));
-        HIPCHK(hipMemcpy(&unresolved, (int*)ctx->sc.ctrl.p + 1, sizeof(int), hipMemcpyDeviceToHost));
-        HIPCHK(hipMemcpy(&bad, (int*)ctx->sc.ctrl.p + 3, sizeof(int), hipMemcpyDeviceToHost));
-        if (bad) {
-            const int zero = 0;
-            HIPCHK(hipMemcpy((int*)ctx->sc.ctrl.p + 3, &zero, sizeof(int), hipMemcpyHostToDevice));
-        }
+        int* c = (int*)ctx->sc.ctrl.p;
+        int most = 0;
+        HIPCHK(hipMemcpy(&bad, c + 3, sizeof(int), hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(&most, c + 8, sizeof(int), hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(&unresolved, c + 9, sizeof(int), hipMemcpyDeviceToHost));
+        const int zero[2] = {0, 0};
+        HIPCHK(hipMemcpy(c + 3, zero, sizeof(int), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(c + 8, zero, 2 * sizeof(int), hipMemcpyHostToDevice));
+        // size the queue for the largest call seen, so that repeating it succeeds
+        if (unresolved) grown = grow_recheck(ctx->sc, (unsigned)most);
     });
     if (st != MRV_OK) return st;
     if (bad) return fail(MRV_E_INVALID, std::to_string(bad) + " queries had malformed path data");
     if (unresolved)
         return fail(MRV_E_NOMEM, std::to_string(unresolved) +
-                                     " queries exceeded the near-contact re-evaluation queue (results 3 / t = -3)");
+                                     " queries exceeded the near-contact re-evaluation queue (results 3 / t = -3)" +
+                                     (grown ? "; the queue has been enlarged, repeat the calls" : ""));
     return MRV_OK;
 }
 
@@ -1141,6 +1178,7 @@ mrv_status mrv_graph_create(mrv_ctx ctx, int32_t team, int32_t env, int32_t kind
                     paths->dof_stride};
         CallPlan pl = single_plan(tm, ev, kind, f, dp, MRV_MAX_T);
         // every buffer exists before capture: nothing is allocated inside the graph
+        g->sc.gq_records = ctx->sc.gq_records;
         ensure_scratch(g->sc, (size_t)MRV_MAX_T + 2, (size_t)paths->n_queries);
         HIPCHK(hipStreamSynchronize(ctx->stream));
         HIPCHK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
@@ -1210,7 +1248,8 @@ mrv_status mrv_submit(mrv_ctx ctx, const mrv_request* req, uint64_t* ticket)
     if (guard(ctx)) return MRV_E_HANDLE;
     if (!req || !ticket) return fail(MRV_E_INVALID, "null argument");
     return wrap([&] {
-        if (!ctx->serve) ctx->serve.reset(new ServeLoop(ctx, ctx->device, ctx->max_inflight, ctx->serve_bytes));
+        if (!ctx->serve) ctx->serve.reset(new ServeLoop(ctx, ctx->device, ctx->max_inflight, ctx->serve_bytes,
+                                                          ctx->recheck_records));
         // validate against the resident handles, resolve their device descriptors, then copy
         ServeRefs refs{};
         {

@@ -110,14 +110,17 @@ struct CallDev {
     int* q_chunk;               // timesteps per tile chosen for each query
     int* status;                // 0 ok, 1 invalid input
     unsigned* word;             // MV: hit flag; FFC: best key t*P + pair
+    unsigned* drop;             // smallest key (MV: 0) of a near test the full queue dropped
     int* sorted_q;
     // tile enumeration scratch (sized for MRV_MAX_T / 1 + 2 bins)
     int* hist;
     int* start;
     int* off;
-    int* ctrl;                  // [0] max nt, [1] unresolved queries, [2] global recheck count,
-                                // [3] invalid-input queries (kept until read), then u64 total tiles, u64 next tile
-    int4* gq;                   // global recheck queue, 2 int4 per record
+    int* ctrl;                  // [0] max nt, [1] unresolved queries, [2] near tests pushed,
+                                // [3] invalid-input queries (kept until read), [4..7] u64 total tiles,
+                                // u64 next tile, [8] most near tests pushed by a call and [9] unresolved
+                                // queries, both kept until read
+    int4* gq;                   // global recheck queue, one int4 per record
     int gq_cap;
     unsigned long long* stats;  // [ST_COUNT]
     // outputs

@@ -268,7 +268,7 @@ __device__ int golden_step(int nt)
 __global__ void k_reset(CallDev cd)
 {
     int i = threadIdx.x;
-    if (i < 4) cd.ctrl[i] = (i == 3) ? cd.ctrl[3] : 0;
+    if (i < 3) cd.ctrl[i] = 0;
     if (i < ST_COUNT) cd.stats[i] = 0ull;
     if (i == 0) {
         // tile counter and total live in 64-bit words after ctrl[0..3]
@@ -317,6 +317,7 @@ __global__ void k_query_info(CallDev cd)
     cd.q_chunk[q] = chunk;
     cd.status[q] = ok ? 0 : 1;
     cd.word[q] = cd.kind == 1 ? 0xFFFFFFFFu : 0u;
+    cd.drop[q] = 0xFFFFFFFFu;
     if (!ok) {
         atomicAdd(&cd.ctrl[3], 1);
     } else {
@@ -399,17 +400,24 @@ __global__ void k_finalize(CallDev cd)
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= cd.n_queries) return;
     const TeamDev& tm = *team_of(cd, q);
-    const int st = cd.status[q];
-    const bool bad = st != 0;
+    if (q == 0) atomicMax(&cd.ctrl[8], cd.ctrl[2]);
+    const bool bad = cd.status[q] != 0;
     const unsigned w = cd.word[q];
-    if (st == 2) atomicAdd(&cd.ctrl[1], 1);
+    const unsigned dk = cd.drop[q];
+    // a dropped near test matters only if it could still change the answer:
+    // MV while no hit is known, FFC when its key is below the best conflict
+    const bool unresolved = !bad && (cd.kind == 0 ? (dk != 0xFFFFFFFFu && w == 0u) : dk < w);
+    if (unresolved) {
+        atomicAdd(&cd.ctrl[1], 1);
+        atomicAdd(&cd.ctrl[9], 1);
+    }
     if (cd.kind == 0) {
-        cd.valid_out[q] = bad ? (st == 2 ? 3 : 2) : (w == 0u ? 1 : 0);
+        cd.valid_out[q] = bad ? 2 : unresolved ? 3 : (w == 0u ? 1 : 0);
         return;
     }
     int t = -1, ri = -1, rj = -1;
-    if (bad) {
-        t = ri = rj = (st == 2 ? -3 : -2);
+    if (bad || unresolved) {
+        t = ri = rj = (bad ? -2 : -3);
     } else if (w != 0xFFFFFFFFu) {
         const int n = tm.n_robots;
         const unsigned P = (unsigned)tm.P;
@@ -435,13 +443,14 @@ __global__ void k_fill_u32(unsigned* p, unsigned v, size_t n)
 // validation
 
 // Queue a near-contact test for FP64 re-evaluation by k_recheck, which runs after
-// the validation kernel; when the call's queue is full the query is marked
-// unresolved (status 2) and the call reports the overflow.
-__device__ __forceinline__ void push_recheck(const CallDev& cd, int q, int t, int kind, int a, int b)
+// the validation kernel.  key orders the test's possible outcome (MV: 0, FFC:
+// t*P + pair); when the call's queue is full the smallest dropped key is kept
+// per query and k_finalize decides whether the drop leaves the answer open.
+__device__ __forceinline__ void push_recheck(const CallDev& cd, int q, int t, int kind, int a, int b, unsigned key)
 {
     const unsigned g = atomicAdd(reinterpret_cast<unsigned*>(cd.ctrl + 2), 1u);
     if (g < (unsigned)cd.gq_cap) cd.gq[g] = make_int4(q, t | (kind << 24), a, b);
-    else atomicMax(cd.status + q, 2);
+    else atomicMin(cd.drop + q, key);
 }
 
 // One robot-robot rotation step: lane L tests its sphere (a-side, scaled by -2 and
@@ -630,6 +639,7 @@ __global__ __launch_bounds__(kWG) void k_validate(CallDev cd)
         if (tid == 0) {
             const long long g = (long long)atomicAdd(&w64[1], 1ull);
             int q = -1, nv = 0, phase = 0, C = 1;
+            unsigned known = KIND == 1 ? 0xFFFFFFFFu : 0u;
             if (g < gtotal) {
                 long long gg = g;
                 if (hier) {
@@ -675,17 +685,19 @@ __global__ __launch_bounds__(kWG) void k_validate(CallDev cd)
                     const long long t = (long long)base + (long long)c * stride;
                     if (t < T) { s_t[c] = (int)t; nv = c + 1; }
                 }
+                // the outcome known so far: skips the tile (early exit, pruning) or,
+                // in exhaustive mode, only the queueing of near tests it decides
+                known = load_word(cd.word + q);
                 bool skip = false;
                 if (!exhaustive) {
-                    const unsigned w = load_word(cd.word + q);
-                    if (KIND == 0) skip = (w != 0u);
-                    else skip = (w != 0xFFFFFFFFu) && (w < (unsigned)base * (unsigned)tq->P);
+                    if (KIND == 0) skip = (known != 0u);
+                    else skip = (known != 0xFFFFFFFFu) && (known < (unsigned)base * (unsigned)tq->P);
                 }
                 if (skip) { nv = 0; ++n_skip; }
                 else { ++n_run; n_states += (unsigned long long)nv * tq->n_robots; }
             }
             s_q = q; s_phase = phase; s_nv = nv; s_chunk = C;
-            s_hit = 0; s_key = 0xFFFFFFFFu; s_rho2 = 0u;
+            s_hit = KIND == 0 && known != 0u; s_key = KIND == 1 ? known : 0xFFFFFFFFu; s_rho2 = 0u;
         }
         __syncthreads();
         const int q = s_q;
@@ -849,7 +861,8 @@ __global__ __launch_bounds__(kWG) void k_validate(CallDev cd)
                                         const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
                                         if (d2 <= phi2) {
                                             if (d2 < plo2) hit = true;
-                                            else push_recheck(cd, q, s_t[c], RK_ENV_PT, a, p);
+                                            else if (!hit && !*(volatile int*)&s_hit)
+                                                push_recheck(cd, q, s_t[c], RK_ENV_PT, a, p, 0u);
                                         }
                                     }
                                 }
@@ -866,19 +879,22 @@ __global__ __launch_bounds__(kWG) void k_validate(CallDev cd)
                         for (int o = 0; o < env.n_box; ++o) {
                             const float v = box_val(x, y, z, env.box32 + o * 16);
                             if (v < rlo * rlo) hit = true;
-                            else if (v <= rhi * rhi) push_recheck(cd, q, s_t[c], RK_ENV_BOX, a, o);
+                            else if (v <= rhi * rhi && !hit && !*(volatile int*)&s_hit)
+                                push_recheck(cd, q, s_t[c], RK_ENV_BOX, a, o, 0u);
                         }
                         for (int o = 0; o < env.n_cyl; ++o) {
                             const float v = cyl_val(x, y, z, env.cyl32 + o * 8);
                             if (v < rlo * rlo) hit = true;
-                            else if (v <= rhi * rhi) push_recheck(cd, q, s_t[c], RK_ENV_CYL, a, o);
+                            else if (v <= rhi * rhi && !hit && !*(volatile int*)&s_hit)
+                                push_recheck(cd, q, s_t[c], RK_ENV_CYL, a, o, 0u);
                         }
                         for (int o = 0; o < env.n_sph; ++o) {
                             const float4 Ob = env.sph32[o];
                             const float dx = x - Ob.x, dy = y - Ob.y, dz = z - Ob.z;
                             const int cl = classify(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), rad + Ob.w, eps);
                             if (cl == 1) hit = true;
-                            else if (cl == 2) push_recheck(cd, q, s_t[c], RK_ENV_SPH, a, o);
+                            else if (cl == 2 && !hit && !*(volatile int*)&s_hit)
+                                push_recheck(cd, q, s_t[c], RK_ENV_SPH, a, o, 0u);
                         }
                     }
                 }
@@ -903,7 +919,8 @@ __global__ __launch_bounds__(kWG) void k_validate(CallDev cd)
                         const float dz = (A.z - B.z) + (OA.z - OB.z);
                         const int cl = classify(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), A.w + B.w, eps);
                         if (cl == 1) hit = true;
-                        else if (cl == 2) push_recheck(cd, q, s_t[c], RK_SELF, pr.x, pr.y);
+                        else if (cl == 2 && !hit && !*(volatile int*)&s_hit)
+                            push_recheck(cd, q, s_t[c], RK_SELF, pr.x, pr.y, 0u);
                     }
                 }
                 c_self += (unsigned long long)__popcll(__ballot(p < tm.n_self)) * (unsigned long long)nv;
@@ -974,8 +991,17 @@ __global__ __launch_bounds__(kWG) void k_validate(CallDev cd)
                             const float4 O = gc[c * G + tm.s_group[b]];
                             const float dx = XA0 - (Br.x + O.x), dy = XA1 - (Br.y + O.y), dz = XA2 - (Br.z + O.z);
                             const int cl = classify(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), ra + Br.w, eps);
-                            if (cl == 1) hit = true;
-                            else if (cl == 2) push_recheck(cd, q, s_t[c], RK_RR, a, b);
+                            if (cl == 1) {
+                                hit = true;
+                            } else if (cl == 2) {
+                                // a near test matters only below the best known outcome
+                                const unsigned key = KIND == 0 ? 0u
+                                                   : (unsigned)s_t[c] * (unsigned)tm.P +
+                                                         pair_index(tm.s_robot[a], rb, n);
+                                const bool open = KIND == 0 ? !*(volatile int*)&s_hit
+                                                            : key < *(volatile unsigned*)&s_key;
+                                if (open) push_recheck(cd, q, s_t[c], RK_RR, a, b, key);
+                            }
                         }
                     }
                 }
@@ -1032,7 +1058,8 @@ __global__ void k_spheres(CallDev cd, const int* st_q, const int* st_t, int n_st
     }
 }
 
-// FP64 re-evaluation of the near-contact tests that did not fit a tile's queue.
+// FP64 re-evaluation of the near-contact tests the validation kernel queued; a
+// record whose outcome the answer no longer depends on is skipped.
 __global__ void k_recheck(CallDev cd)
 {
     const EnvDev none{};
@@ -1043,9 +1070,13 @@ __global__ void k_recheck(CallDev cd)
         const int q = r0.x, t = r0.y & 0xffffff, kind = r0.y >> 24, a = r0.z, b = r0.w;
         const TeamDev& tm = *team_of(cd, q);
         const EnvDev* ep = env_of(cd, q);
+        const unsigned key = cd.kind == 0 ? 0u
+                           : (unsigned)t * (unsigned)tm.P + pair_index(tm.s_robot[a], tm.s_robot[b], tm.n_robots);
+        const unsigned w = load_word(cd.word + q);
+        if (cd.kind == 0 ? w != 0u : key >= w) continue;        // decided already
         if (!recheck64(tm, ep ? *ep : none, cd, q, t, kind, a, b)) continue;
         if (cd.kind == 0) atomicOr(cd.word + q, 1u);
-        else atomicMin(cd.word + q, (unsigned)t * (unsigned)tm.P + pair_index(tm.s_robot[a], tm.s_robot[b], tm.n_robots));
+        else atomicMin(cd.word + q, key);
     }
 }
 

@@ -58,14 +58,17 @@ struct Scratch {
     DevBuf ctrl;            // 8 ints + ST_COUNT u64
     DevBuf hist, start, off;
     size_t bins = 0;
-    DevBuf q_T, q_nt, q_g, q_chunk, q_status, q_word, q_sorted;
+    DevBuf q_T, q_nt, q_g, q_chunk, q_status, q_word, q_drop, q_sorted;
     DevBuf gq;              // near-contact queue (int4 records)
+    size_t gq_records = kGlobalRecheckCap;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     int last_kind = -1;
-    static constexpr int kGlobalRecheckCap = 1 << 21;
+    static constexpr size_t kGlobalRecheckCap = size_t(1) << 21;   // 32 MiB
+    static constexpr size_t kMaxRecheckCap = size_t(1) << 27;      // 2 GiB
     void release()
     {
-        for (DevBuf* b : {&ctrl, &hist, &start, &off, &q_T, &q_nt, &q_g, &q_chunk, &q_status, &q_word, &q_sorted, &gq})
+        for (DevBuf* b : {&ctrl, &hist, &start, &off, &q_T, &q_nt, &q_g, &q_chunk, &q_status, &q_word, &q_drop,
+                          &q_sorted, &gq})
             b->release();
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
@@ -75,11 +78,15 @@ struct Scratch {
     size_t bytes() const
     {
         return ctrl.cap + hist.cap + start.cap + off.cap + q_T.cap + q_nt.cap + q_g.cap + q_chunk.cap +
-               q_status.cap + q_word.cap + q_sorted.cap + gq.cap;
+               q_status.cap + q_word.cap + q_drop.cap + q_sorted.cap + gq.cap;
     }
 };
 
 void ensure_scratch(Scratch& sc, size_t bins, size_t queries);
+// Enlarge the near-contact queue to hold `pushed` records (with 25% headroom).
+// False when it already does or the size would pass kMaxRecheckCap.  The caller
+// must have drained every launch that uses sc.
+bool grow_recheck(Scratch& sc, size_t pushed);
 
 // Path arrays of one call (device pointers).
 struct DevPaths {
@@ -123,7 +130,7 @@ std::mutex& serve_handle_mutex(mrv_ctx ctx);
 // Request loop behind mrv_submit/mrv_poll (mrv_serve.cpp).
 class ServeLoop {
 public:
-    ServeLoop(mrv_ctx ctx, int device, int max_inflight, size_t budget_bytes);
+    ServeLoop(mrv_ctx ctx, int device, int max_inflight, size_t budget_bytes, size_t recheck_records);
     ~ServeLoop();
     mrv_status submit(const mrv_request& req, const ServeRefs& refs, uint64_t* ticket);
     // timeout_ms: 0 = do not wait, < 0 = wait forever

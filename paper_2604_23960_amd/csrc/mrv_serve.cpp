@@ -85,7 +85,9 @@ struct Slot {
     std::vector<int> q_off;   // first query of each request in the batch
     int kind = 0;
     bool busy = false;
-    int unresolved = 0;       // host copy of the scratch's unresolved-query count
+    CallPlan plan{};          // the batch's call, kept to run it again after a queue overflow
+    size_t nout = 0;
+    int attempts = 0;
 };
 
 }  // namespace
@@ -109,11 +111,12 @@ struct ServeLoop::Impl {
     static constexpr int kSlots = 4;
     static constexpr int kMaxBatchQueries = 1 << 16;
 
-    Impl(mrv_ctx c, int dev, int mi, size_t b) : ctx(c), device(dev), max_inflight(mi), budget(b)
+    Impl(mrv_ctx c, int dev, int mi, size_t b, size_t rq) : ctx(c), device(dev), max_inflight(mi), budget(b)
     {
         HIPCHK(hipSetDevice(device));
         slots.resize(kSlots);
         for (Slot& s : slots) {
+            s.sc.gq_records = rq;
             HIPCHK(hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking));
             HIPCHK(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
         }
@@ -326,11 +329,22 @@ struct ServeLoop::Impl {
         pl.min_chunk = min_chunk;
         pl.lds = lds;
         pl.wg_per_cu = 0;
-        serve_run_plan(ctx, s.sc, pl, s.d_out.p, s.stream);
-        HIPCHK(hipMemcpyAsync(s.h_out.p, s.d_out.p, nout, hipMemcpyDeviceToHost, s.stream));
-        HIPCHK(hipMemcpyAsync((char*)s.h_out.p + nout, (int*)s.sc.ctrl.p + 1, sizeof(int), hipMemcpyDeviceToHost,
-                              s.stream));
+        s.plan = pl;
+        s.nout = nout;
+        s.attempts = 0;
+        run_batch(s);
+    }
+
+    // Queue the slot's call; its answers and the overflow counters (unresolved
+    // queries, near tests pushed) come back to pinned memory.
+    void run_batch(Slot& s)
+    {
+        serve_run_plan(ctx, s.sc, s.plan, s.d_out.p, s.stream);
+        HIPCHK(hipMemcpyAsync(s.h_out.p, s.d_out.p, s.nout, hipMemcpyDeviceToHost, s.stream));
+        HIPCHK(hipMemcpyAsync((char*)s.h_out.p + s.nout, (int*)s.sc.ctrl.p + 1, 2 * sizeof(int),
+                              hipMemcpyDeviceToHost, s.stream));
         HIPCHK(hipEventRecord(s.done, s.stream));
+        ++s.attempts;
     }
 
     void complete(Slot& s)
@@ -339,8 +353,24 @@ struct ServeLoop::Impl {
         int total = 0;
         for (auto& r : s.batch) total += r->n_queries;
         const size_t nout = (size_t)total * per;
-        int unresolved = 0;
-        std::memcpy(&unresolved, (char*)s.h_out.p + nout, sizeof(int));
+        int cnt[2] = {0, 0};   // unresolved queries, near tests pushed
+        std::memcpy(cnt, (char*)s.h_out.p + nout, sizeof(cnt));
+        const int unresolved = cnt[0];
+        bool cancelled = true;
+        for (auto& r : s.batch) cancelled = cancelled && r->cancel_requested;
+        if (unresolved && !cancelled && s.attempts < 3) {
+            // the near-contact queue overflowed: enlarge it and run the batch again
+            bool again = false;
+            try {
+                if (grow_recheck(s.sc, (unsigned)cnt[1])) {
+                    run_batch(s);
+                    again = true;
+                }
+            } catch (...) {
+                (void)hipStreamSynchronize(s.stream);
+            }
+            if (again) return;
+        }
         for (size_t k = 0; k < s.batch.size(); ++k) {
             auto& r = s.batch[k];
             const size_t off = (size_t)s.q_off[k] * per;
@@ -361,8 +391,8 @@ struct ServeLoop::Impl {
     }
 };
 
-ServeLoop::ServeLoop(mrv_ctx ctx, int device, int max_inflight, size_t budget_bytes)
-    : impl_(new Impl(ctx, device, max_inflight, budget_bytes))
+ServeLoop::ServeLoop(mrv_ctx ctx, int device, int max_inflight, size_t budget_bytes, size_t recheck_records)
+    : impl_(new Impl(ctx, device, max_inflight, budget_bytes, recheck_records))
 {
 }
 

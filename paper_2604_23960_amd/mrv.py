@@ -38,7 +38,8 @@ class MrvError(RuntimeError):
 
 class CtxOpts(C.Structure):
     _fields_ = [("device", C.c_int32), ("stream", C.c_void_p), ("near_eps", C.c_double),
-                ("max_inflight", C.c_int32), ("serve_bytes", C.c_size_t), ("flags", C.c_uint32)]
+                ("max_inflight", C.c_int32), ("serve_bytes", C.c_size_t), ("recheck_records", C.c_int64),
+                ("flags", C.c_uint32)]
 
 
 class RobotDesc(C.Structure):
@@ -180,10 +181,10 @@ class DevicePaths:
 
 class Context:
     def __init__(self, device: int = 0, stream=None, near_eps: float = 0.0, max_inflight: int = 0,
-                 serve_bytes: int = 0):
+                 serve_bytes: int = 0, recheck_records: int = 0):
         self._keep = []
         h = C.c_void_p()
-        opts = CtxOpts(device, stream, near_eps, max_inflight, serve_bytes, 0)
+        opts = CtxOpts(device, stream, near_eps, max_inflight, serve_bytes, recheck_records, 0)
         check(lib().mrv_create(C.byref(opts), C.byref(h)))
         self.h = h
 

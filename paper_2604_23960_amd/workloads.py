@@ -436,6 +436,27 @@ def ffc_workload(n_queries: int = 16384, seed: int = 2) -> Workload:
     return Workload("ffc-4arm-4rect-200to2000", team, env, paths, "ffc")
 
 
+def grazing_disks(n_queries: int = 300, T: int = 64) -> Workload:
+    """Three disks of radius 0.25 with exact touching contacts, so most tests fall
+    in the near-contact band.  Disk 0 rests at the origin; disks 1 and 2 touch it
+    at (0.5, 0) and (0, 0.5) (clearance exactly 0, not a collision).  By query
+    index mod 3: (0) all rest for T steps; (1) disk 1 rests until T/2, then moves
+    to (0.25, 0), overlapping disk 0 from step T/2 + 1; (2) disk 2 overlaps disk 0
+    at (0, 0.3) throughout."""
+    team = [disk_robot(0.25, f"disk{k}") for k in range(3)]
+    env = Env()
+    rest0 = ([0, T - 1], [[0.0, 0.0], [0.0, 0.0]])
+    touch1 = ([0, T - 1], [[0.5, 0.0], [0.5, 0.0]])
+    touch2 = ([0, T - 1], [[0.0, 0.5], [0.0, 0.5]])
+    move1 = ([0, T // 2, T - 1], [[0.5, 0.0], [0.5, 0.0], [0.25, 0.0]])
+    over2 = ([0, T - 1], [[0.0, 0.3], [0.0, 0.3]])
+    per = []
+    for q in range(n_queries):
+        per.append([rest0, touch1, touch2] if q % 3 == 0 else
+                   [rest0, move1, touch2] if q % 3 == 1 else [rest0, touch1, over2])
+    return Workload("grazing-3disks", team, env, paths_from_lists(per, 2), "mv+ffc")
+
+
 def small(w_fn, n_queries: int, **kw) -> Workload:
     return w_fn(n_queries=n_queries, **kw)
 

@@ -446,3 +446,18 @@ def test_invariant_zero_length_and_single_robot():
     p1 = W.paths_from_lists([[w.paths.path(q, 0)] for q in range(64)], 7)
     assert np.all(oracle.ffc(one, oracle.Paths(p1))[:, 0] == -1)
     assert np.all(oracle.mv(one, oe, oracle.Paths(p1), check_env=False) == 1)
+
+
+def test_touching_is_not_a_collision_and_first_overlap_closed_form():
+    """Contact at clearance exactly 0 is free (a collision needs a negative
+    clearance, §II-B); the first overlapping step of a linear approach and the
+    lexicographic order of FFC's (t, i, j) follow by hand."""
+    T = 64
+    w = W.grazing_disks(9, T)
+    ot, op = oracle.Team(w.team), oracle.Paths(w.paths)
+    v = oracle.mv(ot, None, op, check_env=False)
+    assert list(v) == [1, 0, 0] * 3
+    f = oracle.ffc(ot, op)
+    # disk 1 at x = 0.5 - 0.25 (t - T/2) / (T/2 - 1) clears disk 0 by x - 0.5 < 0 from t = T/2 + 1
+    want = [(-1, -1, -1), (T // 2 + 1, 0, 1), (0, 0, 2)] * 3
+    assert [tuple(r) for r in f] == want
