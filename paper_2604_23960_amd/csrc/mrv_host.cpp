@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <array>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -194,16 +195,6 @@ int build_team(mrv_ctx ctx, const mrv_robot_desc* robots, int n, TeamHost& out)
         r_sphere_off[r + 1] = S;
     }
     if (S > MRV_MAX_TEAM_SPHERES) throw Err{MRV_E_INVALID, "team has too many spheres"};
-    // robot-robot tasks: each 64-sphere slot against every robot above the slot's first robot
-    const int n_slots = (S + 63) / 64;
-    std::vector<int> rr_tasks;
-    for (int slot = 0; slot < n_slots; ++slot) {
-        const int rmin = s_robot[slot * 64];
-        for (int rb = rmin + 1; rb < n; ++rb) {
-            rr_tasks.push_back(slot);
-            rr_tasks.push_back(rb);
-        }
-    }
     // sphere groups: up to 16 consecutive spheres of one robot
     std::vector<int> s_group(S), r_group_off(n + 1, 0), g_range;
     int G = 0;
@@ -218,6 +209,46 @@ int build_team(mrv_ctx ctx, const mrv_robot_desc* robots, int n, TeamHost& out)
         }
     }
     r_group_off[n] = G;
+    // slots: 16 per group, unused ones padded, so a group is one 16-wide MFMA operand
+    const int GS = G * 16;
+    std::vector<int> slot_sphere(GS, -1), sphere_slot(S);
+    for (int g = 0; g < G; ++g)
+        for (int s2 = g_range[2 * g]; s2 < g_range[2 * g + 1]; ++s2) {
+            slot_sphere[g * 16 + (s2 - g_range[2 * g])] = s2;
+            sphere_slot[s2] = g * 16 + (s2 - g_range[2 * g]);
+        }
+    // robot-robot tasks: each group against every higher robot, one 8-int record each
+    std::vector<int> rr_tasks;
+    for (int r = 0; r < n; ++r)
+        for (int g = r_group_off[r]; g < r_group_off[r + 1]; ++g)
+            for (int rb = r + 1; rb < n; ++rb) {
+                const int rec[8] = { g, rb, r_group_off[rb], r_group_off[rb + 1],
+                                     (g_range[2 * g + 1] - g_range[2 * g]) * (r_sphere_off[rb + 1] - r_sphere_off[rb]),
+                                     r, 0, 0 };
+                rr_tasks.insert(rr_tasks.end(), rec, rec + 8);
+            }
+    // self blocks: for each pair of groups (ga <= gb) holding self pairs, one lane
+    // mask per accumulator register r: bit l set when the pair (row 4 (l / 16) + r
+    // of ga, column l % 16 of gb) is in the list (each unordered pair once)
+    std::map<std::pair<int, int>, std::array<uint64_t, 4>> blocks;
+    for (size_t p = 0; p < self_pairs.size(); p += 2) {
+        int sa = sphere_slot[self_pairs[p]], sb = sphere_slot[self_pairs[p + 1]];
+        if (sa > sb) std::swap(sa, sb);
+        const int row = sa % 16, col = sb % 16;
+        auto& m = blocks.emplace(std::make_pair(sa / 16, sb / 16), std::array<uint64_t, 4>{0, 0, 0, 0}).first->second;
+        m[row & 3] |= 1ull << (16 * (row >> 2) + col);
+    }
+    std::vector<int> sblocks;
+    std::vector<uint64_t> sb_mask;
+    int n_self_unique = 0;
+    for (const auto& kv : blocks) {
+        int cnt = 0;
+        for (uint64_t m : kv.second) cnt += __builtin_popcountll(m);
+        const int rec[8] = { kv.first.first, kv.first.second, cnt, s_robot[g_range[2 * kv.first.first]], 0, 0, 0, 0 };
+        sblocks.insert(sblocks.end(), rec, rec + 8);
+        for (uint64_t m : kv.second) sb_mask.push_back(m);
+        n_self_unique += cnt;
+    }
     float r_max = 0.f;
     for (int s2 = 0; s2 < S; ++s2) r_max = std::max(r_max, s_local32[s2 * 4 + 3]);
     long long rr_per_t = 0;
@@ -230,8 +261,9 @@ int build_team(mrv_ctx ctx, const mrv_robot_desc* robots, int n, TeamHost& out)
                  o_fo = pk.add(r_frame_off), o_b32 = pk.add(base32), o_b64 = pk.add(base64),
                  o_jt = pk.add(j_type), o_j32 = pk.add(j32), o_j64 = pk.add(j64), o_sr = pk.add(s_robot),
                  o_ss = pk.add(s_slot), o_sl = pk.add(s_lframe), o_l32 = pk.add(s_local32),
-                 o_l64 = pk.add(s_local64), o_sp = pk.add(self_pairs), o_rt = pk.add(rr_tasks),
-                 o_sg = pk.add(s_group), o_gr = pk.add(g_range), o_rg = pk.add(r_group_off);
+                 o_l64 = pk.add(s_local64), o_rt = pk.add(rr_tasks), o_sg = pk.add(s_group),
+                 o_gr = pk.add(g_range), o_rg = pk.add(r_group_off), o_ss2 = pk.add(slot_sphere),
+                 o_sb = pk.add(sblocks), o_sm = pk.add(sb_mask);
     const TeamDev blank{};
     const size_t o_self = pk.add(&blank, sizeof(TeamDev));
     void* d = nullptr;
@@ -241,13 +273,25 @@ int build_team(mrv_ctx ctx, const mrv_robot_desc* robots, int n, TeamHost& out)
     t.n_robots = n;
     t.S = S;
     t.F = F;
-    t.n_self = (int)self_pairs.size() / 2;
-    t.n_rr_tasks = (int)rr_tasks.size() / 2;
-    t.n_slots = n_slots;
+    t.n_self = n_self_unique;
+    t.n_rr_tasks = (int)rr_tasks.size() / 8;
+    t.n_sblocks = (int)sblocks.size() / 8;
+    t.GS = GS;
+    t.GSp = GS + 16;
     t.P = n * (n - 1) / 2;
     t.max_dof = max_dof;
     t.G = G;
     t.r_max = r_max;
+    {
+        float lo[3] = { 3e38f, 3e38f, 3e38f }, hi[3] = { -3e38f, -3e38f, -3e38f };
+        for (int r = 0; r < n; ++r)
+            for (int d = 0; d < 3; ++d) {
+                lo[d] = std::min(lo[d], base32[r * 12 + 4 * d + 3]);
+                hi[d] = std::max(hi[d], base32[r * 12 + 4 * d + 3]);
+            }
+        for (int d = 0; d < 3; ++d) t.origin[d] = 0.5f * (lo[d] + hi[d]);
+        t.origin[3] = 0.f;
+    }
     t.rr_tests_per_t = rr_per_t;
     t.s_group = (const int*)at(o_sg);
     t.g_range = (const int2*)at(o_gr);
@@ -266,8 +310,10 @@ int build_team(mrv_ctx ctx, const mrv_robot_desc* robots, int n, TeamHost& out)
     t.s_lframe = (const int*)at(o_sl);
     t.s_local32 = (const float4*)at(o_l32);
     t.s_local64 = (const double*)at(o_l64);
-    t.self_pairs = (const int2*)at(o_sp);
-    t.rr_tasks = (const int2*)at(o_rt);
+    t.rr_rec = (const int*)at(o_rt);
+    t.slot_sphere = (const int*)at(o_ss2);
+    t.sblocks = (const int*)at(o_sb);
+    t.sb_mask = (const unsigned long long*)at(o_sm);
     out.dmem = d;
     out.d_dev = (TeamDev*)at(o_self);
     out.dof = r_nj;
@@ -470,7 +516,7 @@ long long max_horizon(const mrv_paths* p, int n_robots)
 
 size_t lds_per_t(const TeamHost& tm)
 {
-    return (size_t)tm.dev.S * 16 + (size_t)tm.dev.S * 4 + (size_t)tm.dev.G * 16 + (size_t)tm.dev.F * 48;
+    return (size_t)tm.dev.GSp * 5 * sizeof(float) + (size_t)tm.dev.F * 48;
 }
 
 int default_chunk(const TeamHost& tm, int kind)
@@ -479,8 +525,13 @@ int default_chunk(const TeamHost& tm, int kind)
     int cmax = (int)((kLdsBudget - 2 * 1024) / per_t);
     cmax = std::min(cmax, kMaxChunk);
     if (cmax < 1) cmax = 1;
-    const int want = kind == 0 ? 8 : 8;
-    return std::min(cmax, want);
+    // up to 8 timesteps, fewer if that keeps four (else three) workgroups per CU
+    // within its 160 KiB of LDS
+    (void)kind;
+    const int c4 = (int)((160 * 1024 / 4 - 1024) / per_t);
+    const int c3 = (int)((160 * 1024 / 3 - 1024) / per_t);
+    const int want = c4 >= 4 ? std::min(8, c4) : c3 >= 4 ? std::min(8, c3) : 8;
+    return std::max(1, std::min(cmax, want));
 }
 
 size_t lds_bytes_for(const TeamHost& tm, int chunk)
@@ -493,11 +544,14 @@ size_t lds_bytes_for(const TeamHost& tm, int chunk)
 namespace mrv {
 // Make sc hold control words, `bins` tile-count bins and `queries` per-query slots.
 // Fresh bins are zeroed here; afterwards k_scan leaves them zero after every call.
-void ensure_scratch(Scratch& sc, size_t bins, size_t queries)
+void ensure_scratch(Scratch& sc, size_t bins, size_t queries, hipStream_t stream)
 {
+    // fresh control words and bins are cleared by a kernel on the stream that will
+    // use them (a blocking hipMemset runs on the null stream, which the library's
+    // non-blocking streams do not wait for)
     if (!sc.ctrl.p) {
         sc.ctrl.ensure(64 + 8 * ST_COUNT + 64);
-        HIPCHK(hipMemset(sc.ctrl.p, 0, sc.ctrl.cap));
+        HIPCHK(fill_u32(sc.ctrl.p, 0u, sc.ctrl.cap / 4, stream));
     }
     if (!sc.ev0) {
         HIPCHK(hipEventCreate(&sc.ev0));
@@ -511,7 +565,7 @@ void ensure_scratch(Scratch& sc, size_t bins, size_t queries)
         sc.hist.ensure(bins * sizeof(int));
         sc.start.ensure(bins * sizeof(int));
         sc.off.ensure(bins * sizeof(long long));
-        HIPCHK(hipMemset(sc.hist.p, 0, sc.hist.cap));
+        HIPCHK(fill_u32(sc.hist.p, 0u, sc.hist.cap / 4, stream));
         sc.bins = bins;
     }
     const size_t Q = std::max<size_t>(queries, 1);
@@ -546,7 +600,7 @@ void run_plan(mrv_ctx ctx, Scratch& sc, const CallPlan& pl, void* out_dev, hipSt
 {
     const int kind = pl.kind;
     const int min_chunk = std::max(1, pl.min_chunk);
-    ensure_scratch(sc, (size_t)((pl.max_T + min_chunk - 1) / min_chunk) + 2, (size_t)pl.dp.n_queries);
+    ensure_scratch(sc, (size_t)((pl.max_T + min_chunk - 1) / min_chunk) + 2, (size_t)pl.dp.n_queries, stream);
     CallDev cd{};
     cd.n_queries = pl.dp.n_queries;
     cd.dof_stride = pl.dp.dof_stride;
@@ -776,7 +830,7 @@ mrv_status mrv_create(const mrv_ctx_opts* opts, mrv_ctx* out)
             HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
             c->own_stream = true;
         }
-        ensure_scratch(c->sc, (size_t)MRV_MAX_T + 2, 1);
+        ensure_scratch(c->sc, (size_t)MRV_MAX_T + 2, 1, c->stream);
         *out = c.release();
     });
 }
@@ -1179,7 +1233,7 @@ mrv_status mrv_graph_create(mrv_ctx ctx, int32_t team, int32_t env, int32_t kind
         CallPlan pl = single_plan(tm, ev, kind, f, dp, MRV_MAX_T);
         // every buffer exists before capture: nothing is allocated inside the graph
         g->sc.gq_records = ctx->sc.gq_records;
-        ensure_scratch(g->sc, (size_t)MRV_MAX_T + 2, (size_t)paths->n_queries);
+        ensure_scratch(g->sc, (size_t)MRV_MAX_T + 2, (size_t)paths->n_queries, ctx->stream);
         HIPCHK(hipStreamSynchronize(ctx->stream));
         HIPCHK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
         try {

@@ -14,7 +14,6 @@ constexpr int kMaxRobots = 32;
 constexpr int kMaxJoints = 8;
 constexpr int kMaxChunk = 64;       // timesteps per tile
 constexpr int kLdsBudget = 64 * 1024;
-constexpr int kEnvC = 8;           // timesteps a lane carries through the obstacle loops
 
 enum RecheckKind : int { RK_RR = 0, RK_SELF = 1, RK_ENV_SPH = 2, RK_ENV_BOX = 3, RK_ENV_CYL = 4, RK_ENV_PT = 5 };
 
@@ -30,15 +29,18 @@ struct TeamDev {
     int n_robots;
     int S;                 // total spheres
     int F;                 // frame slots per timestep: sum over robots of (n_joints + 1)
-    int n_self;            // flattened self-collision pairs
-    int n_rr_tasks;        // (slot, partner robot) tasks per timestep
-    int n_slots;           // ceil(S / 64)
+    int n_self;            // distinct self-collision pairs
+    int n_rr_tasks;        // (group, higher robot) tasks per timestep
+    int n_sblocks;         // 16 x 16 self blocks per timestep
     int P;                 // robot pairs n(n-1)/2
     int max_dof;
     int G;                 // sphere groups per timestep (16 consecutive spheres of one robot)
+    int GS;                // sphere slots, 16 per group
+    int GSp;               // LDS row stride of the slot arrays (GS + 16, against bank conflicts)
     int chunk[2];          // timesteps per tile for MV / FFC
     int lds_per_t;         // LDS bytes one timestep of a tile needs
     float r_max;           // largest sphere radius of the team
+    float origin[4];       // reference point of the FP32 sphere records (centre of the bases' bounding box)
     long long rr_tests_per_t;   // sum_{i<j} n_i n_j
     const int* r_nj;            // [n]
     const int* r_joint_off;     // [n]
@@ -57,8 +59,11 @@ struct TeamDev {
     const int* s_group;         // [S] group of each sphere
     const int2* g_range;        // [G] sphere range [begin, end) of each group
     const int* r_group_off;     // [n+1] first group of each robot
-    const int2* self_pairs;     // [n_self] flattened sphere indices
-    const int2* rr_tasks;       // [n_rr_tasks] (slot, partner robot)
+    const int* rr_rec;          // [n_rr_tasks][8] group ga, higher robot rb, rb's groups [g0, g1),
+                                // tests (spheres of ga x spheres of rb), robot of ga, 0, 0
+    const int* slot_sphere;     // [GS] sphere of each slot, -1 for padding
+    const int* sblocks;         // [n_sblocks][8] row group, column group, pairs, robot, 0, 0, 0, 0
+    const unsigned long long* sb_mask;   // [n_sblocks][4] lane masks, one per accumulator register
 };
 
 // Resident environment in the world frame.

@@ -57,6 +57,21 @@ __device__ __forceinline__ T load_descriptor(unsigned long long p)
     return out;
 }
 
+// Reads of read-only tables at wave-uniform addresses, as scalar loads.
+typedef const __attribute__((address_space(4))) float CFloat;
+typedef const __attribute__((address_space(4))) int CInt;
+typedef const __attribute__((address_space(4))) unsigned long long CU64;
+__device__ __forceinline__ int cload(const int* p) { return *(CInt*)p; }
+__device__ __forceinline__ float cloadf(const float* p) { return *(CFloat*)p; }
+__device__ __forceinline__ unsigned long long cload64(const unsigned long long* p) { return *(CU64*)p; }
+
+// A workgroup flag written by other waves (an LDS load each time).
+__device__ __forceinline__ int flag_read(int* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
+__device__ __forceinline__ unsigned flag_read(unsigned* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 __device__ __forceinline__ const TeamDev* team_of(const CallDev& cd, int q) { return cd.q_team ? cd.q_team[q] : cd.team0; }
 __device__ __forceinline__ const EnvDev* env_of(const CallDev& cd, int q) { return cd.q_env ? cd.q_env[q] : cd.env0; }
 __device__ __forceinline__ long long path_of(const CallDev& cd, int n_robots, int q)
@@ -453,33 +468,23 @@ __device__ __forceinline__ void push_recheck(const CallDev& cd, int q, int t, in
     else atomicMin(cd.drop + q, key);
 }
 
-// One robot-robot rotation step: lane L tests its sphere (a-side, scaled by -2 and
-// centred on the group) against partner record (L + R) mod 16 of its 16-lane row:
-//   acc = w_b + ax x_b + ay y_b + az z_b + ar r_b.
-template <int R>
-__device__ __forceinline__ float rr_step(float bw, float bx, float by, float bz, float br, float ax, float ay,
-                                         float az, float ar)
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr float kFar = 1.0e30f;     // w of an unused slot: its tests never reach zero
+
+// on where bit `lane` of the wave-uniform mask m is set, else off (the mask acts
+// as the lane predicate of one v_cndmask)
+__device__ __forceinline__ float lane_select(unsigned long long m, float on, float off)
 {
-    float acc;
-    asm("v_mov_b32_dpp %0, %1 row_ror:%c2 row_mask:0xf bank_mask:0xf" : "=v"(acc) : "v"(bw), "i"(R));
-    asm("v_fmac_f32_dpp %0, %1, %2 row_ror:%c3 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(bx), "v"(ax), "i"(R));
-    asm("v_fmac_f32_dpp %0, %1, %2 row_ror:%c3 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(by), "v"(ay), "i"(R));
-    asm("v_fmac_f32_dpp %0, %1, %2 row_ror:%c3 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(bz), "v"(az), "i"(R));
-    asm("v_fmac_f32_dpp %0, %1, %2 row_ror:%c3 row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(br), "v"(ar), "i"(R));
-    return acc;
+    return __builtin_amdgcn_inverse_ballot_w64(m) ? on : off;
 }
 
-// Minimum over the 16 records of a row of  w_b - 2 a'.b' - 2 ra rb.
-__device__ __forceinline__ float rr_group_min(float bw, float bx, float by, float bz, float br, float ax, float ay,
-                                              float az, float ar)
+// min(best, min_r d[r] + wb) for one MFMA result: adding w_b first makes the
+// operands of the minimum results of arithmetic, which need no NaN quieting
+__device__ __forceinline__ float block_min(floatx4 d, float wb, float best)
 {
-    float m = fmaf(ax, bx, fmaf(ay, by, fmaf(az, bz, fmaf(ar, br, bw))));
-#define MRV_RR2(R1, R2) m = fminf(m, fminf(rr_step<R1>(bw, bx, by, bz, br, ax, ay, az, ar), \
-                                             rr_step<R2>(bw, bx, by, bz, br, ax, ay, az, ar)));
-    MRV_RR2(1, 2) MRV_RR2(3, 4) MRV_RR2(5, 6) MRV_RR2(7, 8) MRV_RR2(9, 10) MRV_RR2(11, 12) MRV_RR2(13, 14)
-#undef MRV_RR2
-    m = fminf(m, rr_step<15>(bw, bx, by, bz, br, ax, ay, az, ar));
-    return m;
+    const float m = fminf(fminf(best, d[0] + wb), d[1] + wb);
+    return fminf(fminf(m, d[2] + wb), d[3] + wb);
 }
 
 __device__ __forceinline__ float wave_max_f32(float v)
@@ -491,7 +496,7 @@ __device__ __forceinline__ float wave_max_f32(float v)
 
 // Squared distance from x to a box surface region (0 inside), box in the
 // precomputed row form of EnvDev::box32.
-__device__ __forceinline__ float box_val(float x, float y, float z, const float* B)
+__device__ __forceinline__ float box_val(float x, float y, float z, CFloat* B)
 {
     const float p0 = fmaf(B[0], x, fmaf(B[1], y, fmaf(B[2], z, B[3])));
     const float p1 = fmaf(B[4], x, fmaf(B[5], y, fmaf(B[6], z, B[7])));
@@ -502,7 +507,7 @@ __device__ __forceinline__ float box_val(float x, float y, float z, const float*
     return fmaf(e0, e0, fmaf(e1, e1, e2 * e2));
 }
 
-__device__ __forceinline__ float cyl_val(float x, float y, float z, const float* Y)
+__device__ __forceinline__ float cyl_val(float x, float y, float z, CFloat* Y)
 {
     const float vx = x - Y[0], vy = y - Y[1], vz = z - Y[2];
     const float h = fmaf(vx, Y[3], fmaf(vy, Y[4], vz * Y[5]));
@@ -606,7 +611,7 @@ __device__ __forceinline__ float4 place32(const float4* Fp, float4 L)
 }
 
 template <int KIND>
-__global__ __launch_bounds__(kWG) void k_validate(CallDev cd)
+__global__ __launch_bounds__(kWG, 4) void k_validate(CallDev cd)
 {
     extern __shared__ float4 dyn[];
 
@@ -717,10 +722,15 @@ __global__ __launch_bounds__(kWG) void k_validate(CallDev cd)
         const int G = tm.G;
         const int n = tm.n_robots;
         const long long qp0 = path_of(cd, n, q);
-        float4* rec = dyn;                                  // [C][S] (x', y', z', r) relative to the group centre
-        float* rw = reinterpret_cast<float*>(dyn + C * S);  // [C][S] w' = |x'|^2 - r^2
-        float4* gc = dyn + C * S + (C * S + 3) / 4;         // [C][G] group centres
-        float4* fr = gc + C * G;                            // [C][F][3] frame rows
+        // LDS of this tile.  Per timestep c, five rows of GSp floats over the sphere
+        // slots (16 per group, unused slots padded): x, y, z relative to the team's
+        // origin, radius (0 marks padding), w = |p|^2 - r^2; then the frames of the
+        // FK chains.
+        const int GS = tm.GS;
+        const int GSp = tm.GSp;
+        const float ox = tm.origin[0], oy = tm.origin[1], oz = tm.origin[2];
+        float* sp = reinterpret_cast<float*>(dyn);                      // [C][5][GSp]
+        float4* fr = reinterpret_cast<float4*>(sp + C * 5 * GSp);       // [C][F][3] frame rows
 
         // --- configurations and FP32 forward kinematics: one lane per (timestep, robot)
         for (int idx = tid; idx < nv * n; idx += kWG) {
@@ -731,287 +741,272 @@ __global__ __launch_bounds__(kWG) void k_validate(CallDev cd)
         }
         __syncthreads();
 
-        // --- sphere centres (absolute, temporarily), one lane per (timestep, sphere)
-        for (int idx = tid; idx < nv * S; idx += kWG) {
-            const int c = idx / S;
-            const int s = idx - c * S;
-            rec[idx] = place32(fr + ((long long)c * F + tm.s_slot[s]) * 3, tm.s_local32[s]);
-        }
-        __syncthreads();
-        // --- group centres: mean of the group's sphere centres
-        for (int idx = tid; idx < nv * G; idx += kWG) {
-            const int c = idx / G;
-            const int2 rg = tm.g_range[idx - c * G];
-            float sx = 0.f, sy = 0.f, sz = 0.f;
-            for (int s = rg.x; s < rg.y; ++s) {
-                const float4 X = rec[c * S + s];
-                sx += X.x; sy += X.y; sz += X.z;
-            }
-            const float inv = 1.f / (float)(rg.y - rg.x);
-            gc[idx] = make_float4(sx * inv, sy * inv, sz * inv, 0.f);
-        }
-        __syncthreads();
-        // --- records relative to the group centre
+        // --- sphere records, one lane per (timestep, slot)
         {
             float r2max = 0.f;
-            for (int idx = tid; idx < nv * S; idx += kWG) {
-                const int c = idx / S;
-                const int s = idx - c * S;
-                const float4 X = rec[idx];
-                const float4 O = gc[c * G + tm.s_group[s]];
-                const float x = X.x - O.x, y = X.y - O.y, z = X.z - O.z;
-                const float d2 = fmaf(x, x, fmaf(y, y, z * z));
-                rec[idx] = make_float4(x, y, z, X.w);
-                rw[idx] = fmaf(-X.w, X.w, d2);
-                r2max = fmaxf(r2max, d2);
+            for (int idx = tid; idx < nv * GS; idx += kWG) {
+                const int c = idx / GS;
+                const int s = idx - c * GS;
+                const int sph = tm.slot_sphere[s];
+                float x = 0.f, y = 0.f, z = 0.f, r = 0.f, w = kFar;
+                if (sph >= 0) {
+                    const float4 X = place32(fr + ((long long)c * F + tm.s_slot[sph]) * 3, tm.s_local32[sph]);
+                    x = X.x - ox;
+                    y = X.y - oy;
+                    z = X.z - oz;
+                    r = X.w;
+                    const float d2 = fmaf(x, x, fmaf(y, y, z * z));
+                    w = fmaf(-r, r, d2);
+                    r2max = fmaxf(r2max, d2);
+                }
+                float* row = sp + c * 5 * GSp + s;
+                row[0] = x;
+                row[GSp] = y;
+                row[2 * GSp] = z;
+                row[3 * GSp] = r;
+                row[4 * GSp] = w;
             }
             r2max = wave_max_f32(r2max);
             if (lane == 0) atomicMax(&s_rho2, __float_as_uint(r2max));
         }
         __syncthreads();
 
-        // --- robot-obstacle and self tests (MV with environment checking).  A lane keeps
-        // one sphere (or one self pair) for up to kEnvC timesteps of the tile, so each
-        // obstacle's parameters are read once per kEnvC tests.
+        // --- robot-obstacle tests (MV with environment checking): one lane per
+        // (timestep, slot); obstacle parameters are wave-uniform scalar loads.
         if (do_env) {
-            const int nslots = tm.n_slots;
-            const int ncb = (nv + kEnvC - 1) / kEnvC;
-            const int ntask = nslots * ncb;
+            const int nch = (GS + kWave - 1) / kWave;
+            const int ntask = nv * nch;
             float ro_max = 0.f;
-            for (int o = 0; o < env.n_sph; ++o) ro_max = fmaxf(ro_max, env.sph32[o].w);
+            for (int o = 0; o < env.n_sph; ++o) ro_max = fmaxf(ro_max, cloadf(&env.sph32[o].w));
             for (int task = wave; task < ntask; task += kWavesPerWG) {
-                if (!exhaustive && *(volatile int*)&s_hit) break;
-                const int cb = task / nslots;
-                const int a = (task - cb * nslots) * 64 + lane;
-                const int c0 = cb * kEnvC;
-                const int nc = min(kEnvC, nv - c0);
-                const bool act = a < S;
-                float X0[kEnvC], X1[kEnvC], X2[kEnvC], mb[kEnvC], ms[kEnvC];
-                float rad = 0.f;
-                if (act) rad = rec[c0 * S + a].w;
-#pragma unroll
-                for (int cc = 0; cc < kEnvC; ++cc) {
-                    X0[cc] = 1.0e18f; X1[cc] = 1.0e18f; X2[cc] = 1.0e18f;
-                    mb[cc] = 3.0e38f; ms[cc] = 3.0e38f;
-                    if (act && cc < nc) {
-                        const int c = c0 + cc;
-                        const float4 Xr = rec[c * S + a];
-                        const float4 O = gc[c * G + tm.s_group[a]];
-                        X0[cc] = Xr.x + O.x; X1[cc] = Xr.y + O.y; X2[cc] = Xr.z + O.z;
-                    }
+                if (!exhaustive && flag_read(&s_hit)) break;
+                const int c = task / nch;
+                const int a = (task - c * nch) * kWave + lane;     // slot
+                const float* row = sp + c * 5 * GSp + a;
+                const float rad = a < GS ? row[3 * GSp] : 0.f;
+                const bool act = rad > 0.f;
+                float x = 1.0e18f, y = 1.0e18f, z = 1.0e18f;
+                if (act) {
+                    x = row[0] + ox;
+                    y = row[GSp] + oy;
+                    z = row[2 * GSp] + oz;
                 }
-                for (int o = 0; o < env.n_box; ++o) {
-                    const float* B = env.box32 + o * 16;
-#pragma unroll
-                    for (int cc = 0; cc < kEnvC; ++cc) mb[cc] = fminf(mb[cc], box_val(X0[cc], X1[cc], X2[cc], B));
-                }
-                for (int o = 0; o < env.n_cyl; ++o) {
-                    const float* Y = env.cyl32 + o * 8;
-#pragma unroll
-                    for (int cc = 0; cc < kEnvC; ++cc) mb[cc] = fminf(mb[cc], cyl_val(X0[cc], X1[cc], X2[cc], Y));
-                }
+                float mb = 3.0e38f, ms = 3.0e38f;
+#pragma unroll 2
+                for (int o = 0; o < env.n_box; ++o) mb = fminf(mb, box_val(x, y, z, (CFloat*)(env.box32 + o * 16)));
+#pragma unroll 2
+                for (int o = 0; o < env.n_cyl; ++o) mb = fminf(mb, cyl_val(x, y, z, (CFloat*)(env.cyl32 + o * 8)));
                 for (int o = 0; o < env.n_sph; ++o) {
-                    const float4 Ob = env.sph32[o];
-                    const float Rs = rad + Ob.w;
-#pragma unroll
-                    for (int cc = 0; cc < kEnvC; ++cc) {
-                        const float dx = X0[cc] - Ob.x, dy = X1[cc] - Ob.y, dz = X2[cc] - Ob.z;
-                        ms[cc] = fminf(ms[cc], fmaf(-Rs, Rs, fmaf(dx, dx, fmaf(dy, dy, dz * dz))));
-                    }
+                    const float* ob = &env.sph32[o].x;
+                    const float Rs = rad + cloadf(ob + 3);
+                    const float dx = x - cloadf(ob), dy = y - cloadf(ob + 1), dz = z - cloadf(ob + 2);
+                    ms = fminf(ms, fmaf(-Rs, Rs, fmaf(dx, dx, fmaf(dy, dy, dz * dz))));
                 }
-                if (act) c_env += (unsigned long long)nc * (unsigned long long)(env.n_sph + env.n_box + env.n_cyl);
+                if (act) c_env += (unsigned long long)(env.n_sph + env.n_box + env.n_cyl);
                 const float rlo = fmaxf(rad - eps, 0.f), rhi = rad + eps;
                 const float Rb = rad + ro_max;
-                bool hit = false;
-                unsigned unsure = 0u;
-#pragma unroll
-                for (int cc = 0; cc < kEnvC; ++cc) {
-                    if (!act || cc >= nc) continue;
-                    const bool h = (mb[cc] < rlo * rlo) || (ms[cc] < -2.f * Rb * eps);
-                    hit = hit || h;
-                    if (!h && ((mb[cc] <= rhi * rhi) || (ms[cc] <= fmaf(2.f * Rb, eps, eps * eps)))) unsure |= 1u << cc;
+                bool hit = false, unsure = false;
+                if (act) {
+                    hit = (mb < rlo * rlo) || (ms < -2.f * Rb * eps);
+                    unsure = !hit && ((mb <= rhi * rhi) || (ms <= fmaf(2.f * Rb, eps, eps * eps)));
                 }
+                const int sa = act ? tm.slot_sphere[a] : 0;
                 if (env.n_pts > 0 && act) {
                     const float Rp = rad + env.pt_radius;
-                    for (int cc = 0; cc < nc; ++cc) {
-                        const int c = c0 + cc;
-                        const float4 Xr = rec[c * S + a];
-                        const float4 O = gc[c * G + tm.s_group[a]];
-                        const float xs[3] = { Xr.x + O.x, Xr.y + O.y, Xr.z + O.z };
-                        int lo3[3], hi3[3];
-                        const float reach = Rp + eps;
+                    const float xs[3] = { x, y, z };
+                    int lo3[3], hi3[3];
+                    const float reach = Rp + eps;
 #pragma unroll
-                        for (int d = 0; d < 3; ++d) {
-                            const int l = (int)floorf((xs[d] - reach - env.grid_lo[d]) * env.grid_inv);
-                            const int h = (int)floorf((xs[d] + reach - env.grid_lo[d]) * env.grid_inv);
-                            lo3[d] = l < 0 ? 0 : l;
-                            hi3[d] = h >= env.grid_dim[d] ? env.grid_dim[d] - 1 : h;
-                        }
-                        const float plo = fmaxf(Rp - eps, 0.f), phi = Rp + eps;
-                        const float plo2 = plo * plo, phi2 = phi * phi;
-                        if (lo3[0] <= hi3[0])
-                            for (int cz = lo3[2]; cz <= hi3[2]; ++cz)
-                                for (int cy = lo3[1]; cy <= hi3[1]; ++cy) {
-                                    const int row = (cz * env.grid_dim[1] + cy) * env.grid_dim[0];
-                                    const int pb = env.cell_start[row + lo3[0]];
-                                    const int pe = env.cell_start[row + hi3[0] + 1];
-                                    for (int p = pb; p < pe; ++p) {
-                                        const float4 Pt = env.pts32[p];
-                                        const float dx = xs[0] - Pt.x, dy = xs[1] - Pt.y, dz = xs[2] - Pt.z;
-                                        const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                                        if (d2 <= phi2) {
-                                            if (d2 < plo2) hit = true;
-                                            else if (!hit && !*(volatile int*)&s_hit)
-                                                push_recheck(cd, q, s_t[c], RK_ENV_PT, a, p, 0u);
-                                        }
+                    for (int d = 0; d < 3; ++d) {
+                        const int l = (int)floorf((xs[d] - reach - env.grid_lo[d]) * env.grid_inv);
+                        const int h = (int)floorf((xs[d] + reach - env.grid_lo[d]) * env.grid_inv);
+                        lo3[d] = l < 0 ? 0 : l;
+                        hi3[d] = h >= env.grid_dim[d] ? env.grid_dim[d] - 1 : h;
+                    }
+                    const float plo = fmaxf(Rp - eps, 0.f), phi = Rp + eps;
+                    const float plo2 = plo * plo, phi2 = phi * phi;
+                    if (lo3[0] <= hi3[0])
+                        for (int cz = lo3[2]; cz <= hi3[2]; ++cz)
+                            for (int cy = lo3[1]; cy <= hi3[1]; ++cy) {
+                                const int crow = (cz * env.grid_dim[1] + cy) * env.grid_dim[0];
+                                const int pb = env.cell_start[crow + lo3[0]];
+                                const int pe = env.cell_start[crow + hi3[0] + 1];
+                                for (int p = pb; p < pe; ++p) {
+                                    const float4 Pt = env.pts32[p];
+                                    const float dx = x - Pt.x, dy = y - Pt.y, dz = z - Pt.z;
+                                    const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                                    if (d2 <= phi2) {
+                                        if (d2 < plo2) hit = true;
+                                        else if (!hit && !flag_read(&s_hit))
+                                            push_recheck(cd, q, s_t[c], RK_ENV_PT, sa, p, 0u);
                                     }
                                 }
-                    }
+                            }
                 }
                 if (unsure && !(hit && !exhaustive)) {
                     // rare: find the near obstacles and queue each for FP64 re-evaluation
-                    for (int cc = 0; cc < nc; ++cc) {
-                        if (!(unsure & (1u << cc))) continue;
-                        const int c = c0 + cc;
-                        const float4 Xr = rec[c * S + a];
-                        const float4 O = gc[c * G + tm.s_group[a]];
-                        const float x = Xr.x + O.x, y = Xr.y + O.y, z = Xr.z + O.z;
-                        for (int o = 0; o < env.n_box; ++o) {
-                            const float v = box_val(x, y, z, env.box32 + o * 16);
-                            if (v < rlo * rlo) hit = true;
-                            else if (v <= rhi * rhi && !hit && !*(volatile int*)&s_hit)
-                                push_recheck(cd, q, s_t[c], RK_ENV_BOX, a, o, 0u);
-                        }
-                        for (int o = 0; o < env.n_cyl; ++o) {
-                            const float v = cyl_val(x, y, z, env.cyl32 + o * 8);
-                            if (v < rlo * rlo) hit = true;
-                            else if (v <= rhi * rhi && !hit && !*(volatile int*)&s_hit)
-                                push_recheck(cd, q, s_t[c], RK_ENV_CYL, a, o, 0u);
-                        }
-                        for (int o = 0; o < env.n_sph; ++o) {
-                            const float4 Ob = env.sph32[o];
-                            const float dx = x - Ob.x, dy = y - Ob.y, dz = z - Ob.z;
-                            const int cl = classify(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), rad + Ob.w, eps);
-                            if (cl == 1) hit = true;
-                            else if (cl == 2 && !hit && !*(volatile int*)&s_hit)
-                                push_recheck(cd, q, s_t[c], RK_ENV_SPH, a, o, 0u);
-                        }
+                    for (int o = 0; o < env.n_box; ++o) {
+                        const float v = box_val(x, y, z, (CFloat*)(env.box32 + o * 16));
+                        if (v < rlo * rlo) hit = true;
+                        else if (v <= rhi * rhi && !hit && !flag_read(&s_hit))
+                            push_recheck(cd, q, s_t[c], RK_ENV_BOX, sa, o, 0u);
                     }
-                }
-                if (__ballot(hit) && lane == 0) s_hit = 1;
-            }
-            // self-collision pairs: a lane keeps one pair for the tile's timesteps
-            const int nsc = (tm.n_self + 63) >> 6;
-            for (int task = wave; task < nsc; task += kWavesPerWG) {
-                if (!exhaustive && *(volatile int*)&s_hit) break;
-                const int p = task * 64 + lane;
-                bool hit = false;
-                if (p < tm.n_self) {
-                    const int2 pr = tm.self_pairs[p];
-                    const int ga = tm.s_group[pr.x], gb = tm.s_group[pr.y];
-                    for (int c = 0; c < nv; ++c) {
-                        const float4 A = rec[c * S + pr.x];
-                        const float4 B = rec[c * S + pr.y];
-                        const float4 OA = gc[c * G + ga];
-                        const float4 OB = gc[c * G + gb];
-                        const float dx = (A.x - B.x) + (OA.x - OB.x);
-                        const float dy = (A.y - B.y) + (OA.y - OB.y);
-                        const float dz = (A.z - B.z) + (OA.z - OB.z);
-                        const int cl = classify(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), A.w + B.w, eps);
+                    for (int o = 0; o < env.n_cyl; ++o) {
+                        const float v = cyl_val(x, y, z, (CFloat*)(env.cyl32 + o * 8));
+                        if (v < rlo * rlo) hit = true;
+                        else if (v <= rhi * rhi && !hit && !flag_read(&s_hit))
+                            push_recheck(cd, q, s_t[c], RK_ENV_CYL, sa, o, 0u);
+                    }
+                    for (int o = 0; o < env.n_sph; ++o) {
+                        const float* ob = &env.sph32[o].x;
+                        const float dx = x - cloadf(ob), dy = y - cloadf(ob + 1), dz = z - cloadf(ob + 2);
+                        const int cl = classify(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), rad + cloadf(ob + 3), eps);
                         if (cl == 1) hit = true;
-                        else if (cl == 2 && !hit && !*(volatile int*)&s_hit)
-                            push_recheck(cd, q, s_t[c], RK_SELF, pr.x, pr.y, 0u);
+                        else if (cl == 2 && !hit && !flag_read(&s_hit))
+                            push_recheck(cd, q, s_t[c], RK_ENV_SPH, sa, o, 0u);
                     }
                 }
-                c_self += (unsigned long long)__popcll(__ballot(p < tm.n_self)) * (unsigned long long)nv;
                 if (__ballot(hit) && lane == 0) s_hit = 1;
             }
         }
 
-        // --- robot-robot tests.  Lane = sphere a of the lower robot; the partner's
-        // spheres come in groups of 16, centred on the group, and rotate through the
-        // 16-lane rows.  Coarse expanded-form bound first; only lanes within the
-        // bound's uncertainty revisit their partners directly.
-        if (do_rr && !(KIND == 0 && !exhaustive && do_env && *(volatile int*)&s_hit)) {
-            const float rho = sqrtf(__uint_as_float(s_rho2));
-            const float Rm = 2.f * tm.r_max;
+        // --- sphere-pair tests as 16 x 16 blocks on the matrix cores.  For slots a
+        // (rows, group ga) and b (columns, group gb) at one timestep,
+        //   D(a, b) = w_a + w_b - 2 p_a.p_b - 2 r_a r_b = |p_a - p_b|^2 - (r_a + r_b)^2,
+        // the K = 4 product by one MFMA with the accumulator preset to w_a, then a
+        // column minimum plus w_b on the vector unit.  A robot-robot task takes one
+        // group of a robot against every group of one higher robot, a self task one
+        // block of a robot's own groups (MV with environment checking) with the pairs
+        // outside its self list masked; either runs through all timesteps of the tile.
+        // Lanes whose minimum lies within the bound's uncertainty revisit their
+        // pairs directly.
+        const bool do_self = do_env && tm.n_sblocks > 0;
+        if ((do_rr || do_self) && !(KIND == 0 && !exhaustive && flag_read(&s_hit))) {
+            const float rho2 = __uint_as_float(s_rho2);
+            const float rm = tm.r_max;
             const float u = 5.9604645e-8f;
-            const float span = 2.f * rho + Rm + eps;
-            const float e_err = 12.f * u * (span * span + Rm * Rm);
+            // |D_fp32 - D| <= 24 u (rho^2 + rm^2) for |p| <= rho, r <= rm: 4 u from each
+            // of w_a and w_b, 12 u from the MFMA's four fused steps (partial sums up to
+            // 3 (rho^2 + rm^2)), 4 u from adding w_b; 32 u leaves a margin
+            const float e_err = 32.f * u * (rho2 + rm * rm) + 1.0e-30f;
+            const float Rm = 2.f * rm;
             const float e_hi = e_err + fmaf(2.f * Rm, eps, eps * eps);
             const float e_lo = -(e_err + 2.f * Rm * eps);
-            const int ntk = tm.n_rr_tasks;
-            const int ntask = nv * ntk;
-            for (int task = wave; task < ntask; task += kWavesPerWG) {
-                const int c = task / ntk;
-                if (KIND == 0) {
-                    if (!exhaustive && *(volatile int*)&s_hit) break;
-                } else if (!exhaustive) {
-                    const unsigned best = *(volatile unsigned*)&s_key;
-                    if (best != 0xFFFFFFFFu && best < (unsigned)s_t[c] * (unsigned)tm.P) break;
+            const int n_rt = do_rr ? tm.n_rr_tasks : 0;
+            const int n_st = do_self ? tm.n_sblocks : 0;
+            const int ntask = n_rt + n_st;
+            const int i16 = lane & 15;
+            const int q4 = lane >> 4;
+            for (int k = wave; k < ntask; k += kWavesPerWG) {
+                if (KIND == 0 && !exhaustive && flag_read(&s_hit)) break;
+                const bool is_rr = k < n_rt;
+                int ga, g0, g1, rb, ra, ntests;
+                unsigned long long m0 = ~0ull, m1 = ~0ull, m2 = ~0ull, m3 = ~0ull;
+                if (is_rr) {
+                    const int* tk = tm.rr_rec + 8 * k;
+                    ga = cload(tk + 0);
+                    rb = cload(tk + 1);
+                    g0 = cload(tk + 2);
+                    g1 = cload(tk + 3);
+                    ntests = cload(tk + 4);
+                    ra = cload(tk + 5);
+                } else {
+                    const int* sb = tm.sblocks + 8 * (k - n_rt);
+                    ga = cload(sb + 0);
+                    g0 = cload(sb + 1);
+                    g1 = g0 + 1;
+                    ntests = cload(sb + 2);
+                    rb = cload(sb + 3);
+                    ra = rb;
+                    const unsigned long long* mk = tm.sb_mask + 4 * (k - n_rt);
+                    m0 = cload64(mk + 0);
+                    m1 = cload64(mk + 1);
+                    m2 = cload64(mk + 2);
+                    m3 = cload64(mk + 3);
                 }
-                const int2 tk = tm.rr_tasks[task - c * ntk];
-                const int rb = tk.y;
-                const int a = tk.x * 64 + lane;
-                const bool act = a < S && tm.s_robot[a] < rb;
-                float XA0 = 0.f, XA1 = 0.f, XA2 = 0.f, ra = 0.f;
-                if (act) {
-                    const float4 Xr = rec[c * S + a];
-                    const float4 O = gc[c * G + tm.s_group[a]];
-                    XA0 = Xr.x + O.x; XA1 = Xr.y + O.y; XA2 = Xr.z + O.z; ra = Xr.w;
-                }
-                const float ar = -2.f * ra;
-                const float nra2 = -ra * ra;
-                const int g0 = tm.r_group_off[rb];
-                const int g1 = tm.r_group_off[rb + 1];
-                float best = 3.0e38f;
-                for (int g = g0; g < g1; ++g) {
-                    const int2 rg = tm.g_range[g];
-                    const float4 O = gc[c * G + g];
-                    const float px = XA0 - O.x, py = XA1 - O.y, pz = XA2 - O.z;
-                    const float wa = act ? fmaf(px, px, fmaf(py, py, fmaf(pz, pz, nra2))) : 1.0e30f;
-                    const int lb = rg.x + (lane & 15);
-                    float4 B = make_float4(0.f, 0.f, 0.f, 0.f);
-                    float bw = 1.0e30f;
-                    if (lb < rg.y) {
-                        B = rec[c * S + lb];
-                        bw = rw[c * S + lb];
+                const unsigned pair = KIND == 0 ? 0u : pair_index(ra, rb, n);
+                for (int c = 0; c < nv; ++c) {
+                    const int t = s_t[c];
+                    if (KIND == 0) {
+                        if (!exhaustive && flag_read(&s_hit)) break;
+                    } else if (!exhaustive) {
+                        const unsigned known = flag_read(&s_key);
+                        if (known != 0xFFFFFFFFu && known < (unsigned)t * (unsigned)tm.P) break;
                     }
-                    const float m = rr_group_min(bw, B.x, B.y, B.z, B.w, -2.f * px, -2.f * py, -2.f * pz, ar);
-                    best = fminf(best, m + wa);
-                }
-                c_rr += (unsigned long long)__popcll(__ballot(act)) *
-                        (unsigned long long)(tm.r_sphere_off[rb + 1] - tm.r_sphere_off[rb]);
-                bool hit = best < e_lo;
-                const bool unsure = !hit && best < e_hi;
-                if (__ballot(unsure)) {
-                    if (unsure) {
-                        for (int b = tm.r_sphere_off[rb]; b < tm.r_sphere_off[rb + 1] && !hit; ++b) {
-                            const float4 Br = rec[c * S + b];
-                            const float4 O = gc[c * G + tm.s_group[b]];
-                            const float dx = XA0 - (Br.x + O.x), dy = XA1 - (Br.y + O.y), dz = XA2 - (Br.z + O.z);
-                            const int cl = classify(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), ra + Br.w, eps);
-                            if (cl == 1) {
-                                hit = true;
-                            } else if (cl == 2) {
-                                // a near test matters only below the best known outcome
-                                const unsigned key = KIND == 0 ? 0u
-                                                   : (unsigned)s_t[c] * (unsigned)tm.P +
-                                                         pair_index(tm.s_robot[a], rb, n);
-                                const bool open = KIND == 0 ? !*(volatile int*)&s_hit
-                                                            : key < *(volatile unsigned*)&s_key;
-                                if (open) push_recheck(cd, q, s_t[c], RK_RR, a, b, key);
+                    if (is_rr) c_rr += (unsigned long long)ntests;
+                    else c_self += (unsigned long long)ntests;
+                    const float* base = sp + c * 5 * GSp;
+                    const float aop = -2.f * base[q4 * GSp + ga * 16 + i16];
+                    float4 cw = *reinterpret_cast<const float4*>(base + 4 * GSp + ga * 16 + 4 * q4);
+                    if (!is_rr) {
+                        cw.x = lane_select(m0, cw.x, kFar);
+                        cw.y = lane_select(m1, cw.y, kFar);
+                        cw.z = lane_select(m2, cw.z, kFar);
+                        cw.w = lane_select(m3, cw.w, kFar);
+                    }
+                    const floatx4 acc = { cw.x, cw.y, cw.z, cw.w };
+                    // up to four independent MFMAs in flight before their results are reduced
+                    float best = 3.0e38f;
+                    int g = g0;
+                    for (; g + 4 <= g1; g += 4) {
+                        float bop[4], wb[4];
+                        floatx4 d[4];
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            bop[v] = base[q4 * GSp + (g + v) * 16 + i16];
+                            wb[v] = base[4 * GSp + (g + v) * 16 + i16];
+                        }
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) d[v] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, bop[v], acc, 0, 0, 0);
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) best = block_min(d[v], wb[v], best);
+                    }
+                    for (; g < g1; ++g) {
+                        const float bop = base[q4 * GSp + g * 16 + i16];
+                        const float wb = base[4 * GSp + g * 16 + i16];
+                        const floatx4 d = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, bop, acc, 0, 0, 0);
+                        best = block_min(d, wb, best);
+                    }
+                    const unsigned key = KIND == 0 ? 0u : (unsigned)t * (unsigned)tm.P + pair;
+                    bool hit = best < e_lo;
+                    const bool unsure = !hit && best < e_hi;
+                    if (!__ballot(hit) && __ballot(unsure)) {
+                        // rare: this lane's pairs (rows 4 q4 .. 4 q4 + 3, column i16 of each
+                        // block) in the direct form
+                        if (unsure) {
+                            const int rk = is_rr ? RK_RR : RK_SELF;
+                            for (int gg = g0; gg < g1 && !hit; ++gg) {
+                                const int bs = gg * 16 + i16;
+                                const float br = base[3 * GSp + bs];
+                                if (!(br > 0.f)) continue;
+                                const float bx = base[bs], by = base[GSp + bs], bz = base[2 * GSp + bs];
+#pragma unroll
+                                for (int r = 0; r < 4; ++r) {
+                                    const unsigned long long mr = r == 0 ? m0 : r == 1 ? m1 : r == 2 ? m2 : m3;
+                                    const int as = ga * 16 + 4 * q4 + r;
+                                    const float ar = base[3 * GSp + as];
+                                    if (!(ar > 0.f) || !((mr >> lane) & 1ull)) continue;
+                                    const float dx = base[as] - bx, dy = base[GSp + as] - by, dz = base[2 * GSp + as] - bz;
+                                    const int cl = classify(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), ar + br, eps);
+                                    if (cl == 1) {
+                                        hit = true;
+                                    } else if (cl == 2) {
+                                        // a near test matters only below the best known outcome
+                                        const bool open = KIND == 0 ? !flag_read(&s_hit) : key < flag_read(&s_key);
+                                        if (open) push_recheck(cd, q, t, rk, tm.slot_sphere[as], tm.slot_sphere[bs], key);
+                                    }
+                                }
                             }
                         }
                     }
-                }
-                if (KIND == 0) {
-                    if (__ballot(hit) && lane == 0) s_hit = 1;
-                } else if (__ballot(hit)) {
-                    unsigned key = 0xFFFFFFFFu;
-                    if (hit) key = (unsigned)s_t[c] * (unsigned)tm.P + pair_index(tm.s_robot[a], rb, n);
-                    key = wave_min_u32(key);
-                    if (lane == 0) atomicMin(&s_key, key);
+                    if (__ballot(hit)) {
+                        if (lane == 0) {
+                            if (KIND == 0) s_hit = 1;
+                            else atomicMin(&s_key, key);
+                        }
+                        // FFC: this pair's later timesteps have larger keys
+                        if (KIND == 1 && !exhaustive) break;
+                    }
                 }
             }
         }

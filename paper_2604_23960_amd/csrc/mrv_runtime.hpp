@@ -82,7 +82,7 @@ struct Scratch {
     }
 };
 
-void ensure_scratch(Scratch& sc, size_t bins, size_t queries);
+void ensure_scratch(Scratch& sc, size_t bins, size_t queries, hipStream_t stream);
 // Enlarge the near-contact queue to hold `pushed` records (with 25% headroom).
 // False when it already does or the size would pass kMaxRecheckCap.  The caller
 // must have drained every launch that uses sc.
