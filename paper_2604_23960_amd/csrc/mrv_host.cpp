@@ -217,16 +217,6 @@ int build_team(mrv_ctx ctx, const mrv_robot_desc* robots, int n, TeamHost& out)
             slot_sphere[g * 16 + (s2 - g_range[2 * g])] = s2;
             sphere_slot[s2] = g * 16 + (s2 - g_range[2 * g]);
         }
-    // robot-robot tasks: each group against every higher robot, one 8-int record each
-    std::vector<int> rr_tasks;
-    for (int r = 0; r < n; ++r)
-        for (int g = r_group_off[r]; g < r_group_off[r + 1]; ++g)
-            for (int rb = r + 1; rb < n; ++rb) {
-                const int rec[8] = { g, rb, r_group_off[rb], r_group_off[rb + 1],
-                                     (g_range[2 * g + 1] - g_range[2 * g]) * (r_sphere_off[rb + 1] - r_sphere_off[rb]),
-                                     r, 0, 0 };
-                rr_tasks.insert(rr_tasks.end(), rec, rec + 8);
-            }
     // self blocks: for each pair of groups (ga <= gb) holding self pairs, one lane
     // mask per accumulator register r: bit l set when the pair (row 4 (l / 16) + r
     // of ga, column l % 16 of gb) is in the list (each unordered pair once)
@@ -249,6 +239,22 @@ int build_team(mrv_ctx ctx, const mrv_robot_desc* robots, int n, TeamHost& out)
         for (uint64_t m : kv.second) sb_mask.push_back(m);
         n_self_unique += cnt;
     }
+    // pair tasks, one per group ga: its self blocks [sb0, sb1) (sorted by ga) and the
+    // groups of every higher robot from gstart on; 8 ints each
+    std::vector<int> gtask;
+    {
+        size_t sbi = 0;
+        const size_t nsb = sblocks.size() / 8;
+        for (int g = 0; g < G; ++g) {
+            const int r = s_robot[g_range[2 * g]];
+            const int sb0 = (int)sbi;
+            int self_tests = 0;
+            while (sbi < nsb && sblocks[8 * sbi] == g) self_tests += sblocks[8 * sbi++ + 2];
+            const int rec[8] = { g, r, sb0, (int)sbi, r_group_off[r + 1],
+                                 (g_range[2 * g + 1] - g_range[2 * g]) * (S - r_sphere_off[r + 1]), self_tests, 0 };
+            gtask.insert(gtask.end(), rec, rec + 8);
+        }
+    }
     float r_max = 0.f;
     for (int s2 = 0; s2 < S; ++s2) r_max = std::max(r_max, s_local32[s2 * 4 + 3]);
     long long rr_per_t = 0;
@@ -261,7 +267,7 @@ int build_team(mrv_ctx ctx, const mrv_robot_desc* robots, int n, TeamHost& out)
                  o_fo = pk.add(r_frame_off), o_b32 = pk.add(base32), o_b64 = pk.add(base64),
                  o_jt = pk.add(j_type), o_j32 = pk.add(j32), o_j64 = pk.add(j64), o_sr = pk.add(s_robot),
                  o_ss = pk.add(s_slot), o_sl = pk.add(s_lframe), o_l32 = pk.add(s_local32),
-                 o_l64 = pk.add(s_local64), o_rt = pk.add(rr_tasks), o_sg = pk.add(s_group),
+                 o_l64 = pk.add(s_local64), o_rt = pk.add(gtask), o_sg = pk.add(s_group),
                  o_gr = pk.add(g_range), o_rg = pk.add(r_group_off), o_ss2 = pk.add(slot_sphere),
                  o_sb = pk.add(sblocks), o_sm = pk.add(sb_mask);
     const TeamDev blank{};
@@ -274,7 +280,6 @@ int build_team(mrv_ctx ctx, const mrv_robot_desc* robots, int n, TeamHost& out)
     t.S = S;
     t.F = F;
     t.n_self = n_self_unique;
-    t.n_rr_tasks = (int)rr_tasks.size() / 8;
     t.n_sblocks = (int)sblocks.size() / 8;
     t.GS = GS;
     t.GSp = GS + 16;
@@ -310,7 +315,7 @@ int build_team(mrv_ctx ctx, const mrv_robot_desc* robots, int n, TeamHost& out)
     t.s_lframe = (const int*)at(o_sl);
     t.s_local32 = (const float4*)at(o_l32);
     t.s_local64 = (const double*)at(o_l64);
-    t.rr_rec = (const int*)at(o_rt);
+    t.gtask = (const int*)at(o_rt);
     t.slot_sphere = (const int*)at(o_ss2);
     t.sblocks = (const int*)at(o_sb);
     t.sb_mask = (const unsigned long long*)at(o_sm);

@@ -30,7 +30,6 @@ struct TeamDev {
     int S;                 // total spheres
     int F;                 // frame slots per timestep: sum over robots of (n_joints + 1)
     int n_self;            // distinct self-collision pairs
-    int n_rr_tasks;        // (group, higher robot) tasks per timestep
     int n_sblocks;         // 16 x 16 self blocks per timestep
     int P;                 // robot pairs n(n-1)/2
     int max_dof;
@@ -59,8 +58,8 @@ struct TeamDev {
     const int* s_group;         // [S] group of each sphere
     const int2* g_range;        // [G] sphere range [begin, end) of each group
     const int* r_group_off;     // [n+1] first group of each robot
-    const int* rr_rec;          // [n_rr_tasks][8] group ga, higher robot rb, rb's groups [g0, g1),
-                                // tests (spheres of ga x spheres of rb), robot of ga, 0, 0
+    const int* gtask;           // [G][8] pair task of group ga: ga, its robot, self blocks [sb0, sb1),
+                                // first group of the higher robots, robot-robot tests, self tests, 0
     const int* slot_sphere;     // [GS] sphere of each slot, -1 for padding
     const int* sblocks;         // [n_sblocks][8] row group, column group, pairs, robot, 0, 0, 0, 0
     const unsigned long long* sb_mask;   // [n_sblocks][4] lane masks, one per accumulator register

@@ -512,7 +512,8 @@ __device__ __forceinline__ float cyl_val(float x, float y, float z, CFloat* Y)
     const float vx = x - Y[0], vy = y - Y[1], vz = z - Y[2];
     const float h = fmaf(vx, Y[3], fmaf(vy, Y[4], vz * Y[5]));
     const float wx = fmaf(-h, Y[3], vx), wy = fmaf(-h, Y[4], vy), wz = fmaf(-h, Y[5], vz);
-    const float sr = sqrtf(fmaf(wx, wx, fmaf(wy, wy, wz * wz)));
+    // hardware square root (within 1 ulp): the near band absorbs far more
+    const float sr = __builtin_amdgcn_sqrtf(fmaf(wx, wx, fmaf(wy, wy, wz * wz)));
     const float er = fmaxf(sr - Y[7], 0.f);
     const float ea = fmaxf(fabsf(h) - Y[6], 0.f);
     return fmaf(er, er, ea * ea);
@@ -525,6 +526,37 @@ __device__ __forceinline__ int classify(float d2, float R, float eps)
     if (d2 > hi * hi) return 0;
     const float lo = fmaxf(R - eps, 0.f);
     return d2 < lo * lo ? 1 : 2;
+}
+
+// The pairs one lane covers in block (ga, gb) -- rows 4 (lane / 16) .. + 3 of ga
+// against column lane % 16 of gb -- in the direct form, masked by mk (the block's
+// four per-register lane masks; null: every pair).  Near pairs below the best
+// known outcome are queued.  Returns whether a pair collides.
+__device__ bool direct_block(const CallDev& cd, const TeamDev& tm, const float* base, int GSp, int ga, int gb, int lane,
+                             const unsigned long long* mk, float eps, int q, int t, int rk, unsigned key, int* s_hit,
+                             unsigned* s_key, bool mv)
+{
+    const int bs = gb * 16 + (lane & 15);
+    const float br = base[3 * GSp + bs];
+    if (!(br > 0.f)) return false;
+    const float bx = base[bs], by = base[GSp + bs], bz = base[2 * GSp + bs];
+    bool hit = false;
+    for (int r = 0; r < 4; ++r) {
+        if (mk && !((cload64(mk + r) >> lane) & 1ull)) continue;
+        const int as = ga * 16 + 4 * (lane >> 4) + r;
+        const float ar = base[3 * GSp + as];
+        if (!(ar > 0.f)) continue;
+        const float dx = base[as] - bx, dy = base[GSp + as] - by, dz = base[2 * GSp + as] - bz;
+        const int cl = classify(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), ar + br, eps);
+        if (cl == 1) {
+            hit = true;
+        } else if (cl == 2) {
+            // a near test matters only below the best known outcome
+            const bool open = mv ? !flag_read(s_hit) : key < flag_read(s_key);
+            if (open) push_recheck(cd, q, t, rk, tm.slot_sphere[as], tm.slot_sphere[bs], key);
+        }
+    }
+    return hit;
 }
 
 // FP32 frames of robot r at timestep t: the configuration is interpolated in FP64
@@ -874,12 +906,11 @@ __global__ __launch_bounds__(kWG, 4) void k_validate(CallDev cd)
         // (rows, group ga) and b (columns, group gb) at one timestep,
         //   D(a, b) = w_a + w_b - 2 p_a.p_b - 2 r_a r_b = |p_a - p_b|^2 - (r_a + r_b)^2,
         // the K = 4 product by one MFMA with the accumulator preset to w_a, then a
-        // column minimum plus w_b on the vector unit.  A robot-robot task takes one
-        // group of a robot against every group of one higher robot, a self task one
-        // block of a robot's own groups (MV with environment checking) with the pairs
-        // outside its self list masked; either runs through all timesteps of the tile.
-        // Lanes whose minimum lies within the bound's uncertainty revisit their
-        // pairs directly.
+        // column minimum plus w_b on the vector unit.  One task per group ga runs,
+        // timestep by timestep, the self blocks of ga (MV with environment checking;
+        // pairs outside the self list masked) and its blocks against every group of
+        // the higher robots.  Lanes whose minimum lies within the bound's
+        // uncertainty revisit their pairs directly.
         const bool do_self = do_env && tm.n_sblocks > 0;
         if ((do_rr || do_self) && !(KIND == 0 && !exhaustive && flag_read(&s_hit))) {
             const float rho2 = __uint_as_float(s_rho2);
@@ -892,39 +923,19 @@ __global__ __launch_bounds__(kWG, 4) void k_validate(CallDev cd)
             const float Rm = 2.f * rm;
             const float e_hi = e_err + fmaf(2.f * Rm, eps, eps * eps);
             const float e_lo = -(e_err + 2.f * Rm * eps);
-            const int n_rt = do_rr ? tm.n_rr_tasks : 0;
-            const int n_st = do_self ? tm.n_sblocks : 0;
-            const int ntask = n_rt + n_st;
             const int i16 = lane & 15;
             const int q4 = lane >> 4;
-            for (int k = wave; k < ntask; k += kWavesPerWG) {
+            for (int k = wave; k < G; k += kWavesPerWG) {
                 if (KIND == 0 && !exhaustive && flag_read(&s_hit)) break;
-                const bool is_rr = k < n_rt;
-                int ga, g0, g1, rb, ra, ntests;
-                unsigned long long m0 = ~0ull, m1 = ~0ull, m2 = ~0ull, m3 = ~0ull;
-                if (is_rr) {
-                    const int* tk = tm.rr_rec + 8 * k;
-                    ga = cload(tk + 0);
-                    rb = cload(tk + 1);
-                    g0 = cload(tk + 2);
-                    g1 = cload(tk + 3);
-                    ntests = cload(tk + 4);
-                    ra = cload(tk + 5);
-                } else {
-                    const int* sb = tm.sblocks + 8 * (k - n_rt);
-                    ga = cload(sb + 0);
-                    g0 = cload(sb + 1);
-                    g1 = g0 + 1;
-                    ntests = cload(sb + 2);
-                    rb = cload(sb + 3);
-                    ra = rb;
-                    const unsigned long long* mk = tm.sb_mask + 4 * (k - n_rt);
-                    m0 = cload64(mk + 0);
-                    m1 = cload64(mk + 1);
-                    m2 = cload64(mk + 2);
-                    m3 = cload64(mk + 3);
-                }
-                const unsigned pair = KIND == 0 ? 0u : pair_index(ra, rb, n);
+                const int* tk = tm.gtask + 8 * k;
+                const int ga = cload(tk + 0);
+                const int ra = cload(tk + 1);
+                const int sb0 = do_self ? cload(tk + 2) : 0;
+                const int sb1 = do_self ? cload(tk + 3) : 0;
+                const int gs = do_rr ? cload(tk + 4) : G;
+                const unsigned long long rr_tests = do_rr ? (unsigned long long)cload(tk + 5) : 0ull;
+                const unsigned long long self_tests = do_self ? (unsigned long long)cload(tk + 6) : 0ull;
+                if (sb0 == sb1 && gs >= G) continue;
                 for (int c = 0; c < nv; ++c) {
                     const int t = s_t[c];
                     if (KIND == 0) {
@@ -933,80 +944,91 @@ __global__ __launch_bounds__(kWG, 4) void k_validate(CallDev cd)
                         const unsigned known = flag_read(&s_key);
                         if (known != 0xFFFFFFFFu && known < (unsigned)t * (unsigned)tm.P) break;
                     }
-                    if (is_rr) c_rr += (unsigned long long)ntests;
-                    else c_self += (unsigned long long)ntests;
+                    c_rr += rr_tests;
+                    c_self += self_tests;
                     const float* base = sp + c * 5 * GSp;
                     const float aop = -2.f * base[q4 * GSp + ga * 16 + i16];
-                    float4 cw = *reinterpret_cast<const float4*>(base + 4 * GSp + ga * 16 + 4 * q4);
-                    if (!is_rr) {
-                        cw.x = lane_select(m0, cw.x, kFar);
-                        cw.y = lane_select(m1, cw.y, kFar);
-                        cw.z = lane_select(m2, cw.z, kFar);
-                        cw.w = lane_select(m3, cw.w, kFar);
-                    }
-                    const floatx4 acc = { cw.x, cw.y, cw.z, cw.w };
-                    // up to four independent MFMAs in flight before their results are reduced
-                    float best = 3.0e38f;
-                    int g = g0;
-                    for (; g + 4 <= g1; g += 4) {
-                        float bop[4], wb[4];
-                        floatx4 d[4];
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) {
-                            bop[v] = base[q4 * GSp + (g + v) * 16 + i16];
-                            wb[v] = base[4 * GSp + (g + v) * 16 + i16];
+                    const float4 cw = *reinterpret_cast<const float4*>(base + 4 * GSp + ga * 16 + 4 * q4);
+                    bool found = false;
+
+                    // self blocks of ga
+                    if (sb0 < sb1) {
+                        float best = 3.0e38f;
+                        for (int sb = sb0; sb < sb1; ++sb) {
+                            const int gb = cload(tm.sblocks + 8 * sb + 1);
+                            const unsigned long long* mk = tm.sb_mask + 4 * sb;
+                            const floatx4 acc = { lane_select(cload64(mk + 0), cw.x, kFar), lane_select(cload64(mk + 1), cw.y, kFar),
+                                                  lane_select(cload64(mk + 2), cw.z, kFar), lane_select(cload64(mk + 3), cw.w, kFar) };
+                            const float bop = base[q4 * GSp + gb * 16 + i16];
+                            const float wb = base[4 * GSp + gb * 16 + i16];
+                            const floatx4 d = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, bop, acc, 0, 0, 0);
+                            best = block_min(d, wb, best);
                         }
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) d[v] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, bop[v], acc, 0, 0, 0);
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) best = block_min(d[v], wb[v], best);
+                        bool hit = best < e_lo;
+                        const bool unsure = !hit && best < e_hi;
+                        if (!__ballot(hit) && __ballot(unsure) && unsure) {
+                            for (int sb = sb0; sb < sb1 && !hit; ++sb) {
+                                const int gb = cload(tm.sblocks + 8 * sb + 1);
+                                const unsigned long long* mk = tm.sb_mask + 4 * sb;
+                                hit = direct_block(cd, tm, base, GSp, ga, gb, lane, mk, eps, q, t, RK_SELF, 0u, &s_hit, &s_key, true);
+                            }
+                        }
+                        if (__ballot(hit)) {
+                            found = true;
+                            if (lane == 0) s_hit = 1;
+                        }
                     }
-                    for (; g < g1; ++g) {
-                        const float bop = base[q4 * GSp + g * 16 + i16];
-                        const float wb = base[4 * GSp + g * 16 + i16];
-                        const floatx4 d = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, bop, acc, 0, 0, 0);
-                        best = block_min(d, wb, best);
-                    }
-                    const unsigned key = KIND == 0 ? 0u : (unsigned)t * (unsigned)tm.P + pair;
-                    bool hit = best < e_lo;
-                    const bool unsure = !hit && best < e_hi;
-                    if (!__ballot(hit) && __ballot(unsure)) {
-                        // rare: this lane's pairs (rows 4 q4 .. 4 q4 + 3, column i16 of each
-                        // block) in the direct form
-                        if (unsure) {
-                            const int rk = is_rr ? RK_RR : RK_SELF;
-                            for (int gg = g0; gg < g1 && !hit; ++gg) {
-                                const int bs = gg * 16 + i16;
-                                const float br = base[3 * GSp + bs];
-                                if (!(br > 0.f)) continue;
-                                const float bx = base[bs], by = base[GSp + bs], bz = base[2 * GSp + bs];
+
+                    // robot-robot blocks against the higher robots
+                    if (gs < G && !(found && !exhaustive)) {
+                        const floatx4 acc = { cw.x, cw.y, cw.z, cw.w };
+                        const int rb_end = KIND == 0 ? ra + 2 : n;   // MV: all higher robots in one sweep
+                        for (int rb = ra + 1; rb < rb_end; ++rb) {
+                            const int g0 = KIND == 0 ? gs : cload(tm.r_group_off + rb);
+                            const int g1 = KIND == 0 ? G : cload(tm.r_group_off + rb + 1);
+                            const unsigned key = KIND == 0 ? 0u : (unsigned)t * (unsigned)tm.P + pair_index(ra, rb, n);
+                            if (KIND == 1 && !exhaustive && key >= flag_read(&s_key)) break;
+                            float best = 3.0e38f;
+                            int g = g0;
+                            for (; g + 4 <= g1; g += 4) {
+                                float bop[4], wb[4];
+                                floatx4 d[4];
 #pragma unroll
-                                for (int r = 0; r < 4; ++r) {
-                                    const unsigned long long mr = r == 0 ? m0 : r == 1 ? m1 : r == 2 ? m2 : m3;
-                                    const int as = ga * 16 + 4 * q4 + r;
-                                    const float ar = base[3 * GSp + as];
-                                    if (!(ar > 0.f) || !((mr >> lane) & 1ull)) continue;
-                                    const float dx = base[as] - bx, dy = base[GSp + as] - by, dz = base[2 * GSp + as] - bz;
-                                    const int cl = classify(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), ar + br, eps);
-                                    if (cl == 1) {
-                                        hit = true;
-                                    } else if (cl == 2) {
-                                        // a near test matters only below the best known outcome
-                                        const bool open = KIND == 0 ? !flag_read(&s_hit) : key < flag_read(&s_key);
-                                        if (open) push_recheck(cd, q, t, rk, tm.slot_sphere[as], tm.slot_sphere[bs], key);
-                                    }
+                                for (int v = 0; v < 4; ++v) {
+                                    bop[v] = base[q4 * GSp + (g + v) * 16 + i16];
+                                    wb[v] = base[4 * GSp + (g + v) * 16 + i16];
                                 }
+#pragma unroll
+                                for (int v = 0; v < 4; ++v) d[v] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, bop[v], acc, 0, 0, 0);
+#pragma unroll
+                                for (int v = 0; v < 4; ++v) best = block_min(d[v], wb[v], best);
+                            }
+                            for (; g < g1; ++g) {
+                                const float bop = base[q4 * GSp + g * 16 + i16];
+                                const float wb = base[4 * GSp + g * 16 + i16];
+                                const floatx4 d = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, bop, acc, 0, 0, 0);
+                                best = block_min(d, wb, best);
+                            }
+                            bool hit = best < e_lo;
+                            const bool unsure = !hit && best < e_hi;
+                            if (!__ballot(hit) && __ballot(unsure) && unsure) {
+                                for (int gg = g0; gg < g1 && !hit; ++gg)
+                                    hit = direct_block(cd, tm, base, GSp, ga, gg, lane, nullptr, eps, q, t, RK_RR, key,
+                                                       &s_hit, &s_key, KIND == 0);
+                            }
+                            if (__ballot(hit)) {
+                                found = true;
+                                if (lane == 0) {
+                                    if (KIND == 0) s_hit = 1;
+                                    else atomicMin(&s_key, key);
+                                }
+                                // FFC: higher robots give larger keys
+                                if (KIND == 1 && !exhaustive) break;
                             }
                         }
                     }
-                    if (__ballot(hit)) {
-                        if (lane == 0) {
-                            if (KIND == 0) s_hit = 1;
-                            else atomicMin(&s_key, key);
-                        }
-                        // FFC: this pair's later timesteps have larger keys
-                        if (KIND == 1 && !exhaustive) break;
-                    }
+                    // FFC: this group's later timesteps give larger keys
+                    if (KIND == 1 && found && !exhaustive) break;
                 }
             }
         }
