@@ -153,7 +153,8 @@ def cloud_bench(log, n_queries=262_144, tune_sample=2048, exhaustive_queries=819
         out["mv_exhaustive_slice"] = dict(queries=sub.n_queries, ms_per_call=w3 / 2 * 1e3,
                                           kernel_ms=float(np.mean(k3)),
                                           states_per_s=s3["states_evaluated"] * 2 / w3)
-        out["tiling"] = dict(mv=ctx.get_tiling(th, 0), ffc=ctx.get_tiling(th, 1))
+        out["tiling"] = dict(mv_early=ctx.get_tiling(th, 0), mv_exhaustive=ctx.get_tiling(th, 0, mrv.EXHAUSTIVE),
+                             ffc=ctx.get_tiling(th, 1))
         log(f"cloud {tag}: {out['mv_exhaustive_slice']['states_per_s']:.3g} states/s exhaustive")
         return out
 

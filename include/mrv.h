@@ -210,14 +210,18 @@ typedef struct {
     int32_t chunk;           /* timesteps per tile; 0 = automatic */
     int32_t wg_per_cu;       /* persistent workgroups per compute unit; 0 = occupancy limit */
 } mrv_tiling;
-/* Set the tiling used for (team, kind) where kind 0 = MV, 1 = FFC. */
-mrv_status mrv_set_tiling(mrv_ctx ctx, int32_t team, int32_t kind, const mrv_tiling* tiling);
-mrv_status mrv_get_tiling(mrv_ctx ctx, int32_t team, int32_t kind, mrv_tiling* tiling);
+/* Set the tiling used for (team, kind), kind 0 = MV, 1 = FFC, by the calls whose
+ * MRV_EXHAUSTIVE flag equals that of flags (other flag bits are ignored): calls
+ * that run every test favour tiles sized for occupancy, early-terminating calls
+ * longer tiles with less fixed cost per tile, so each mode keeps its own. */
+mrv_status mrv_set_tiling(mrv_ctx ctx, int32_t team, int32_t kind, uint32_t flags, const mrv_tiling* tiling);
+mrv_status mrv_get_tiling(mrv_ctx ctx, int32_t team, int32_t kind, uint32_t flags, mrv_tiling* tiling);
 
 /* Search the tiling for (team, env, kind, flags) by timing the validation kernel on
  * the given host paths (a representative sample of the workload) with every
  * chunk size that fits in LDS and a few workgroup counts per compute unit; the
- * fastest is set for the team (as mrv_set_tiling would) and returned in *best.
+ * fastest is set for the team (as mrv_set_tiling with the same flags would) and
+ * returned in *best.
  * Results are cached per context by the team's shape (spheres, frames, groups,
  * robots), the environment's obstacle counts and the flags: a later call with
  * an equal key returns the cached tiling without timing.  The answers of MV/FFC

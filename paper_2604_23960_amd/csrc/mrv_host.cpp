@@ -51,7 +51,7 @@ struct TeamHost {
     void* dmem = nullptr;
     std::vector<int> dof;
     int max_dof = 0;
-    mrv_tiling tiling[2] = {{0, 0}, {0, 0}};
+    mrv_tiling tiling[2][2] = {{{0, 0}, {0, 0}}, {{0, 0}, {0, 0}}};   // [kind][exhaustive]
     int inflight = 0;
 };
 
@@ -68,7 +68,8 @@ struct EnvHost {
 namespace {
 
 size_t lds_per_t(const TeamHost& tm);
-int default_chunk(const TeamHost& tm, int kind);
+int default_chunk(const TeamHost& tm, int kind, int exhaustive);
+inline int mode_of(uint32_t flags) { return (flags & MRV_EXHAUSTIVE) ? 1 : 0; }
 
 bool finite_all(const double* p, size_t n)
 {
@@ -324,8 +325,8 @@ int build_team(mrv_ctx ctx, const mrv_robot_desc* robots, int n, TeamHost& out)
     out.dof = r_nj;
     out.max_dof = max_dof;
     t.lds_per_t = (int)lds_per_t(out);
-    t.chunk[0] = default_chunk(out, 0);
-    t.chunk[1] = default_chunk(out, 1);
+    for (int k = 0; k < 2; ++k)
+        for (int m = 0; m < 2; ++m) t.chunk[k][m] = default_chunk(out, k, m);
     std::memcpy(pk.bytes.data() + o_self, &t, sizeof(TeamDev));
     if (hipMemcpy(d, pk.bytes.data(), pk.bytes.size(), hipMemcpyHostToDevice) != hipSuccess) {
         (void)hipFree(d);
@@ -524,15 +525,17 @@ size_t lds_per_t(const TeamHost& tm)
     return (size_t)tm.dev.GSp * 5 * sizeof(float) + (size_t)tm.dev.F * 48;
 }
 
-int default_chunk(const TeamHost& tm, int kind)
+int default_chunk(const TeamHost& tm, int kind, int exhaustive)
 {
     const size_t per_t = lds_per_t(tm);
     int cmax = (int)((kLdsBudget - 2 * 1024) / per_t);
     cmax = std::min(cmax, kMaxChunk);
     if (cmax < 1) cmax = 1;
-    // up to 8 timesteps, fewer if that keeps four (else three) workgroups per CU
-    // within its 160 KiB of LDS
+    // early-terminating calls: 8 timesteps (most queries end in their first tiles,
+    // whose fixed cost then dominates); exhaustive calls: up to 8, fewer if that
+    // keeps four (else three) workgroups per CU within its 160 KiB of LDS
     (void)kind;
+    if (!exhaustive) return std::max(1, std::min(cmax, 8));
     const int c4 = (int)((160 * 1024 / 4 - 1024) / per_t);
     const int c3 = (int)((160 * 1024 / 3 - 1024) / per_t);
     const int want = c4 >= 4 ? std::min(8, c4) : c3 >= 4 ? std::min(8, c3) : 8;
@@ -664,9 +667,10 @@ CallPlan single_plan(const TeamHost& tm, const EnvHost* env, int kind, uint32_t 
     pl.team0 = tm.d_dev;
     pl.env0 = env ? env->d_dev : nullptr;
     pl.max_T = max_T;
-    pl.min_chunk = tm.dev.chunk[kind];
-    pl.lds = lds_bytes_for(tm, tm.dev.chunk[kind]);
-    pl.wg_per_cu = tm.tiling[kind].wg_per_cu;
+    const int m = mode_of(flags);
+    pl.min_chunk = tm.dev.chunk[kind][m];
+    pl.lds = lds_bytes_for(tm, tm.dev.chunk[kind][m]);
+    pl.wg_per_cu = tm.tiling[kind][m].wg_per_cu;
     return pl;
 }
 
@@ -1005,7 +1009,7 @@ int64_t mrv_motion_steps(const double* dq, int32_t dof, double step, int32_t met
     return (int64_t)n;
 }
 
-mrv_status mrv_set_tiling(mrv_ctx ctx, int32_t team, int32_t kind, const mrv_tiling* tiling)
+mrv_status mrv_set_tiling(mrv_ctx ctx, int32_t team, int32_t kind, uint32_t flags, const mrv_tiling* tiling)
 {
     if (guard(ctx)) return MRV_E_HANDLE;
     return wrap([&] {
@@ -1016,21 +1020,23 @@ mrv_status mrv_set_tiling(mrv_ctx ctx, int32_t team, int32_t kind, const mrv_til
         if (tiling->chunk > 0 && lds_bytes_for(tm, tiling->chunk) > (size_t)kLdsBudget - 2 * 1024)
             throw Err{MRV_E_INVALID, "chunk does not fit in LDS for this team"};
         if (tiling->wg_per_cu < 0 || tiling->wg_per_cu > 32) throw Err{MRV_E_INVALID, "wg_per_cu out of range"};
-        tm.tiling[kind] = *tiling;
-        tm.dev.chunk[kind] = tiling->chunk > 0 ? tiling->chunk : default_chunk(tm, kind);
+        const int m = mode_of(flags);
+        tm.tiling[kind][m] = *tiling;
+        tm.dev.chunk[kind][m] = tiling->chunk > 0 ? tiling->chunk : default_chunk(tm, kind, m);
         HIPCHK(hipMemcpy(tm.d_dev, &tm.dev, sizeof(TeamDev), hipMemcpyHostToDevice));
     });
 }
 
-mrv_status mrv_get_tiling(mrv_ctx ctx, int32_t team, int32_t kind, mrv_tiling* tiling)
+mrv_status mrv_get_tiling(mrv_ctx ctx, int32_t team, int32_t kind, uint32_t flags, mrv_tiling* tiling)
 {
     if (guard(ctx)) return MRV_E_HANDLE;
     return wrap([&] {
         if (!tiling || (kind != 0 && kind != 1)) throw Err{MRV_E_INVALID, "bad tiling arguments"};
         std::lock_guard<std::mutex> lk(ctx->handle_mu);
         TeamHost& tm = find_team(ctx, team);
-        mrv_tiling t = tm.tiling[kind];
-        t.chunk = tm.dev.chunk[kind];
+        const int m = mode_of(flags);
+        mrv_tiling t = tm.tiling[kind][m];
+        t.chunk = tm.dev.chunk[kind][m];
         *tiling = t;
     });
 }
@@ -1178,8 +1184,8 @@ mrv_status mrv_autotune(mrv_ctx ctx, int32_t team, int32_t env, int32_t kind, co
             TeamHost trial = tm;
             for (int c : chunks) {
                 for (int wg : {0, 1, 2}) {
-                    trial.dev.chunk[kind] = c;
-                    trial.tiling[kind] = mrv_tiling{c, wg};
+                    trial.dev.chunk[kind][mode_of(f)] = c;
+                    trial.tiling[kind][mode_of(f)] = mrv_tiling{c, wg};
                     HIPCHK(hipMemcpyAsync(tm.d_dev, &trial.dev, sizeof(TeamDev), hipMemcpyHostToDevice, ctx->stream));
                     float ms_min = 1e30f;
                     for (int rep = 0; rep < 3; ++rep) {
@@ -1200,8 +1206,8 @@ mrv_status mrv_autotune(mrv_ctx ctx, int32_t team, int32_t env, int32_t kind, co
         // apply the choice to the team (restores its descriptor)
         std::lock_guard<std::mutex> lk(ctx->handle_mu);
         TeamHost& live = find_team(ctx, team);
-        live.tiling[kind] = choice;
-        live.dev.chunk[kind] = choice.chunk;
+        live.tiling[kind][mode_of(f)] = choice;
+        live.dev.chunk[kind][mode_of(f)] = choice.chunk;
         HIPCHK(hipMemcpy(live.d_dev, &live.dev, sizeof(TeamDev), hipMemcpyHostToDevice));
         *best = choice;
     });
@@ -1321,8 +1327,9 @@ mrv_status mrv_submit(mrv_ctx ctx, const mrv_request* req, uint64_t* ticket)
             refs.team = tm.d_dev;
             refs.env = ev ? ev->d_dev : nullptr;
             refs.n_robots = tm.dev.n_robots;
-            refs.chunk = tm.dev.chunk[req->kind];
-            refs.lds = lds_bytes_for(tm, tm.dev.chunk[req->kind]);
+            const int m = mode_of(req->flags);
+            refs.chunk = tm.dev.chunk[req->kind][m];
+            refs.lds = lds_bytes_for(tm, tm.dev.chunk[req->kind][m]);
             tm.inflight++;
             if (req->kind == 0 && req->env >= 0) ctx->envs.find(req->env)->second.inflight++;
         }

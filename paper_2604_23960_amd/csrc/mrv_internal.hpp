@@ -36,7 +36,7 @@ struct TeamDev {
     int G;                 // sphere groups per timestep (16 consecutive spheres of one robot)
     int GS;                // sphere slots, 16 per group
     int GSp;               // LDS row stride of the slot arrays (GS + 16, against bank conflicts)
-    int chunk[2];          // timesteps per tile for MV / FFC
+    int chunk[2][2];       // timesteps per tile: [MV / FFC][early-terminating / exhaustive]
     int lds_per_t;         // LDS bytes one timestep of a tile needs
     float r_max;           // largest sphere radius of the team
     float origin[4];       // reference point of the FP32 sphere records (centre of the bases' bounding box)

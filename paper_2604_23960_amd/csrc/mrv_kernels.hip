@@ -300,7 +300,7 @@ __global__ void k_query_info(CallDev cd)
     const TeamDev& tm = *team_of(cd, q);
     const int n = tm.n_robots;
     const long long p0 = path_of(cd, n, q);
-    int chunk = min(tm.chunk[cd.kind], (cd.lds_bytes - 64) / tm.lds_per_t);
+    int chunk = min(tm.chunk[cd.kind][(cd.flags & MRV_EXHAUSTIVE) ? 1 : 0], (cd.lds_bytes - 64) / tm.lds_per_t);
     chunk = max(1, min(chunk, kMaxChunk));
     int T = 0;
     bool ok = true;

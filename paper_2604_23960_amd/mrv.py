@@ -107,8 +107,8 @@ def lib():
                 "mrv_mv_device": [P, I32, I32, C.POINTER(PathsDesc), U32, P],
                 "mrv_ffc_device": [P, I32, C.POINTER(PathsDesc), U32, P],
                 "mrv_sync": [P],
-                "mrv_set_tiling": [P, I32, I32, C.POINTER(Tiling)],
-                "mrv_get_tiling": [P, I32, I32, C.POINTER(Tiling)],
+                "mrv_set_tiling": [P, I32, I32, U32, C.POINTER(Tiling)],
+                "mrv_get_tiling": [P, I32, I32, U32, C.POINTER(Tiling)],
                 "mrv_last_stats": [P, C.POINTER(Stats)],
                 "mrv_submit": [P, C.POINTER(Request), C.POINTER(C.c_uint64)],
                 "mrv_poll": [P, C.c_uint64, P],
@@ -278,13 +278,15 @@ class Context:
         return out[:len(sq)]
 
     # -- tuning / stats
-    def set_tiling(self, team: int, kind: int, chunk: int = 0, wg_per_cu: int = 0):
+    def set_tiling(self, team: int, kind: int, chunk: int = 0, wg_per_cu: int = 0, flags: int | None = None):
+        """flags=None sets both modes (early-terminating and exhaustive calls)."""
         t = Tiling(chunk, wg_per_cu)
-        check(lib().mrv_set_tiling(self.h, team, kind, C.byref(t)))
+        for f in ((0, EXHAUSTIVE) if flags is None else (flags,)):
+            check(lib().mrv_set_tiling(self.h, team, kind, f, C.byref(t)))
 
-    def get_tiling(self, team: int, kind: int):
+    def get_tiling(self, team: int, kind: int, flags: int = 0):
         t = Tiling()
-        check(lib().mrv_get_tiling(self.h, team, kind, C.byref(t)))
+        check(lib().mrv_get_tiling(self.h, team, kind, flags, C.byref(t)))
         return t.chunk, t.wg_per_cu
 
     def last_stats(self) -> dict:

@@ -23,7 +23,7 @@ def test_autotune_keeps_answers():
         team, env = ctx.load_team(w.team), ctx.load_env(w.env)
         chunk, wg = ctx.autotune(team, env, 0, w.paths.subset(np.arange(128)), mrv.CHECK_ENV | mrv.EXHAUSTIVE)
         assert 1 <= chunk <= 64 and 0 <= wg <= 2
-        assert ctx.get_tiling(team, 0)[0] == chunk
+        assert ctx.get_tiling(team, 0, mrv.EXHAUSTIVE)[0] == chunk
         ref = oracle.mv(oracle.Team(w.team), oracle.Env(w.env), oracle.Paths(w.paths))
         assert np.array_equal(ctx.mv(team, env, w.paths, mrv.CHECK_ENV | mrv.EXHAUSTIVE), ref)
         # cached: same answer, no retiming needed
