@@ -531,15 +531,17 @@ int default_chunk(const TeamHost& tm, int kind, int exhaustive)
     int cmax = (int)((kLdsBudget - 2 * 1024) / per_t);
     cmax = std::min(cmax, kMaxChunk);
     if (cmax < 1) cmax = 1;
-    // early-terminating calls: 8 timesteps (most queries end in their first tiles,
-    // whose fixed cost then dominates); exhaustive calls: up to 8, fewer if that
-    // keeps four (else three) workgroups per CU within its 160 KiB of LDS
+    // early-terminating calls: 16 timesteps (most queries end in their first tiles,
+    // whose fixed cost then dominates); exhaustive calls: up to 8, the largest that
+    // keeps four workgroups per CU within its 160 KiB of LDS if that is at least 2,
+    // else three, two, one
     (void)kind;
-    if (!exhaustive) return std::max(1, std::min(cmax, 8));
-    const int c4 = (int)((160 * 1024 / 4 - 1024) / per_t);
-    const int c3 = (int)((160 * 1024 / 3 - 1024) / per_t);
-    const int want = c4 >= 4 ? std::min(8, c4) : c3 >= 4 ? std::min(8, c3) : 8;
-    return std::max(1, std::min(cmax, want));
+    if (!exhaustive) return std::max(1, std::min(cmax, 16));
+    for (int wgs = 4; wgs >= 1; --wgs) {
+        const int c = (int)((160 * 1024 / wgs - 1024) / per_t);
+        if (c >= 2 || wgs == 1) return std::max(1, std::min(cmax, std::min(8, c)));
+    }
+    return 1;
 }
 
 size_t lds_bytes_for(const TeamHost& tm, int chunk)

@@ -13,7 +13,7 @@ constexpr int kWavesPerWG = kWG / kWave;
 constexpr int kMaxRobots = 32;
 constexpr int kMaxJoints = 8;
 constexpr int kMaxChunk = 64;       // timesteps per tile
-constexpr int kLdsBudget = 64 * 1024;
+constexpr int kLdsBudget = 160 * 1024;   // LDS one workgroup may use on gfx950
 
 enum RecheckKind : int { RK_RR = 0, RK_SELF = 1, RK_ENV_SPH = 2, RK_ENV_BOX = 3, RK_ENV_CYL = 4, RK_ENV_PT = 5 };
 
