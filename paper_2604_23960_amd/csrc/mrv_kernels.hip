@@ -1125,6 +1125,16 @@ hipError_t launch_prepare(const CallDev& cd, hipStream_t stream)
 hipError_t launch_validate(const CallDev& cd, int grid, hipStream_t stream)
 {
     if (cd.n_queries == 0) return hipSuccess;
+    // allow dynamic LDS beyond 64 KiB (once per process)
+    static const hipError_t lds_opt = [] {
+        hipError_t e = hipFuncSetAttribute((const void*)k_validate<0>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           kLdsBudget - 1024);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)k_validate<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    kLdsBudget - 1024);
+        return e;
+    }();
+    if (lds_opt != hipSuccess && cd.lds_bytes > 64 * 1024) return lds_opt;
     if (cd.kind == 0)
         hipLaunchKernelGGL(k_validate<0>, dim3(grid), dim3(kWG), (size_t)cd.lds_bytes, stream, cd);
     else
