@@ -385,37 +385,57 @@ int orc_points_any_hit(const orc_env* E, const double* x, double r)
 /* single-state checks                                                        */
 
 /* Robot-obstacle and self collision of one robot state (spheres in world frame). */
-static int env_self_hit(const orc_team* tm, const orc_env* E, int r, const double* sph)
+/* Robot r's self pairs and obstacles at one state.  all = 0 stops at the first
+ * collision; all = 1 evaluates every relation (exhaustive validation, paper
+ * Sec. V: every collision relation at every intermediate state). */
+static int env_self_hit(const orc_team* tm, const orc_env* E, int r, const double* sph, int all)
 {
     int s0 = tm->sphere_off[r], ns = tm->sphere_off[r + 1] - s0;
+    int hit = 0;
     for (int p = tm->self_off[r]; p < tm->self_off[r + 1]; ++p) {
         int a = tm->self_pairs[2 * p], b = tm->self_pairs[2 * p + 1];
-        if (orc_clear_sphere_sphere(sph + a * 4, sph[a * 4 + 3], sph + b * 4, sph[b * 4 + 3]) < 0.0)
-            return 1;
+        if (orc_clear_sphere_sphere(sph + a * 4, sph[a * 4 + 3], sph + b * 4, sph[b * 4 + 3]) < 0.0) {
+            hit = 1;
+            if (!all) return 1;
+        }
     }
-    if (!E) return 0;
+    if (!E) return hit;
     for (int a = 0; a < ns; ++a) {
         const double* x = sph + a * 4;
         double rad = x[3];
         for (int o = 0; o < E->n_spheres; ++o)
-            if (orc_clear_sphere_sphere(x, rad, E->spheres + o * 4, E->spheres[o * 4 + 3]) < 0.0)
-                return 1;
+            if (orc_clear_sphere_sphere(x, rad, E->spheres + o * 4, E->spheres[o * 4 + 3]) < 0.0) {
+                hit = 1;
+                if (!all) return 1;
+            }
         for (int o = 0; o < E->n_boxes; ++o)
-            if (orc_clear_sphere_box(x, rad, E->boxes + o * 15) < 0.0) return 1;
+            if (orc_clear_sphere_box(x, rad, E->boxes + o * 15) < 0.0) {
+                hit = 1;
+                if (!all) return 1;
+            }
         for (int o = 0; o < E->n_cyls; ++o)
-            if (orc_clear_sphere_cylinder(x, rad, E->cyls + o * 8) < 0.0) return 1;
-        if (orc_points_any_hit(E, x, rad)) return 1;
+            if (orc_clear_sphere_cylinder(x, rad, E->cyls + o * 8) < 0.0) {
+                hit = 1;
+                if (!all) return 1;
+            }
+        if (orc_points_any_hit(E, x, rad)) {
+            hit = 1;
+            if (!all) return 1;
+        }
     }
-    return 0;
+    return hit;
 }
 
-static int pair_hit(const double* si, int ni, const double* sj, int nj)
+static int pair_hit(const double* si, int ni, const double* sj, int nj, int all)
 {
+    int hit = 0;
     for (int a = 0; a < ni; ++a)
         for (int b = 0; b < nj; ++b)
-            if (orc_clear_sphere_sphere(si + a * 4, si[a * 4 + 3], sj + b * 4, sj[b * 4 + 3]) < 0.0)
-                return 1;
-    return 0;
+            if (orc_clear_sphere_sphere(si + a * 4, si[a * 4 + 3], sj + b * 4, sj[b * 4 + 3]) < 0.0) {
+                hit = 1;
+                if (!all) return 1;
+            }
+    return hit;
 }
 
 static int team_total_spheres(const orc_team* tm) { return tm->sphere_off[tm->n_robots]; }
@@ -424,31 +444,33 @@ static int team_total_spheres(const orc_team* tm) { return tm->sphere_off[tm->n_
 /* MV and FFC                                                                 */
 
 /* MV of one query.  Returns 1 valid, 0 invalid.  first_hit (optional) gets the
- * timestep at which the ascending scan stopped, -1 if valid. */
+ * first colliding timestep of the ascending scan, -1 if valid.  exhaustive = 1
+ * evaluates every relation at every state instead of stopping (same answer). */
 static int mv_one(const orc_team* tm, const orc_env* E, const orc_paths* P, int64_t qi,
-                  int check_env, double* buf, int64_t* first_hit)
+                  int check_env, int exhaustive, double* buf, int64_t* first_hit)
 {
     int n = tm->n_robots;
     int64_t T = orc_query_horizon(P, qi);
+    int64_t fh = -1;
     for (int64_t t = 0; t < T; ++t) {
+        int hit = 0;
         for (int r = 0; r < n; ++r)
             robot_spheres_at(tm, P, qi, r, t, buf + (int64_t)tm->sphere_off[r] * 4);
         if (check_env)
-            for (int r = 0; r < n; ++r)
-                if (env_self_hit(tm, E, r, buf + (int64_t)tm->sphere_off[r] * 4)) {
-                    if (first_hit) *first_hit = t;
-                    return 0;
-                }
-        for (int i = 0; i + 1 < n; ++i)
-            for (int j = i + 1; j < n; ++j)
-                if (pair_hit(buf + (int64_t)tm->sphere_off[i] * 4, tm->sphere_off[i + 1] - tm->sphere_off[i],
-                             buf + (int64_t)tm->sphere_off[j] * 4, tm->sphere_off[j + 1] - tm->sphere_off[j])) {
-                    if (first_hit) *first_hit = t;
-                    return 0;
-                }
+            for (int r = 0; r < n && (exhaustive || !hit); ++r)
+                hit |= env_self_hit(tm, E, r, buf + (int64_t)tm->sphere_off[r] * 4, exhaustive);
+        for (int i = 0; i + 1 < n && (exhaustive || !hit); ++i)
+            for (int j = i + 1; j < n && (exhaustive || !hit); ++j)
+                hit |= pair_hit(buf + (int64_t)tm->sphere_off[i] * 4, tm->sphere_off[i + 1] - tm->sphere_off[i],
+                                buf + (int64_t)tm->sphere_off[j] * 4, tm->sphere_off[j + 1] - tm->sphere_off[j],
+                                exhaustive);
+        if (hit && fh < 0) {
+            fh = t;
+            if (!exhaustive) break;
+        }
     }
-    if (first_hit) *first_hit = -1;
-    return 1;
+    if (first_hit) *first_hit = fh;
+    return fh < 0;
 }
 
 static void ffc_one(const orc_team* tm, const orc_paths* P, int64_t qi, double* buf, int32_t* out)
@@ -461,7 +483,7 @@ static void ffc_one(const orc_team* tm, const orc_paths* P, int64_t qi, double* 
         for (int i = 0; i + 1 < n; ++i)
             for (int j = i + 1; j < n; ++j)
                 if (pair_hit(buf + (int64_t)tm->sphere_off[i] * 4, tm->sphere_off[i + 1] - tm->sphere_off[i],
-                             buf + (int64_t)tm->sphere_off[j] * 4, tm->sphere_off[j + 1] - tm->sphere_off[j])) {
+                             buf + (int64_t)tm->sphere_off[j] * 4, tm->sphere_off[j + 1] - tm->sphere_off[j], 0)) {
                     out[0] = (int32_t)t; out[1] = i; out[2] = j;
                     return;
                 }
@@ -481,9 +503,10 @@ static int set_threads(int nthreads)
 }
 
 /* MV over queries [q0, q1).  env may be NULL (no obstacles).  check_env = 0 skips
- * robot-obstacle and self checks.  valid_out[q - q0]; first_hit_out optional. */
+ * robot-obstacle and self checks; exhaustive = 1 evaluates every relation at every
+ * state.  valid_out[q - q0]; first_hit_out optional. */
 int orc_mv(const orc_team* tm, const orc_env* E, const orc_paths* P, int64_t q0, int64_t q1,
-           int32_t check_env, uint8_t* valid_out, int64_t* first_hit_out, int32_t nthreads)
+           int32_t check_env, int32_t exhaustive, uint8_t* valid_out, int64_t* first_hit_out, int32_t nthreads)
 {
     set_threads(nthreads);
     int S = team_total_spheres(tm);
@@ -498,7 +521,7 @@ int orc_mv(const orc_team* tm, const orc_env* E, const orc_paths* P, int64_t q0,
 #pragma omp for schedule(dynamic, 4)
             for (int64_t qi = q0; qi < q1; ++qi) {
                 int64_t fh = -1;
-                valid_out[qi - q0] = (uint8_t)mv_one(tm, E, P, qi, check_env, buf, &fh);
+                valid_out[qi - q0] = (uint8_t)mv_one(tm, E, P, qi, check_env, exhaustive, buf, &fh);
                 if (first_hit_out) first_hit_out[qi - q0] = fh;
             }
             free(buf);

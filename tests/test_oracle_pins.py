@@ -461,3 +461,14 @@ def test_touching_is_not_a_collision_and_first_overlap_closed_form():
     # disk 1 at x = 0.5 - 0.25 (t - T/2) / (T/2 - 1) clears disk 0 by x - 0.5 < 0 from t = T/2 + 1
     want = [(-1, -1, -1), (T // 2 + 1, 0, 1), (0, 0, 2)] * 3
     assert [tuple(r) for r in f] == want
+
+
+def test_exhaustive_scan_gives_the_same_answers():
+    """Evaluating every relation at every state (exhaustive validation) changes
+    the work, not MV's answer or the first colliding timestep."""
+    w = W.arms_workload(96)
+    ot, oe, op = oracle.Team(w.team), oracle.Env(w.env), oracle.Paths(w.paths)
+    for check_env in (True, False):
+        v0, f0 = oracle.mv(ot, oe, op, check_env=check_env, first_hit=True)
+        v1, f1 = oracle.mv(ot, oe, op, check_env=check_env, first_hit=True, exhaustive=True)
+        assert np.array_equal(v0, v1) and np.array_equal(f0, f1)
