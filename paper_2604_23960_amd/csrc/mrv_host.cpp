@@ -284,6 +284,7 @@ int build_team(mrv_ctx ctx, const mrv_robot_desc* robots, int n, TeamHost& out)
     t.n_sblocks = (int)sblocks.size() / 8;
     t.GS = GS;
     t.GSp = GS + 16;
+    t.TS = std::max(5 * t.GSp, 3 * t.GSp + 12 * F);
     t.P = n * (n - 1) / 2;
     t.max_dof = max_dof;
     t.G = G;
@@ -522,7 +523,7 @@ long long max_horizon(const mrv_paths* p, int n_robots)
 
 size_t lds_per_t(const TeamHost& tm)
 {
-    return (size_t)tm.dev.GSp * 5 * sizeof(float) + (size_t)tm.dev.F * 48;
+    return (size_t)tm.dev.TS * sizeof(float);
 }
 
 int default_chunk(const TeamHost& tm, int kind, int exhaustive)

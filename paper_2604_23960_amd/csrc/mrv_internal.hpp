@@ -36,6 +36,7 @@ struct TeamDev {
     int G;                 // sphere groups per timestep (16 consecutive spheres of one robot)
     int GS;                // sphere slots, 16 per group
     int GSp;               // LDS row stride of the slot arrays (GS + 16, against bank conflicts)
+    int TS;                // LDS floats per timestep of a tile: five slot rows, or three and the FK frames
     int chunk[2][2];       // timesteps per tile: [MV / FFC][early-terminating / exhaustive]
     int lds_per_t;         // LDS bytes one timestep of a tile needs
     float r_max;           // largest sphere radius of the team

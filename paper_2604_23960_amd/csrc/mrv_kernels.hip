@@ -754,47 +754,64 @@ __global__ __launch_bounds__(kWG, 4) void k_validate(CallDev cd)
         const int G = tm.G;
         const int n = tm.n_robots;
         const long long qp0 = path_of(cd, n, q);
-        // LDS of this tile.  Per timestep c, five rows of GSp floats over the sphere
-        // slots (16 per group, unused slots padded): x, y, z relative to the team's
-        // origin, radius (0 marks padding), w = |p|^2 - r^2; then the frames of the
-        // FK chains.
+        // LDS of this tile, TS floats per timestep c: five rows of GSp floats over the
+        // sphere slots (16 per group, unused slots padded) -- x, y, z relative to the
+        // team's origin, radius (0 marks padding), w = |p|^2 - r^2.  The FK frames of
+        // the timestep take its last 12 F floats, past the x, y, z rows, until the
+        // radius and w rows are written over them.
         const int GS = tm.GS;
         const int GSp = tm.GSp;
+        const int TS = tm.TS;
+        const int fr_off = TS - 12 * F;
         const float ox = tm.origin[0], oy = tm.origin[1], oz = tm.origin[2];
-        float* sp = reinterpret_cast<float*>(dyn);                      // [C][5][GSp]
-        float4* fr = reinterpret_cast<float4*>(sp + C * 5 * GSp);       // [C][F][3] frame rows
+        float* sp = reinterpret_cast<float*>(dyn);                      // [C][TS]
 
         // --- configurations and FP32 forward kinematics: one lane per (timestep, robot)
         for (int idx = tid; idx < nv * n; idx += kWG) {
             const int c = idx / n;
             const int r = idx - c * n;
             robot_frames32(tm, cd, cd.wp_begin[qp0 + r], cd.wp_begin[qp0 + r + 1], r, s_t[c],
-                           fr + ((long long)c * F + tm.r_frame_off[r]) * 3);
+                           reinterpret_cast<float4*>(sp + (long long)c * TS + fr_off) + tm.r_frame_off[r] * 3);
         }
         __syncthreads();
 
-        // --- sphere records, one lane per (timestep, slot)
+        // --- sphere centres, one lane per (timestep, slot); padding slots sit at the origin
+        for (int idx = tid; idx < nv * GS; idx += kWG) {
+            const int c = idx / GS;
+            const int s = idx - c * GS;
+            const int sph = tm.slot_sphere[s];
+            float x = 0.f, y = 0.f, z = 0.f;
+            if (sph >= 0) {
+                const float4 X = place32(reinterpret_cast<const float4*>(sp + (long long)c * TS + fr_off) +
+                                             tm.s_slot[sph] * 3,
+                                         tm.s_local32[sph]);
+                x = X.x - ox;
+                y = X.y - oy;
+                z = X.z - oz;
+            }
+            float* row = sp + (long long)c * TS + s;
+            row[0] = x;
+            row[GSp] = y;
+            row[2 * GSp] = z;
+        }
+        __syncthreads();
+
+        // --- radius and w rows, over the frames
         {
             float r2max = 0.f;
             for (int idx = tid; idx < nv * GS; idx += kWG) {
                 const int c = idx / GS;
                 const int s = idx - c * GS;
                 const int sph = tm.slot_sphere[s];
-                float x = 0.f, y = 0.f, z = 0.f, r = 0.f, w = kFar;
+                float* row = sp + (long long)c * TS + s;
+                float r = 0.f, w = kFar;
                 if (sph >= 0) {
-                    const float4 X = place32(fr + ((long long)c * F + tm.s_slot[sph]) * 3, tm.s_local32[sph]);
-                    x = X.x - ox;
-                    y = X.y - oy;
-                    z = X.z - oz;
-                    r = X.w;
+                    const float x = row[0], y = row[GSp], z = row[2 * GSp];
+                    r = tm.s_local32[sph].w;
                     const float d2 = fmaf(x, x, fmaf(y, y, z * z));
                     w = fmaf(-r, r, d2);
                     r2max = fmaxf(r2max, d2);
                 }
-                float* row = sp + c * 5 * GSp + s;
-                row[0] = x;
-                row[GSp] = y;
-                row[2 * GSp] = z;
                 row[3 * GSp] = r;
                 row[4 * GSp] = w;
             }
@@ -814,7 +831,7 @@ __global__ __launch_bounds__(kWG, 4) void k_validate(CallDev cd)
                 if (!exhaustive && flag_read(&s_hit)) break;
                 const int c = task / nch;
                 const int a = (task - c * nch) * kWave + lane;     // slot
-                const float* row = sp + c * 5 * GSp + a;
+                const float* row = sp + (long long)c * TS + a;
                 const float rad = a < GS ? row[3 * GSp] : 0.f;
                 const bool act = rad > 0.f;
                 float x = 1.0e18f, y = 1.0e18f, z = 1.0e18f;
@@ -946,7 +963,7 @@ __global__ __launch_bounds__(kWG, 4) void k_validate(CallDev cd)
                     }
                     c_rr += rr_tests;
                     c_self += self_tests;
-                    const float* base = sp + c * 5 * GSp;
+                    const float* base = sp + (long long)c * TS;
                     const float aop = -2.f * base[q4 * GSp + ga * 16 + i16];
                     const float4 cw = *reinterpret_cast<const float4*>(base + 4 * GSp + ga * 16 + 4 * q4);
                     bool found = false;
