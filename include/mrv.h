@@ -63,6 +63,10 @@ enum {
 #define MRV_MAX_SPHERES_PER_ROBOT 256
 #define MRV_MAX_TEAM_SPHERES 2048
 #define MRV_MAX_T (1 << 20)
+/* Every floating-point input (team geometry, obstacles, points, waypoint
+ * configurations) must be finite with magnitude <= MRV_MAX_COORD (metres or
+ * radians); the kernels' FP32 arithmetic then cannot overflow. */
+#define MRV_MAX_COORD 1.0e6
 
 typedef struct mrv_ctx_s* mrv_ctx;
 
@@ -135,7 +139,7 @@ mrv_status mrv_unload(mrv_ctx ctx, int32_t handle);
 /* Query-major CSR over per-robot timed waypoint lists.  Path (q, r) is
  * waypoints [wp_begin[q*n_robots + r], wp_begin[q*n_robots + r + 1]).  Its first
  * time is 0, times strictly increase, the last time is < MRV_MAX_T, and the
- * configurations are finite.  wp_q rows hold dof_stride doubles (the team's
+ * configuration values are finite and within MRV_MAX_COORD.  wp_q rows hold dof_stride doubles (the team's
  * largest dof; a robot reads its first n_joints values). */
 typedef struct {
     int32_t n_queries;

@@ -9,34 +9,45 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmrv.so")
-SOURCES = ["mrv_kernels.hip", "mrv_host.cpp", "mrv_serve.cpp"]
+KERNELS = "mrv_kernels.hip"
+HOST_SOURCES = ["mrv_host.cpp", "mrv_serve.cpp"]
+SOURCES = [KERNELS, *HOST_SOURCES]
 HEADERS = ["mrv_internal.hpp", "mrv_runtime.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 
-def command(out: str) -> list[str]:
-    objs = [os.path.join(CSRC, s) for s in SOURCES]
-    return [HIPCC, f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+def _common() -> list[str]:
+    return [HIPCC, f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
             # packed FP32 instructions are left to nobody: see the build notes in the design doc
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            "-Wno-unused-command-line-argument",
-            "-I", os.path.join(ROOT, "include"), "-o", out, *objs, "-lpthread"]
+            "-Wno-unused-command-line-argument", "-I", os.path.join(ROOT, "include")]
+
+
+def commands(out: str) -> list[list[str]]:
+    """Kernels compiled on their own, assuming no NaN (every floating-point value
+    they read is checked finite and within MRV_MAX_COORD before any kernel uses
+    it), so minima of matrix-core results need no NaN quieting; then the host
+    code, without that assumption, linked into one library."""
+    obj = out + ".kernels.o"
+    return [[*_common(), "-fno-honor-nans", "-c", os.path.join(CSRC, KERNELS), "-o", obj],
+            [*_common(), "-shared", "-o", out, obj, *[os.path.join(CSRC, s) for s in HOST_SOURCES], "-lpthread"]]
 
 
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
-    cmd = command(tmp)
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    if res.returncode != 0:
-        sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libmrv.so")
-    warn = [ln for ln in res.stderr.splitlines() if "packed-fp32-ops" not in ln and ln.strip()]
-    if verbose and warn:
-        sys.stderr.write("\n".join(warn) + "\n")
+    for cmd in commands(tmp):
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            sys.stderr.write(res.stdout + res.stderr)
+            raise RuntimeError("hipcc failed building libmrv.so")
+        warn = [ln for ln in res.stderr.splitlines() if "packed-fp32-ops" not in ln and ln.strip()]
+        if verbose and warn:
+            sys.stderr.write("\n".join(warn) + "\n")
+    os.remove(tmp + ".kernels.o")
     os.replace(tmp, LIB)
     return LIB
 

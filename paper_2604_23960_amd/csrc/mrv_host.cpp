@@ -71,10 +71,11 @@ size_t lds_per_t(const TeamHost& tm);
 int default_chunk(const TeamHost& tm, int kind, int exhaustive);
 inline int mode_of(uint32_t flags) { return (flags & MRV_EXHAUSTIVE) ? 1 : 0; }
 
-bool finite_all(const double* p, size_t n)
+// Finite and within MRV_MAX_COORD (NaN fails the comparison).
+bool bounded_all(const double* p, size_t n)
 {
     for (size_t i = 0; i < n; ++i)
-        if (!std::isfinite(p[i])) return false;
+        if (!(std::fabs(p[i]) <= MRV_MAX_COORD)) return false;
     return true;
 }
 
@@ -149,11 +150,11 @@ int build_team(mrv_ctx ctx, const mrv_robot_desc* robots, int n, TeamHost& out)
         if (!R.sphere_frame || !R.sphere_xyzr) throw Err{MRV_E_INVALID, who + "null sphere arrays"};
         if (R.n_self_pairs < 0 || (R.n_self_pairs > 0 && !R.self_pairs))
             throw Err{MRV_E_INVALID, who + "bad self pair list"};
-        if (!finite_all(R.base, 12)) throw Err{MRV_E_INVALID, who + "non-finite base"};
-        if (R.n_joints > 0 && !finite_all(R.joint_fixed, (size_t)R.n_joints * 12))
-            throw Err{MRV_E_INVALID, who + "non-finite joint transform"};
-        if (!finite_all(R.sphere_xyzr, (size_t)R.n_spheres * 4))
-            throw Err{MRV_E_INVALID, who + "non-finite sphere"};
+        if (!bounded_all(R.base, 12)) throw Err{MRV_E_INVALID, who + "base not finite or beyond MRV_MAX_COORD"};
+        if (R.n_joints > 0 && !bounded_all(R.joint_fixed, (size_t)R.n_joints * 12))
+            throw Err{MRV_E_INVALID, who + "joint transform not finite or beyond MRV_MAX_COORD"};
+        if (!bounded_all(R.sphere_xyzr, (size_t)R.n_spheres * 4))
+            throw Err{MRV_E_INVALID, who + "sphere not finite or beyond MRV_MAX_COORD"};
         r_nj[r] = R.n_joints;
         max_dof = std::max(max_dof, R.n_joints);
         r_joint_off[r] = (int)j_type.size();
@@ -348,11 +349,11 @@ void build_env(const mrv_env_desc* e, EnvHost& out)
     if ((e->n_spheres && !e->spheres) || (e->n_boxes && !e->boxes) || (e->n_cyls && !e->cylinders) ||
         (e->n_points && !e->points))
         throw Err{MRV_E_INVALID, "null obstacle array"};
-    if (e->n_spheres && !finite_all(e->spheres, (size_t)e->n_spheres * 4)) throw Err{MRV_E_INVALID, "non-finite sphere obstacle"};
-    if (e->n_boxes && !finite_all(e->boxes, (size_t)e->n_boxes * 15)) throw Err{MRV_E_INVALID, "non-finite box"};
-    if (e->n_cyls && !finite_all(e->cylinders, (size_t)e->n_cyls * 8)) throw Err{MRV_E_INVALID, "non-finite cylinder"};
-    if (e->n_points && !finite_all(e->points, (size_t)e->n_points * 3)) throw Err{MRV_E_INVALID, "non-finite point"};
-    if (!std::isfinite(e->point_radius) || e->point_radius < 0) throw Err{MRV_E_INVALID, "bad point radius"};
+    if (e->n_spheres && !bounded_all(e->spheres, (size_t)e->n_spheres * 4)) throw Err{MRV_E_INVALID, "sphere obstacle not finite or beyond MRV_MAX_COORD"};
+    if (e->n_boxes && !bounded_all(e->boxes, (size_t)e->n_boxes * 15)) throw Err{MRV_E_INVALID, "box not finite or beyond MRV_MAX_COORD"};
+    if (e->n_cyls && !bounded_all(e->cylinders, (size_t)e->n_cyls * 8)) throw Err{MRV_E_INVALID, "cylinder not finite or beyond MRV_MAX_COORD"};
+    if (e->n_points && !bounded_all(e->points, (size_t)e->n_points * 3)) throw Err{MRV_E_INVALID, "point not finite or beyond MRV_MAX_COORD"};
+    if (!bounded_all(&e->point_radius, 1) || e->point_radius < 0) throw Err{MRV_E_INVALID, "bad point radius"};
     std::vector<float> sph32;
     for (int i = 0; i < e->n_spheres; ++i) {
         if (e->spheres[i * 4 + 3] < 0) throw Err{MRV_E_INVALID, "negative obstacle radius"};
@@ -506,8 +507,8 @@ void check_paths_host(const TeamHost& tm, const mrv_paths* p)
             if (w > b && p->wp_t[w] <= p->wp_t[w - 1])
                 throw Err{MRV_E_INVALID, "waypoint times must strictly increase"};
             for (int d = 0; d < dof; ++d)
-                if (!std::isfinite(p->wp_q[w * p->dof_stride + d]))
-                    throw Err{MRV_E_INVALID, "non-finite waypoint configuration"};
+                if (!bounded_all(&p->wp_q[w * p->dof_stride + d], 1))
+                    throw Err{MRV_E_INVALID, "waypoint configuration not finite or beyond MRV_MAX_COORD"};
         }
         if (p->wp_t[e - 1] >= MRV_MAX_T) throw Err{MRV_E_INVALID, "path longer than MRV_MAX_T"};
     }
@@ -532,13 +533,17 @@ int default_chunk(const TeamHost& tm, int kind, int exhaustive)
     int cmax = (int)((kLdsBudget - 2 * 1024) / per_t);
     cmax = std::min(cmax, kMaxChunk);
     if (cmax < 1) cmax = 1;
-    // early-terminating calls: 16 timesteps (most queries end in their first tiles,
-    // whose fixed cost then dominates); exhaustive calls: up to 8, the largest that
-    // keeps four workgroups per CU within its 160 KiB of LDS if that is at least 2,
-    // else three, two, one
-    (void)kind;
-    if (!exhaustive) return std::max(1, std::min(cmax, 16));
-    for (int wgs = 4; wgs >= 1; --wgs) {
+    // early-terminating calls: long tiles, since most queries end in their first
+    // tiles, whose fixed cost then dominates -- FFC 16 timesteps, MV the most that
+    // keep two workgroups per CU (at least 8, at most 16); exhaustive calls: up to 8,
+    // the largest that keeps five workgroups per CU (the register limit) within its
+    // 160 KiB of LDS if that is at least 2, else four, three, two, one
+    if (!exhaustive) {
+        int c = 16;
+        if (kind == 0) c = std::max(8, std::min(16, (int)((160 * 1024 / 2 - 1024) / per_t)));
+        return std::max(1, std::min(cmax, c));
+    }
+    for (int wgs = kWGsPerCU; wgs >= 1; --wgs) {
         const int c = (int)((160 * 1024 / wgs - 1024) / per_t);
         if (c >= 2 || wgs == 1) return std::max(1, std::min(cmax, std::min(8, c)));
     }

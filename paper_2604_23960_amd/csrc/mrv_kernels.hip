@@ -101,6 +101,14 @@ __device__ __forceinline__ unsigned load_word(const unsigned* p)
 
 // Locate the waypoint segment of path [b, e) for timestep t: returns k with
 // wp_t[k] <= t < wp_t[k+1], or e-1 when t is at or past the last waypoint.
+// |v| <= MRV_MAX_COORD, false for NaN and infinities.  An integer test: the
+// kernels are compiled assuming no NaN, so a floating-point test could be folded.
+// Non-negative doubles order as their bit patterns, and NaN and infinity lie above.
+__device__ __forceinline__ bool bounded64(double v)
+{
+    return (__double_as_longlong(v) & 0x7FFFFFFFFFFFFFFFLL) <= __double_as_longlong(MRV_MAX_COORD);
+}
+
 __device__ __forceinline__ long long find_segment(const int* wt, long long b, long long e, int t)
 {
     if (t >= wt[e - 1]) return e - 1;
@@ -316,7 +324,7 @@ __global__ void k_query_info(CallDev cd)
             if (i > b && ti <= prev) ok = false;
             prev = ti;
             for (int d = 0; d < dof; ++d)
-                if (!isfinite(cd.wp_q[i * cd.dof_stride + d])) ok = false;
+                if (!bounded64(cd.wp_q[i * cd.dof_stride + d])) ok = false;
         }
         if (prev >= MRV_MAX_T) ok = false;
         if (prev + 1 > T) T = prev + 1;
@@ -481,10 +489,17 @@ __device__ __forceinline__ float lane_select(unsigned long long m, float on, flo
 
 // min(best, min_r d[r] + wb) for one MFMA result: adding w_b first makes the
 // operands of the minimum results of arithmetic, which need no NaN quieting
+// Smallest D in a lane's share of a block: its four rows share the column b, so
+// w_b is added once, after the minimum (rounding to nearest is monotonic, so this
+// equals the minimum of the four sums).
+__device__ __forceinline__ float col_min(floatx4 d, float wb)
+{
+    return fminf(fminf(fminf(d[0], d[1]), d[2]), d[3]) + wb;
+}
+
 __device__ __forceinline__ float block_min(floatx4 d, float wb, float best)
 {
-    const float m = fminf(fminf(best, d[0] + wb), d[1] + wb);
-    return fminf(fminf(m, d[2] + wb), d[3] + wb);
+    return fminf(best, col_min(d, wb));
 }
 
 __device__ __forceinline__ float wave_max_f32(float v)
@@ -642,8 +657,133 @@ __device__ __forceinline__ float4 place32(const float4* Fp, float4 L)
                        fmaf(r2.x, L.x, fmaf(r2.y, L.y, fmaf(r2.z, L.z, r2.w))), L.w);
 }
 
+// Robot-obstacle tests of J (timestep, 64-slot chunk) tasks of one wave, one lane
+// per slot: each obstacle's parameters are loaded once (wave-uniform scalar loads)
+// and applied to all J tasks.  Sets *s_hit on a confirmed hit; near tests below
+// the known outcome are queued for FP64 re-evaluation.
+template <int J>
+__device__ __forceinline__ void env_tasks(const CallDev& cd, const TeamDev& tm, const EnvDev& env, const float* sp,
+                                          const int* task, int nch, float ro_max, float eps, bool exhaustive, int q,
+                                          const int* s_t, int* s_hit, unsigned long long& c_env, int lane)
+{
+    const int GS = tm.GS, GSp = tm.GSp, TS = tm.TS;
+    int c[J], a[J];
+    float x[J], y[J], z[J], rad[J], mb[J], ms[J];
+    bool act[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        c[j] = task[j] / nch;
+        a[j] = (task[j] - c[j] * nch) * kWave + lane;     // slot
+        const float* row = sp + (long long)c[j] * TS + a[j];
+        rad[j] = a[j] < GS ? row[3 * GSp] : 0.f;
+        act[j] = rad[j] > 0.f;
+        x[j] = 1.0e18f; y[j] = 1.0e18f; z[j] = 1.0e18f;
+        if (act[j]) {
+            x[j] = row[0] + tm.origin[0];
+            y[j] = row[GSp] + tm.origin[1];
+            z[j] = row[2 * GSp] + tm.origin[2];
+        }
+        mb[j] = 3.0e38f;
+        ms[j] = 3.0e38f;
+    }
+#pragma unroll 2
+    for (int o = 0; o < env.n_box; ++o) {
+        CFloat* B = (CFloat*)(env.box32 + o * 16);
+#pragma unroll
+        for (int j = 0; j < J; ++j) mb[j] = fminf(mb[j], box_val(x[j], y[j], z[j], B));
+    }
+#pragma unroll 2
+    for (int o = 0; o < env.n_cyl; ++o) {
+        CFloat* Y = (CFloat*)(env.cyl32 + o * 8);
+#pragma unroll
+        for (int j = 0; j < J; ++j) mb[j] = fminf(mb[j], cyl_val(x[j], y[j], z[j], Y));
+    }
+    for (int o = 0; o < env.n_sph; ++o) {
+        const float* ob = &env.sph32[o].x;
+        const float ocx = cloadf(ob), ocy = cloadf(ob + 1), ocz = cloadf(ob + 2), orad = cloadf(ob + 3);
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const float Rs = rad[j] + orad;
+            const float dx = x[j] - ocx, dy = y[j] - ocy, dz = z[j] - ocz;
+            ms[j] = fminf(ms[j], fmaf(-Rs, Rs, fmaf(dx, dx, fmaf(dy, dy, dz * dz))));
+        }
+    }
+    bool any_hit = false;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        if (act[j]) c_env += (unsigned long long)(env.n_sph + env.n_box + env.n_cyl);
+        const float rlo = fmaxf(rad[j] - eps, 0.f), rhi = rad[j] + eps;
+        const float Rb = rad[j] + ro_max;
+        bool hit = false, unsure = false;
+        if (act[j]) {
+            hit = (mb[j] < rlo * rlo) || (ms[j] < -2.f * Rb * eps);
+            unsure = !hit && ((mb[j] <= rhi * rhi) || (ms[j] <= fmaf(2.f * Rb, eps, eps * eps)));
+        }
+        const int sa = act[j] ? tm.slot_sphere[a[j]] : 0;
+        const int t = s_t[c[j]];
+        if (env.n_pts > 0 && act[j]) {
+            const float Rp = rad[j] + env.pt_radius;
+            const float xs[3] = { x[j], y[j], z[j] };
+            int lo3[3], hi3[3];
+            const float reach = Rp + eps;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const int l = (int)floorf((xs[d] - reach - env.grid_lo[d]) * env.grid_inv);
+                const int h = (int)floorf((xs[d] + reach - env.grid_lo[d]) * env.grid_inv);
+                lo3[d] = l < 0 ? 0 : l;
+                hi3[d] = h >= env.grid_dim[d] ? env.grid_dim[d] - 1 : h;
+            }
+            const float plo = fmaxf(Rp - eps, 0.f), phi = Rp + eps;
+            const float plo2 = plo * plo, phi2 = phi * phi;
+            if (lo3[0] <= hi3[0])
+                for (int cz = lo3[2]; cz <= hi3[2]; ++cz)
+                    for (int cy = lo3[1]; cy <= hi3[1]; ++cy) {
+                        const int crow = (cz * env.grid_dim[1] + cy) * env.grid_dim[0];
+                        const int pb = env.cell_start[crow + lo3[0]];
+                        const int pe = env.cell_start[crow + hi3[0] + 1];
+                        for (int p = pb; p < pe; ++p) {
+                            const float4 Pt = env.pts32[p];
+                            const float dx = x[j] - Pt.x, dy = y[j] - Pt.y, dz = z[j] - Pt.z;
+                            const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                            if (d2 <= phi2) {
+                                if (d2 < plo2) hit = true;
+                                else if (!hit && !flag_read(s_hit))
+                                    push_recheck(cd, q, t, RK_ENV_PT, sa, p, 0u);
+                            }
+                        }
+                    }
+        }
+        if (unsure && !(hit && !exhaustive)) {
+            // rare: find the near obstacles and queue each for FP64 re-evaluation
+            const float xj = x[j], yj = y[j], zj = z[j];
+            for (int o = 0; o < env.n_box; ++o) {
+                const float v = box_val(xj, yj, zj, (CFloat*)(env.box32 + o * 16));
+                if (v < rlo * rlo) hit = true;
+                else if (v <= rhi * rhi && !hit && !flag_read(s_hit))
+                    push_recheck(cd, q, t, RK_ENV_BOX, sa, o, 0u);
+            }
+            for (int o = 0; o < env.n_cyl; ++o) {
+                const float v = cyl_val(xj, yj, zj, (CFloat*)(env.cyl32 + o * 8));
+                if (v < rlo * rlo) hit = true;
+                else if (v <= rhi * rhi && !hit && !flag_read(s_hit))
+                    push_recheck(cd, q, t, RK_ENV_CYL, sa, o, 0u);
+            }
+            for (int o = 0; o < env.n_sph; ++o) {
+                const float* ob = &env.sph32[o].x;
+                const float dx = xj - cloadf(ob), dy = yj - cloadf(ob + 1), dz = zj - cloadf(ob + 2);
+                const int cl = classify(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), rad[j] + cloadf(ob + 3), eps);
+                if (cl == 1) hit = true;
+                else if (cl == 2 && !hit && !flag_read(s_hit))
+                    push_recheck(cd, q, t, RK_ENV_SPH, sa, o, 0u);
+            }
+        }
+        any_hit = any_hit || hit;
+    }
+    if (__ballot(any_hit) && lane == 0) *s_hit = 1;
+}
+
 template <int KIND>
-__global__ __launch_bounds__(kWG, 4) void k_validate(CallDev cd)
+__global__ __launch_bounds__(kWG, kWGsPerCU) void k_validate(CallDev cd)
 {
     extern __shared__ float4 dyn[];
 
@@ -651,6 +791,10 @@ __global__ __launch_bounds__(kWG, 4) void k_validate(CallDev cd)
     __shared__ int s_q, s_nv, s_phase, s_hit, s_chunk;
     __shared__ unsigned s_key, s_rho2;
     __shared__ unsigned long long s_tp, s_ep;
+    // thread 0's claim state and tile counts, kept in LDS rather than registers
+    __shared__ long long s_kcur;
+    __shared__ int s_phase_cur;
+    __shared__ unsigned long long s_nrun, s_nskip, s_nstates;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -667,10 +811,14 @@ __global__ __launch_bounds__(kWG, 4) void k_validate(CallDev cd)
     const long long* off = reinterpret_cast<const long long*>(cd.off);
     const int M = cd.ctrl[0];
 
-    long long k_cur = 0;
-    int phase_cur = 0;
     unsigned long long c_rr = 0, c_env = 0, c_self = 0;                 // wave-uniform counters
-    unsigned long long n_run = 0, n_skip = 0, n_states = 0;             // thread 0
+    if (tid == 0) {
+        s_kcur = 0;
+        s_phase_cur = 0;
+        s_nrun = 0;
+        s_nskip = 0;
+        s_nstates = 0;
+    }
 
     for (;;) {
         if (tid == 0) {
@@ -682,10 +830,10 @@ __global__ __launch_bounds__(kWG, 4) void k_validate(CallDev cd)
                 if (hier) {
                     phase = g >= total ? 1 : 0;
                     gg = g - (long long)phase * total;
-                    if (phase != phase_cur) { phase_cur = phase; k_cur = 0; }
+                    if (phase != s_phase_cur) { s_phase_cur = phase; s_kcur = 0; }
                 }
                 // largest rank k with off[k] <= gg (ranks are non-empty below M; off[M] = total)
-                long long lo = k_cur;
+                long long lo = s_kcur;
                 if (off[lo + 1] <= gg) {
                     long long step = 1, hi;
                     lo = lo + 1;
@@ -701,7 +849,7 @@ __global__ __launch_bounds__(kWG, 4) void k_validate(CallDev cd)
                         if (off[mid] <= gg) lo = mid; else hi = mid;
                     }
                 }
-                k_cur = lo;
+                s_kcur = lo;
                 const int k = (int)lo;
                 q = cd.sorted_q[gg - off[lo]];
                 const TeamDev* tq = team_of(cd, q);
@@ -730,8 +878,8 @@ __global__ __launch_bounds__(kWG, 4) void k_validate(CallDev cd)
                     if (KIND == 0) skip = (known != 0u);
                     else skip = (known != 0xFFFFFFFFu) && (known < (unsigned)base * (unsigned)tq->P);
                 }
-                if (skip) { nv = 0; ++n_skip; }
-                else { ++n_run; n_states += (unsigned long long)nv * tq->n_robots; }
+                if (skip) { nv = 0; ++s_nskip; }
+                else { ++s_nrun; s_nstates += (unsigned long long)nv * tq->n_robots; }
             }
             s_q = q; s_phase = phase; s_nv = nv; s_chunk = C;
             s_hit = KIND == 0 && known != 0u; s_key = KIND == 1 ? known : 0xFFFFFFFFu; s_rho2 = 0u;
@@ -827,95 +975,17 @@ __global__ __launch_bounds__(kWG, 4) void k_validate(CallDev cd)
             const int ntask = nv * nch;
             float ro_max = 0.f;
             for (int o = 0; o < env.n_sph; ++o) ro_max = fmaxf(ro_max, cloadf(&env.sph32[o].w));
-            for (int task = wave; task < ntask; task += kWavesPerWG) {
-                if (!exhaustive && flag_read(&s_hit)) break;
-                const int c = task / nch;
-                const int a = (task - c * nch) * kWave + lane;     // slot
-                const float* row = sp + (long long)c * TS + a;
-                const float rad = a < GS ? row[3 * GSp] : 0.f;
-                const bool act = rad > 0.f;
-                float x = 1.0e18f, y = 1.0e18f, z = 1.0e18f;
-                if (act) {
-                    x = row[0] + ox;
-                    y = row[GSp] + oy;
-                    z = row[2 * GSp] + oz;
-                }
-                float mb = 3.0e38f, ms = 3.0e38f;
-#pragma unroll 2
-                for (int o = 0; o < env.n_box; ++o) mb = fminf(mb, box_val(x, y, z, (CFloat*)(env.box32 + o * 16)));
-#pragma unroll 2
-                for (int o = 0; o < env.n_cyl; ++o) mb = fminf(mb, cyl_val(x, y, z, (CFloat*)(env.cyl32 + o * 8)));
-                for (int o = 0; o < env.n_sph; ++o) {
-                    const float* ob = &env.sph32[o].x;
-                    const float Rs = rad + cloadf(ob + 3);
-                    const float dx = x - cloadf(ob), dy = y - cloadf(ob + 1), dz = z - cloadf(ob + 2);
-                    ms = fminf(ms, fmaf(-Rs, Rs, fmaf(dx, dx, fmaf(dy, dy, dz * dz))));
-                }
-                if (act) c_env += (unsigned long long)(env.n_sph + env.n_box + env.n_cyl);
-                const float rlo = fmaxf(rad - eps, 0.f), rhi = rad + eps;
-                const float Rb = rad + ro_max;
-                bool hit = false, unsure = false;
-                if (act) {
-                    hit = (mb < rlo * rlo) || (ms < -2.f * Rb * eps);
-                    unsure = !hit && ((mb <= rhi * rhi) || (ms <= fmaf(2.f * Rb, eps, eps * eps)));
-                }
-                const int sa = act ? tm.slot_sphere[a] : 0;
-                if (env.n_pts > 0 && act) {
-                    const float Rp = rad + env.pt_radius;
-                    const float xs[3] = { x, y, z };
-                    int lo3[3], hi3[3];
-                    const float reach = Rp + eps;
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        const int l = (int)floorf((xs[d] - reach - env.grid_lo[d]) * env.grid_inv);
-                        const int h = (int)floorf((xs[d] + reach - env.grid_lo[d]) * env.grid_inv);
-                        lo3[d] = l < 0 ? 0 : l;
-                        hi3[d] = h >= env.grid_dim[d] ? env.grid_dim[d] - 1 : h;
-                    }
-                    const float plo = fmaxf(Rp - eps, 0.f), phi = Rp + eps;
-                    const float plo2 = plo * plo, phi2 = phi * phi;
-                    if (lo3[0] <= hi3[0])
-                        for (int cz = lo3[2]; cz <= hi3[2]; ++cz)
-                            for (int cy = lo3[1]; cy <= hi3[1]; ++cy) {
-                                const int crow = (cz * env.grid_dim[1] + cy) * env.grid_dim[0];
-                                const int pb = env.cell_start[crow + lo3[0]];
-                                const int pe = env.cell_start[crow + hi3[0] + 1];
-                                for (int p = pb; p < pe; ++p) {
-                                    const float4 Pt = env.pts32[p];
-                                    const float dx = x - Pt.x, dy = y - Pt.y, dz = z - Pt.z;
-                                    const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                                    if (d2 <= phi2) {
-                                        if (d2 < plo2) hit = true;
-                                        else if (!hit && !flag_read(&s_hit))
-                                            push_recheck(cd, q, s_t[c], RK_ENV_PT, sa, p, 0u);
-                                    }
-                                }
-                            }
-                }
-                if (unsure && !(hit && !exhaustive)) {
-                    // rare: find the near obstacles and queue each for FP64 re-evaluation
-                    for (int o = 0; o < env.n_box; ++o) {
-                        const float v = box_val(x, y, z, (CFloat*)(env.box32 + o * 16));
-                        if (v < rlo * rlo) hit = true;
-                        else if (v <= rhi * rhi && !hit && !flag_read(&s_hit))
-                            push_recheck(cd, q, s_t[c], RK_ENV_BOX, sa, o, 0u);
-                    }
-                    for (int o = 0; o < env.n_cyl; ++o) {
-                        const float v = cyl_val(x, y, z, (CFloat*)(env.cyl32 + o * 8));
-                        if (v < rlo * rlo) hit = true;
-                        else if (v <= rhi * rhi && !hit && !flag_read(&s_hit))
-                            push_recheck(cd, q, s_t[c], RK_ENV_CYL, sa, o, 0u);
-                    }
-                    for (int o = 0; o < env.n_sph; ++o) {
-                        const float* ob = &env.sph32[o].x;
-                        const float dx = x - cloadf(ob), dy = y - cloadf(ob + 1), dz = z - cloadf(ob + 2);
-                        const int cl = classify(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), rad + cloadf(ob + 3), eps);
-                        if (cl == 1) hit = true;
-                        else if (cl == 2 && !hit && !flag_read(&s_hit))
-                            push_recheck(cd, q, s_t[c], RK_ENV_SPH, sa, o, 0u);
-                    }
-                }
-                if (__ballot(hit) && lane == 0) s_hit = 1;
+            // tasks task0, task0 + 4, ... of this wave, two at a time through each obstacle
+            int task = wave;
+            bool stop = false;
+            for (; task + kWavesPerWG < ntask; task += 2 * kWavesPerWG) {
+                if (!exhaustive && flag_read(&s_hit)) { stop = true; break; }
+                const int tk[2] = { task, task + kWavesPerWG };
+                env_tasks<2>(cd, tm, env, sp, tk, nch, ro_max, eps, exhaustive, q, s_t, &s_hit, c_env, lane);
+            }
+            if (task < ntask && !stop && !(!exhaustive && flag_read(&s_hit))) {
+                const int tk[1] = { task };
+                env_tasks<1>(cd, tm, env, sp, tk, nch, ro_max, eps, exhaustive, q, s_t, &s_hit, c_env, lane);
             }
         }
 
@@ -1017,8 +1087,8 @@ __global__ __launch_bounds__(kWG, 4) void k_validate(CallDev cd)
                                 }
 #pragma unroll
                                 for (int v = 0; v < 4; ++v) d[v] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, bop[v], acc, 0, 0, 0);
-#pragma unroll
-                                for (int v = 0; v < 4; ++v) best = block_min(d[v], wb[v], best);
+                                best = fminf(best, fminf(fminf(col_min(d[0], wb[0]), col_min(d[1], wb[1])),
+                                                         fminf(col_min(d[2], wb[2]), col_min(d[3], wb[3]))));
                             }
                             for (; g < g1; ++g) {
                                 const float bop = base[q4 * GSp + g * 16 + i16];
@@ -1067,9 +1137,9 @@ __global__ __launch_bounds__(kWG, 4) void k_validate(CallDev cd)
     }
     if (c_env) atomicAdd(&cd.stats[ST_ENV_TESTS], c_env);
     if (tid == 0) {
-        atomicAdd(&cd.stats[ST_TILES_RUN], n_run);
-        atomicAdd(&cd.stats[ST_TILES_SKIPPED], n_skip);
-        atomicAdd(&cd.stats[ST_STATES_EVAL], n_states);
+        atomicAdd(&cd.stats[ST_TILES_RUN], s_nrun);
+        atomicAdd(&cd.stats[ST_TILES_SKIPPED], s_nskip);
+        atomicAdd(&cd.stats[ST_STATES_EVAL], s_nstates);
     }
 }
 

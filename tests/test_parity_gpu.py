@@ -221,3 +221,44 @@ def test_invalid_inputs_rejected(ctx):
     assert o.cpu().numpy()[0] == 2
     ctx.sync()   # error reported once
     del out
+
+
+@pytest.mark.parametrize("value", [float("nan"), float("inf"), 2.0e6])
+def test_out_of_range_values_rejected(ctx, value):
+    """Every floating-point input must be finite and within MRV_MAX_COORD: the
+    host checks teams, environments and host paths, the device checks the paths
+    of device calls (by an integer test on the bits, valid in the kernels' no-NaN
+    build)."""
+    import dataclasses
+    import torch
+    say("out-of-range input", value)
+    w = W.arms_workload(8)
+    team, env = ctx.load_team(w.team), ctx.load_env(w.env)
+    bad = W.paths_from_lists([[w.paths.path(q, r) for r in range(4)] for q in range(8)], 7)
+    bad.wp_q = bad.wp_q.copy()
+    bad.wp_q[bad.wp_begin[3 * 4 + 2] + 1, 3] = value      # query 3, robot 2, second waypoint
+    with pytest.raises(mrv.MrvError) as e:
+        ctx.mv(team, env, bad, mrv.CHECK_ENV)
+    assert e.value.status == mrv.MRV_E_INVALID
+    o = torch.zeros(8, dtype=torch.uint8, device="cuda")
+    ctx.mv_device(team, env, mrv.DevicePaths(bad), mrv.CHECK_ENV, o.data_ptr())
+    with pytest.raises(mrv.MrvError):
+        ctx.sync()
+    got = o.cpu().numpy()
+    assert got[3] == 2
+    ok = np.arange(8) != 3
+    ref = oracle.mv(oracle.Team(w.team), oracle.Env(w.env), oracle.Paths(w.paths.subset(np.arange(8))))
+    assert np.array_equal(got[ok], ref[ok])
+
+    boxes = w.env.boxes.copy()
+    boxes[5, 1] = value
+    with pytest.raises(mrv.MrvError) as e:
+        ctx.load_env(dataclasses.replace(w.env, boxes=boxes))
+    assert e.value.status == mrv.MRV_E_INVALID
+    robots = list(w.team)
+    sx = robots[1].sphere_xyzr.copy()
+    sx[7, 0] = value
+    robots[1] = dataclasses.replace(robots[1], sphere_xyzr=sx)
+    with pytest.raises(mrv.MrvError) as e:
+        ctx.load_team(robots)
+    assert e.value.status == mrv.MRV_E_INVALID
