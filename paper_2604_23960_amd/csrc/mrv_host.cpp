@@ -534,13 +534,15 @@ int default_chunk(const TeamHost& tm, int kind, int exhaustive)
     cmax = std::min(cmax, kMaxChunk);
     if (cmax < 1) cmax = 1;
     // early-terminating calls: long tiles, since most queries end in their first
-    // tiles, whose fixed cost then dominates -- FFC 16 timesteps, MV the most that
-    // keep two workgroups per CU (at least 8, at most 16); exhaustive calls: up to 8,
+    // tiles, whose fixed cost then dominates -- FFC 16 timesteps; MV the most that
+    // keep two workgroups per CU if that is at least 12 (at most 16), else 16 (as
+    // many as fit); exhaustive calls: up to 8,
     // the largest that keeps five workgroups per CU (the register limit) within its
     // 160 KiB of LDS if that is at least 2, else four, three, two, one
     if (!exhaustive) {
         int c = 16;
-        if (kind == 0) c = std::max(8, std::min(16, (int)((160 * 1024 / 2 - 1024) / per_t)));
+        const int c2 = (int)((160 * 1024 / 2 - 1024) / per_t);
+        if (kind == 0 && c2 >= 12) c = std::min(16, c2);
         return std::max(1, std::min(cmax, c));
     }
     for (int wgs = kWGsPerCU; wgs >= 1; --wgs) {

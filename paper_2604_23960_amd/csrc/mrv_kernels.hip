@@ -975,15 +975,17 @@ __global__ __launch_bounds__(kWG, kWGsPerCU) void k_validate(CallDev cd)
             const int ntask = nv * nch;
             float ro_max = 0.f;
             for (int o = 0; o < env.n_sph; ++o) ro_max = fmaxf(ro_max, cloadf(&env.sph32[o].w));
-            // tasks task0, task0 + 4, ... of this wave, two at a time through each obstacle
+            // tasks wave, wave + 4, ... of this wave: exhaustive calls take two at a time
+            // through each obstacle; early-terminating calls one at a time, so a hit
+            // stops the wave before its next task
             int task = wave;
-            bool stop = false;
-            for (; task + kWavesPerWG < ntask; task += 2 * kWavesPerWG) {
-                if (!exhaustive && flag_read(&s_hit)) { stop = true; break; }
-                const int tk[2] = { task, task + kWavesPerWG };
-                env_tasks<2>(cd, tm, env, sp, tk, nch, ro_max, eps, exhaustive, q, s_t, &s_hit, c_env, lane);
+            if (exhaustive) {
+                for (; task + kWavesPerWG < ntask; task += 2 * kWavesPerWG) {
+                    const int tk[2] = { task, task + kWavesPerWG };
+                    env_tasks<2>(cd, tm, env, sp, tk, nch, ro_max, eps, exhaustive, q, s_t, &s_hit, c_env, lane);
+                }
             }
-            if (task < ntask && !stop && !(!exhaustive && flag_read(&s_hit))) {
+            for (; task < ntask && !(!exhaustive && flag_read(&s_hit)); task += kWavesPerWG) {
                 const int tk[1] = { task };
                 env_tasks<1>(cd, tm, env, sp, tk, nch, ro_max, eps, exhaustive, q, s_t, &s_hit, c_env, lane);
             }
