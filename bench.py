@@ -93,6 +93,86 @@ def run_device(ctx, team, env, dp, kind, flags, out, steps, warmup):
     return wall, kernel_ms, stats
 
 
+def ordering_study(log, n_motions=4096, step=1.0 / 128, max_rounds=64):
+    """Early-termination orders on ring teams of 4, 8 and 16 arms, with the arm
+    workload's obstacle field inside the ring and without obstacles (self tests
+    still on), over random
+    straight-line motions whose endpoints are valid (each robot moves at most
+    `step` in L2 per timestep, the composite motion time-scaled to the slowest).
+    Endpoint validity is decided by this library (MV of single-state motions).
+    For every order: kernel time per call, effort (robot-states evaluated per
+    robot-state covered) and the valid fraction; exhaustive MV for reference.
+    Endpoints are composed from per-robot configurations that are valid alone
+    (self and obstacle tests of a one-robot team), then kept if the whole team's
+    state is valid."""
+    import torch
+    from paper_2604_23960_amd import mrv
+    from paper_2604_23960_amd import workloads as W
+    orders = [("combined-bisect", 0), ("combined-rake", mrv.ORDER_RAKE), ("combined-linear", mrv.ORDER_LINEAR),
+              ("hierarchical-bisect", mrv.HIERARCHICAL), ("hierarchical-rake", mrv.HIERARCHICAL | mrv.ORDER_RAKE),
+              ("hierarchical-linear", mrv.HIERARCHICAL | mrv.ORDER_LINEAR)]
+    ctx = mrv.Context(0)
+    rows = []
+    for n_arms in (4, 8, 16):
+        team = W.ring_team(n_arms)
+        th = ctx.load_team(team)
+        dofs = [r.dof for r in team]
+        for env_name in ("obstacles", "empty"):
+            env = W.cube_env(1) if env_name == "obstacles" else W.Env()     # obstacles inside the ring
+            eh = ctx.load_env(env)
+            rng = np.random.default_rng(1000 + n_arms)
+            alone = []
+            for rob in team:                     # configurations valid for the robot alone
+                h1 = ctx.load_team([rob])
+                good = np.zeros((0, 1, 7))
+                for _ in range(max_rounds):
+                    if len(good) >= 4 * n_motions:
+                        break
+                    cand = W.sample_configs(rng, [rob], 8192, 7)
+                    ok = ctx.mv(h1, eh, W.straight_line_paths(cand, cand, [rob.dof], step, "l2", 7),
+                                mrv.CHECK_ENV).astype(bool)
+                    good = np.concatenate([good, cand[ok]])
+                ctx.unload(h1)
+                alone.append(good[:, 0, :])
+            pool, tried = [], 0
+            if min(len(a) for a in alone) > 0:
+                for _ in range(max_rounds):
+                    if len(pool) >= 2 * n_motions:
+                        break
+                    cand = np.stack([a[rng.integers(0, len(a), 8192)] for a in alone], axis=1)
+                    one = W.straight_line_paths(cand, cand, dofs, step, "l2", 7)     # single-state motions
+                    ok = ctx.mv(th, eh, one, mrv.CHECK_ENV).astype(bool)
+                    tried += len(cand)
+                    pool.extend(cand[ok])
+            m = min(n_motions, len(pool) // 2)
+            row = dict(arms=n_arms, env=env_name, motions=m, endpoint_acceptance=len(pool) / max(tried, 1))
+            if m == 0:
+                log(f"ordering study: {n_arms} arms, {env_name}: no valid endpoints")
+                rows.append(row)
+                ctx.unload(eh)
+                continue
+            pool = np.asarray(pool)
+            paths = W.straight_line_paths(pool[:m], pool[m:2 * m], dofs, step, "l2", 7)
+            row["mean_T"] = float(paths.horizon().mean())
+            dp = mrv.DevicePaths(paths)
+            out = torch.zeros(m, dtype=torch.uint8, device="cuda")
+            for name, fl in orders:
+                _, kms, st = run_device(ctx, th, eh, dp, 0, mrv.CHECK_ENV | fl, out, 3, 1)
+                row[name] = dict(kernel_ms=float(np.median(kms)),
+                                 effort=st["states_evaluated"] / max(st["states_covered"], 1))
+            row["valid_fraction"] = float(out.float().mean().item())
+            _, kms, st = run_device(ctx, th, eh, dp, 0, mrv.CHECK_ENV | mrv.EXHAUSTIVE, out, 3, 1)
+            row["exhaustive"] = dict(kernel_ms=float(np.median(kms)), effort=1.0)
+            best = min((n for n, _ in orders), key=lambda n: row[n]["kernel_ms"])
+            log(f"ordering study: {n_arms} arms, {env_name}: {m} motions, valid {row['valid_fraction']:.3f}, "
+                f"fastest {best} {row[best]['kernel_ms']:.3f} ms, exhaustive {row['exhaustive']['kernel_ms']:.3f} ms")
+            rows.append(row)
+            ctx.unload(eh)
+        ctx.unload(th)
+    ctx.close()
+    return rows
+
+
 def serving_bench(log, n_requests=3000, n_plain=400):
     """Served (mrv_submit/mrv_wait, continuous batching) vs plain (one synchronous
     call per query) on 64 simulated clients with resident teams of 2-8 robots."""
@@ -240,6 +320,8 @@ def main():
     ap.add_argument("--cpu-queries", type=int, default=65536, help="upper bound on the oracle sample")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (HBM counter calibration)")
+    ap.add_argument("--ordering-study", type=int, default=0, metavar="MOTIONS",
+                    help="only run the early-termination ordering study with this many motions per team")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
@@ -252,6 +334,11 @@ def main():
 
     def log(*a):
         print("[bench]", *a, file=sys.stderr, flush=True)
+
+    if args.ordering_study > 0:
+        print(json.dumps(dict(study="mv-ordering", step_l2=1.0 / 128,
+                              rows=ordering_study(log, args.ordering_study))), flush=True)
+        return
 
     if args.copy_calib_mib > 0:
         n = args.copy_calib_mib * (1 << 20) // 4

@@ -227,6 +227,25 @@ def arm_team(seed: int = 1) -> list[Robot]:
     return [m.with_base(arm_base(x, y)) for m, (x, y) in zip(arm_models(seed), CORNERS)]
 
 
+def ring_radius(n_arms: int) -> float:
+    """Base circle of a ring team: the arm workload's corner distance for four
+    arms, else about 1 m between neighbouring bases."""
+    return max(math.hypot(*CORNERS[0]), n_arms / (2.0 * math.pi))
+
+
+def ring_team(n_arms: int, seed: int = 1) -> list[Robot]:
+    """n_arms copies of the four seeded arm models (cycled) on a circle, facing
+    its centre; four arms sit on the arm workload's corners."""
+    models = arm_models(seed)
+    R = ring_radius(n_arms)
+    team = []
+    for k in range(n_arms):
+        ang = math.pi / 4 + 2.0 * math.pi * k / n_arms
+        x, y = R * math.cos(ang), R * math.sin(ang)
+        team.append(models[k % 4].with_base(arm_base(x, y), f"arm{k}"))
+    return team
+
+
 # ----------------------------------------------------------------------------
 # environments
 
