@@ -78,7 +78,7 @@ def lib():
             L.orc_path_state.restype = None
             L.orc_query_horizon.argtypes = [P, I64]
             L.orc_query_horizon.restype = I64
-            L.orc_mv.argtypes = [P, P, P, I64, I64, I32, I32, P, P, I32]
+            L.orc_mv.argtypes = [P, P, P, I64, I64, I32, I32, C.c_uint32, P, P, I32]
             L.orc_mv.restype = C.c_int
             L.orc_ffc.argtypes = [P, P, I64, I64, P, I32]
             L.orc_ffc.restype = C.c_int
@@ -170,13 +170,17 @@ class Paths:
 
 
 def mv(team: Team, env: Env | None, paths: Paths, check_env: bool = True, q0: int = 0,
-       q1: int | None = None, nthreads: int = 0, first_hit: bool = False, exhaustive: bool = False):
+       q1: int | None = None, nthreads: int = 0, first_hit: bool = False, exhaustive: bool = False,
+       focus: int = 0):
+    """MV (Alg. 1).  focus: bit r puts robot r in focus (prioritised MV, §III-C):
+    only robots in focus get obstacle and self tests, and only robot pairs with a
+    robot in focus are tested; 0 = every robot."""
     q1 = paths.py.n_queries if q1 is None else q1
     out = np.zeros(q1 - q0, np.uint8)
     fh = np.zeros(q1 - q0, np.int64) if first_hit else None
     rc = lib().orc_mv(C.byref(team.c), C.byref(env.c) if env is not None else None,
-                      C.byref(paths.c), q0, q1, int(bool(check_env)), int(bool(exhaustive)), _ptr(out),
-                      _ptr(fh) if fh is not None else None, nthreads)
+                      C.byref(paths.c), q0, q1, int(bool(check_env)), int(bool(exhaustive)), int(focus) & 0xFFFFFFFF,
+                      _ptr(out), _ptr(fh) if fh is not None else None, nthreads)
     if rc != 0:
         raise MemoryError("oracle MV failed")
     return (out, fh) if first_hit else out

@@ -446,8 +446,19 @@ static int team_total_spheres(const orc_team* tm) { return tm->sphere_off[tm->n_
 /* MV of one query.  Returns 1 valid, 0 invalid.  first_hit (optional) gets the
  * first colliding timestep of the ascending scan, -1 if valid.  exhaustive = 1
  * evaluates every relation at every state instead of stopping (same answer). */
+/* Prioritised MV (PP-ST-RRT, §III-C): a robot is planned against the fixed paths
+ * of others.  Robot r is in focus iff bit r of focus is set; focus = 0 puts every
+ * robot in focus (plain MV). */
+static int in_focus(uint32_t focus, int r)
+{
+    return focus == 0 || ((focus >> r) & 1u);
+}
+
+/* MV of one query (Alg. 1 as a plain scan): at every timestep, the obstacle and
+ * self tests of each robot in focus, then every robot pair with at least one
+ * robot in focus. */
 static int mv_one(const orc_team* tm, const orc_env* E, const orc_paths* P, int64_t qi,
-                  int check_env, int exhaustive, double* buf, int64_t* first_hit)
+                  int check_env, int exhaustive, uint32_t focus, double* buf, int64_t* first_hit)
 {
     int n = tm->n_robots;
     int64_t T = orc_query_horizon(P, qi);
@@ -458,10 +469,12 @@ static int mv_one(const orc_team* tm, const orc_env* E, const orc_paths* P, int6
             robot_spheres_at(tm, P, qi, r, t, buf + (int64_t)tm->sphere_off[r] * 4);
         if (check_env)
             for (int r = 0; r < n && (exhaustive || !hit); ++r)
-                hit |= env_self_hit(tm, E, r, buf + (int64_t)tm->sphere_off[r] * 4, exhaustive);
+                if (in_focus(focus, r))
+                    hit |= env_self_hit(tm, E, r, buf + (int64_t)tm->sphere_off[r] * 4, exhaustive);
         for (int i = 0; i + 1 < n && (exhaustive || !hit); ++i)
             for (int j = i + 1; j < n && (exhaustive || !hit); ++j)
-                hit |= pair_hit(buf + (int64_t)tm->sphere_off[i] * 4, tm->sphere_off[i + 1] - tm->sphere_off[i],
+                if (in_focus(focus, i) || in_focus(focus, j))
+                    hit |= pair_hit(buf + (int64_t)tm->sphere_off[i] * 4, tm->sphere_off[i + 1] - tm->sphere_off[i],
                                 buf + (int64_t)tm->sphere_off[j] * 4, tm->sphere_off[j + 1] - tm->sphere_off[j],
                                 exhaustive);
         if (hit && fh < 0) {
@@ -504,9 +517,11 @@ static int set_threads(int nthreads)
 
 /* MV over queries [q0, q1).  env may be NULL (no obstacles).  check_env = 0 skips
  * robot-obstacle and self checks; exhaustive = 1 evaluates every relation at every
- * state.  valid_out[q - q0]; first_hit_out optional. */
+ * state; focus selects the robots validated (in_focus).  valid_out[q - q0];
+ * first_hit_out optional. */
 int orc_mv(const orc_team* tm, const orc_env* E, const orc_paths* P, int64_t q0, int64_t q1,
-           int32_t check_env, int32_t exhaustive, uint8_t* valid_out, int64_t* first_hit_out, int32_t nthreads)
+           int32_t check_env, int32_t exhaustive, uint32_t focus, uint8_t* valid_out, int64_t* first_hit_out,
+           int32_t nthreads)
 {
     set_threads(nthreads);
     int S = team_total_spheres(tm);
@@ -521,7 +536,7 @@ int orc_mv(const orc_team* tm, const orc_env* E, const orc_paths* P, int64_t q0,
 #pragma omp for schedule(dynamic, 4)
             for (int64_t qi = q0; qi < q1; ++qi) {
                 int64_t fh = -1;
-                valid_out[qi - q0] = (uint8_t)mv_one(tm, E, P, qi, check_env, exhaustive, buf, &fh);
+                valid_out[qi - q0] = (uint8_t)mv_one(tm, E, P, qi, check_env, exhaustive, focus, buf, &fh);
                 if (first_hit_out) first_hit_out[qi - q0] = fh;
             }
             free(buf);

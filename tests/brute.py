@@ -120,11 +120,13 @@ def env_hit(team, env, sph_t, r):
     return False
 
 
-def mv(team, env, paths, qi, check_env=True):
+def mv(team, env, paths, qi, check_env=True, focus=None):
+    """focus: robots validated (a set of indices; None = all), prioritised MV."""
+    F = set(range(len(team))) if focus is None else set(focus)
     for sph_t in team_states(team, paths, qi):
-        if check_env and any(env_hit(team, env, sph_t, r) for r in range(len(team))):
+        if check_env and any(env_hit(team, env, sph_t, r) for r in F):
             return False
-        if rr_hits(sph_t):
+        if any(i in F or j in F for (i, j) in rr_hits(sph_t)):
             return False
     return True
 

@@ -472,3 +472,72 @@ def test_exhaustive_scan_gives_the_same_answers():
         v0, f0 = oracle.mv(ot, oe, op, check_env=check_env, first_hit=True)
         v1, f1 = oracle.mv(ot, oe, op, check_env=check_env, first_hit=True, exhaustive=True)
         assert np.array_equal(v0, v1) and np.array_equal(f0, f1)
+
+
+# ----------------------------------------------------------------------------- prioritised MV
+
+def _mask(robots):
+    return sum(1 << r for r in robots)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_focus_matches_brute_force_tiny(seed):
+    """Prioritised MV (§III-C, PP-ST-RRT): the oracle against the brute-force
+    definition (obstacle and self tests of the robots in focus, robot pairs with
+    a robot in focus) for random focus sets."""
+    rng = np.random.default_rng(700 + seed)
+    n_diff = 0
+    for _ in range(5):
+        n = int(rng.integers(2, 4))
+        team = tiny_team(rng, n)
+        env = tiny_env(rng)
+        paths = tiny_paths(rng, team, 10, 14)
+        ot, oe, op = oracle.Team(team), oracle.Env(env), oracle.Paths(paths)
+        full = oracle.mv(ot, oe, op, check_env=True)
+        for _ in range(3):
+            F = [r for r in range(n) if rng.random() < 0.5] or [int(rng.integers(0, n))]
+            for check_env in (True, False):
+                got = oracle.mv(ot, oe, op, check_env=check_env, focus=_mask(F))
+                for q in range(paths.n_queries):
+                    assert bool(got[q]) == brute.mv(team, env, paths, q, check_env, focus=F)
+            n_diff += int(np.sum(oracle.mv(ot, oe, op, focus=_mask(F)) != full))
+    assert n_diff > 0       # some focus sets must drop a collision the full check sees
+
+
+def test_focus_decomposes_full_mv(arms_small):
+    """Every relation of MV belongs to the focus set of one of its robots, so a
+    motion is valid iff it is valid with each single robot in focus; a larger
+    focus set can only invalidate more."""
+    w, ot, oe, op = arms_small
+    for check_env in (True, False):
+        full = oracle.mv(ot, oe, op, check_env=check_env)
+        single = [oracle.mv(ot, oe, op, check_env=check_env, focus=1 << r) for r in range(4)]
+        assert np.array_equal(full, np.logical_and.reduce(single).astype(np.uint8))
+        pair01 = oracle.mv(ot, oe, op, check_env=check_env, focus=0b0011)
+        assert np.all(pair01 <= single[0]) and np.all(pair01 <= single[1])
+        assert np.array_equal(oracle.mv(ot, oe, op, check_env=check_env, focus=0b1111), full)
+        assert np.array_equal(oracle.mv(ot, oe, op, check_env=check_env, focus=0), full)
+        assert any(not np.array_equal(s, full) for s in single)
+
+
+def test_focus_skips_pairs_of_fixed_robots():
+    """Three disks of radius 0.1 (contact at centre distance 0.2): disks 1 and 2
+    overlap at every step (fixed, higher-priority paths that collide with each
+    other); disk 0 sweeps along y = y0 and passes disk 1 at t = 5 at distance
+    0.5 - y0: clear for y0 = 0.25, a collision for y0 = 0.35."""
+    team = [W.disk_robot(0.1, f"d{k}") for k in range(3)]
+    ot = oracle.Team(team)
+
+    def paths(y0):
+        rows = [(np.array([0, 10]), np.array([[-1.0, y0], [1.0, y0]])),     # disk 0 sweeps x in [-1, 1]
+                (np.array([0]), np.array([[0.0, 0.5]])),                    # disk 1 rests at (0, 0.5)
+                (np.array([0]), np.array([[0.05, 0.5]]))]                   # disk 2 rests 0.05 from disk 1
+        return W.paths_from_lists([rows], 2)
+
+    clear, hit = oracle.Paths(paths(0.25)), oracle.Paths(paths(0.35))
+    assert oracle.mv(ot, None, clear, check_env=False, focus=0b001)[0] == 1
+    assert oracle.mv(ot, None, clear, check_env=False, focus=0b011)[0] == 0       # pair (1, 2) collides
+    assert oracle.mv(ot, None, clear, check_env=False, focus=0b010)[0] == 0
+    assert oracle.mv(ot, None, clear, check_env=False)[0] == 0
+    assert oracle.mv(ot, None, hit, check_env=False, focus=0b001)[0] == 0
+    assert oracle.mv(ot, None, hit, check_env=False, focus=0b100)[0] == 0      # pair (1, 2)
