@@ -189,6 +189,20 @@ mrv_status mrv_mv_device(mrv_ctx ctx, int32_t team, int32_t env, const mrv_paths
                          uint32_t flags, uint8_t* valid_out);
 mrv_status mrv_ffc_device(mrv_ctx ctx, int32_t team, const mrv_paths* paths, uint32_t flags,
                           mrv_conflict* out);
+
+/* Prioritised MV (the PP-ST-RRT use of MV in §III-C: a robot is planned against
+ * the fixed paths of higher-priority robots).  As mrv_mv / mrv_mv_device, but
+ * only the robots in `focus` (bit r = robot r of the team) are validated: their
+ * obstacle and self tests (with MRV_CHECK_ENV) and every robot pair with at
+ * least one robot in focus.  Pairs of robots outside focus are not tested, so
+ * collisions among the fixed paths do not invalidate the motion.  focus = 0, or
+ * every robot of the team, is plain MV; bits at or above the team's robot count
+ * are ignored. */
+mrv_status mrv_mv_focus(mrv_ctx ctx, int32_t team, int32_t env, const mrv_paths* paths, uint32_t flags,
+                        uint32_t focus, uint8_t* valid_out);
+mrv_status mrv_mv_focus_device(mrv_ctx ctx, int32_t team, int32_t env, const mrv_paths* paths,
+                               uint32_t flags, uint32_t focus, uint8_t* valid_out);
+
 /* Wait for the context stream; report device-side input errors since the last
  * sync (MRV_E_INVALID), then unresolved queries (MRV_E_NOMEM; the queue is then
  * enlarged to what the largest of those calls needed, so repeating them
@@ -267,6 +281,7 @@ typedef struct {
     int32_t team, env;       /* env = -1: none */
     uint32_t flags;
     mrv_paths paths;         /* host arrays, copied by mrv_submit */
+    uint32_t focus;          /* MV: robots validated as in mrv_mv_focus; 0 = all (FFC: ignored) */
 } mrv_request;
 
 /* Queue a request for the serving loop; returns once its inputs are copied.

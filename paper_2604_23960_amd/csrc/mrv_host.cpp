@@ -630,6 +630,8 @@ void run_plan(mrv_ctx ctx, Scratch& sc, const CallPlan& pl, void* out_dev, hipSt
     cd.env0 = pl.env0;
     cd.q_env = pl.q_env;
     cd.q_pathoff = pl.q_pathoff;
+    cd.focus0 = pl.focus;
+    cd.q_focus = pl.q_focus;
     cd.eps32 = (float)ctx->eps;
     cd.eps64 = ctx->eps;
     cd.n_wp = pl.dp.n_wp;
@@ -668,11 +670,12 @@ void run_plan(mrv_ctx ctx, Scratch& sc, const CallPlan& pl, void* out_dev, hipSt
 
 // Plan for a call whose queries all use one team and environment.
 CallPlan single_plan(const TeamHost& tm, const EnvHost* env, int kind, uint32_t flags, const DevPaths& dp,
-                     long long max_T)
+                     long long max_T, uint32_t focus = 0)
 {
     CallPlan pl{};
     pl.kind = kind;
     pl.flags = flags;
+    pl.focus = focus;
     pl.dp = dp;
     pl.team0 = tm.d_dev;
     pl.env0 = env ? env->d_dev : nullptr;
@@ -700,7 +703,8 @@ const EnvHost* find_env(mrv_ctx ctx, int h)
 }
 
 // Host-array call: validate, upload, run, download, wait.
-void host_call(mrv_ctx ctx, int team, int env, int kind, const mrv_paths* p, uint32_t flags, void* out_host)
+void host_call(mrv_ctx ctx, int team, int env, int kind, const mrv_paths* p, uint32_t flags, void* out_host,
+               uint32_t focus = 0)
 {
     set_device(ctx);
     TeamHost tm;
@@ -731,7 +735,7 @@ void host_call(mrv_ctx ctx, int team, int env, int kind, const mrv_paths* p, uin
     HIPCHK(hipMemcpyAsync(ctx->in_q.p, p->wp_q, nq, hipMemcpyHostToDevice, ctx->stream));
     DevPaths dp{(const long long*)ctx->in_begin.p, (const int*)ctx->in_t.p, (const double*)ctx->in_q.p,
                 p->n_wp, p->n_queries, p->dof_stride};
-    const CallPlan pl = single_plan(tm, ev, kind, flags, dp, max_horizon(p, n));
+    const CallPlan pl = single_plan(tm, ev, kind, flags, dp, max_horizon(p, n), focus);
     // a call whose near tests overflow the queue runs again with a queue that fits
     for (int attempt = 0;; ++attempt) {
         run_plan(ctx, ctx->sc, pl, ctx->out_buf.p, ctx->stream);
@@ -752,7 +756,8 @@ void host_call(mrv_ctx ctx, int team, int env, int kind, const mrv_paths* p, uin
     HIPCHK(hipStreamSynchronize(ctx->stream));
 }
 
-void device_call(mrv_ctx ctx, int team, int env, int kind, const mrv_paths* p, uint32_t flags, void* out_dev)
+void device_call(mrv_ctx ctx, int team, int env, int kind, const mrv_paths* p, uint32_t flags, void* out_dev,
+                 uint32_t focus = 0)
 {
     set_device(ctx);
     TeamHost tm;
@@ -773,7 +778,7 @@ void device_call(mrv_ctx ctx, int team, int env, int kind, const mrv_paths* p, u
     if (p->n_wp < 1) throw Err{MRV_E_INVALID, "n_wp must be positive"};
     if (p->dof_stride < tm.max_dof) throw Err{MRV_E_INVALID, "dof_stride smaller than the team's largest dof"};
     DevPaths dp{(const long long*)p->wp_begin, p->wp_t, p->wp_q, p->n_wp, p->n_queries, p->dof_stride};
-    run_plan(ctx, ctx->sc, single_plan(tm, ev, kind, flags, dp, MRV_MAX_T), out_dev, ctx->stream);
+    run_plan(ctx, ctx->sc, single_plan(tm, ev, kind, flags, dp, MRV_MAX_T, focus), out_dev, ctx->stream);
 }
 
 uint32_t check_flags(int kind, uint32_t flags)
@@ -935,6 +940,27 @@ mrv_status mrv_mv(mrv_ctx ctx, int32_t team, int32_t env, const mrv_paths* paths
     return wrap([&] {
         const uint32_t f = check_flags(0, flags);
         host_call(ctx, team, env, 0, paths, f, valid_out);
+    });
+}
+
+mrv_status mrv_mv_focus(mrv_ctx ctx, int32_t team, int32_t env, const mrv_paths* paths, uint32_t flags,
+                        uint32_t focus, uint8_t* valid_out)
+{
+    if (guard(ctx)) return MRV_E_HANDLE;
+    if (!valid_out && paths && paths->n_queries > 0) return fail(MRV_E_INVALID, "null valid_out");
+    return wrap([&] {
+        const uint32_t f = check_flags(0, flags);
+        host_call(ctx, team, env, 0, paths, f, valid_out, focus);
+    });
+}
+
+mrv_status mrv_mv_focus_device(mrv_ctx ctx, int32_t team, int32_t env, const mrv_paths* paths, uint32_t flags,
+                               uint32_t focus, uint8_t* valid_out)
+{
+    if (guard(ctx)) return MRV_E_HANDLE;
+    return wrap([&] {
+        const uint32_t f = check_flags(0, flags);
+        device_call(ctx, team, env, 0, paths, f, valid_out, focus);
     });
 }
 

@@ -103,6 +103,8 @@ struct CallDev {
     const EnvDev* env0;         // null: no obstacles
     const EnvDev* const* q_env;
     const long long* q_pathoff;
+    unsigned focus0;            // robots validated (bit r), 0 = all: prioritised MV
+    const unsigned* q_focus;    // per query, or null: focus0 for every query
     float eps32;
     double eps64;
     long long n_wp;

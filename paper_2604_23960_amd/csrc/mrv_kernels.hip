@@ -664,7 +664,8 @@ __device__ __forceinline__ float4 place32(const float4* Fp, float4 L)
 template <int J>
 __device__ __forceinline__ void env_tasks(const CallDev& cd, const TeamDev& tm, const EnvDev& env, const float* sp,
                                           const int* task, int nch, float ro_max, float eps, bool exhaustive, int q,
-                                          const int* s_t, int* s_hit, unsigned long long& c_env, int lane)
+                                          unsigned focus, bool fall, const int* s_t, int* s_hit,
+                                          unsigned long long& c_env, int lane)
 {
     const int GS = tm.GS, GSp = tm.GSp, TS = tm.TS;
     int c[J], a[J];
@@ -677,6 +678,7 @@ __device__ __forceinline__ void env_tasks(const CallDev& cd, const TeamDev& tm, 
         const float* row = sp + (long long)c[j] * TS + a[j];
         rad[j] = a[j] < GS ? row[3 * GSp] : 0.f;
         act[j] = rad[j] > 0.f;
+        if (act[j] && !fall) act[j] = ((focus >> tm.s_robot[tm.slot_sphere[a[j]]]) & 1u) != 0;
         x[j] = 1.0e18f; y[j] = 1.0e18f; z[j] = 1.0e18f;
         if (act[j]) {
             x[j] = row[0] + tm.origin[0];
@@ -791,6 +793,7 @@ __global__ __launch_bounds__(kWG, kWGsPerCU) void k_validate(CallDev cd)
     __shared__ int s_q, s_nv, s_phase, s_hit, s_chunk;
     __shared__ unsigned s_key, s_rho2;
     __shared__ unsigned long long s_tp, s_ep;
+    __shared__ unsigned s_focus;
     // thread 0's claim state and tile counts, kept in LDS rather than registers
     __shared__ long long s_kcur;
     __shared__ int s_phase_cur;
@@ -824,7 +827,7 @@ __global__ __launch_bounds__(kWG, kWGsPerCU) void k_validate(CallDev cd)
         if (tid == 0) {
             const long long g = (long long)atomicAdd(&w64[1], 1ull);
             int q = -1, nv = 0, phase = 0, C = 1;
-            unsigned known = KIND == 1 ? 0xFFFFFFFFu : 0u;
+            unsigned known = KIND == 1 ? 0xFFFFFFFFu : 0u, focus = 0u;
             if (g < gtotal) {
                 long long gg = g;
                 if (hier) {
@@ -852,6 +855,7 @@ __global__ __launch_bounds__(kWG, kWGsPerCU) void k_validate(CallDev cd)
                 s_kcur = lo;
                 const int k = (int)lo;
                 q = cd.sorted_q[gg - off[lo]];
+                focus = cd.q_focus ? cd.q_focus[q] : cd.focus0;
                 const TeamDev* tq = team_of(cd, q);
                 const EnvDev* eq = env_of(cd, q);
                 s_tp = (unsigned long long)tq;
@@ -881,7 +885,7 @@ __global__ __launch_bounds__(kWG, kWGsPerCU) void k_validate(CallDev cd)
                 if (skip) { nv = 0; ++s_nskip; }
                 else { ++s_nrun; s_nstates += (unsigned long long)nv * tq->n_robots; }
             }
-            s_q = q; s_phase = phase; s_nv = nv; s_chunk = C;
+            s_q = q; s_phase = phase; s_nv = nv; s_chunk = C; s_focus = focus;
             s_hit = KIND == 0 && known != 0u; s_key = KIND == 1 ? known : 0xFFFFFFFFu; s_rho2 = 0u;
         }
         __syncthreads();
@@ -897,10 +901,15 @@ __global__ __launch_bounds__(kWG, kWGsPerCU) void k_validate(CallDev cd)
         const unsigned long long epu = uniform_u64(s_ep);
         const EnvDev env = epu ? load_descriptor<EnvDev>(epu) : EnvDev{};
         const int C = wave_uniform(s_chunk);
+        // prioritised MV: robots outside the focus set only take part in pairs
+        // with a robot in it
+        const unsigned focus = (unsigned)wave_uniform((int)s_focus);
         const int S = tm.S;
         const int F = tm.F;
         const int G = tm.G;
         const int n = tm.n_robots;
+        const unsigned all_robots = n >= 32 ? 0xFFFFFFFFu : (1u << n) - 1u;
+        const bool fall = focus == 0u || (focus & all_robots) == all_robots;
         const long long qp0 = path_of(cd, n, q);
         // LDS of this tile, TS floats per timestep c: five rows of GSp floats over the
         // sphere slots (16 per group, unused slots padded) -- x, y, z relative to the
@@ -982,12 +991,14 @@ __global__ __launch_bounds__(kWG, kWGsPerCU) void k_validate(CallDev cd)
             if (exhaustive) {
                 for (; task + kWavesPerWG < ntask; task += 2 * kWavesPerWG) {
                     const int tk[2] = { task, task + kWavesPerWG };
-                    env_tasks<2>(cd, tm, env, sp, tk, nch, ro_max, eps, exhaustive, q, s_t, &s_hit, c_env, lane);
+                    env_tasks<2>(cd, tm, env, sp, tk, nch, ro_max, eps, exhaustive, q, focus, fall, s_t, &s_hit, c_env,
+                             lane);
                 }
             }
             for (; task < ntask && !(!exhaustive && flag_read(&s_hit)); task += kWavesPerWG) {
                 const int tk[1] = { task };
-                env_tasks<1>(cd, tm, env, sp, tk, nch, ro_max, eps, exhaustive, q, s_t, &s_hit, c_env, lane);
+                env_tasks<1>(cd, tm, env, sp, tk, nch, ro_max, eps, exhaustive, q, focus, fall, s_t, &s_hit, c_env,
+                             lane);
             }
         }
 
@@ -1019,11 +1030,16 @@ __global__ __launch_bounds__(kWG, kWGsPerCU) void k_validate(CallDev cd)
                 const int* tk = tm.gtask + 8 * k;
                 const int ga = cload(tk + 0);
                 const int ra = cload(tk + 1);
-                const int sb0 = do_self ? cload(tk + 2) : 0;
-                const int sb1 = do_self ? cload(tk + 3) : 0;
-                const int gs = do_rr ? cload(tk + 4) : G;
-                const unsigned long long rr_tests = do_rr ? (unsigned long long)cload(tk + 5) : 0ull;
-                const unsigned long long self_tests = do_self ? (unsigned long long)cload(tk + 6) : 0ull;
+                const bool a_in = fall || ((focus >> ra) & 1u);     // ga's robot in focus
+                const int sb0 = do_self && a_in ? cload(tk + 2) : 0;
+                const int sb1 = do_self && a_in ? cload(tk + 3) : 0;
+                const bool higher_in = ra + 1 < 32 && (focus >> (ra + 1)) != 0u;   // a higher robot in focus
+                const int gs = do_rr && (a_in || higher_in) ? cload(tk + 4) : G;
+                const unsigned long long rr_tests = do_rr && a_in ? (unsigned long long)cload(tk + 5) : 0ull;
+                const unsigned long long self_tests = do_self && a_in ? (unsigned long long)cload(tk + 6) : 0ull;
+                // spheres of group ga, for the test counts of a robot outside the focus set
+                const int ga_n = a_in ? 0 : cload(reinterpret_cast<const int*>(tm.g_range) + 2 * ga + 1) -
+                                            cload(reinterpret_cast<const int*>(tm.g_range) + 2 * ga);
                 if (sb0 == sb1 && gs >= G) continue;
                 for (int c = 0; c < nv; ++c) {
                     const int t = s_t[c];
@@ -1071,10 +1087,17 @@ __global__ __launch_bounds__(kWG, kWGsPerCU) void k_validate(CallDev cd)
                     // robot-robot blocks against the higher robots
                     if (gs < G && !(found && !exhaustive)) {
                         const floatx4 acc = { cw.x, cw.y, cw.z, cw.w };
-                        const int rb_end = KIND == 0 ? ra + 2 : n;   // MV: all higher robots in one sweep
+                        // MV: all higher robots in one sweep, unless ga's robot is outside the
+                        // focus set; then robot by robot, over those in it
+                        const bool sweep = KIND == 0 && a_in;
+                        const int rb_end = sweep ? ra + 2 : n;
                         for (int rb = ra + 1; rb < rb_end; ++rb) {
-                            const int g0 = KIND == 0 ? gs : cload(tm.r_group_off + rb);
-                            const int g1 = KIND == 0 ? G : cload(tm.r_group_off + rb + 1);
+                            if (!a_in && !((focus >> rb) & 1u)) continue;
+                            const int g0 = sweep ? gs : cload(tm.r_group_off + rb);
+                            const int g1 = sweep ? G : cload(tm.r_group_off + rb + 1);
+                            if (!a_in)
+                                c_rr += (unsigned long long)ga_n *
+                                        (unsigned)(cload(tm.r_sphere_off + rb + 1) - cload(tm.r_sphere_off + rb));
                             const unsigned key = KIND == 0 ? 0u : (unsigned)t * (unsigned)tm.P + pair_index(ra, rb, n);
                             if (KIND == 1 && !exhaustive && key >= flag_read(&s_key)) break;
                             float best = 3.0e38f;
@@ -1111,8 +1134,8 @@ __global__ __launch_bounds__(kWG, kWGsPerCU) void k_validate(CallDev cd)
                                     if (KIND == 0) s_hit = 1;
                                     else atomicMin(&s_key, key);
                                 }
-                                // FFC: higher robots give larger keys
-                                if (KIND == 1 && !exhaustive) break;
+                                // FFC: higher robots give larger keys; MV: one hit decides
+                                if (!exhaustive) break;
                             }
                         }
                     }

@@ -108,6 +108,8 @@ struct CallPlan {
     const EnvDev* env0;                // null: no obstacles
     const EnvDev* const* q_env;        // device array, one per query, or null
     const long long* q_pathoff;        // device array: first path of each query, or null
+    uint32_t focus;                    // robots validated (bit r), 0 = all
+    const unsigned* q_focus;           // device array: focus of each query, or null
     long long max_T;                   // bound on every query's horizon
     int min_chunk;                     // smallest timesteps-per-tile among the queries' teams
     size_t lds;                        // dynamic LDS: max over the queries' teams

@@ -35,6 +35,7 @@ struct Req {
     int kind = 0, team = 0, env = -1;
     ServeRefs refs{};
     uint32_t flags = 0;
+    uint32_t focus = 0;                 // MV: robots validated, 0 = all
     int n_queries = 0, n_robots = 0, dof_stride = 0;
     long long max_T = 1;
     std::vector<long long> wp_begin;   // relative to this request's waypoints
@@ -47,7 +48,7 @@ struct Req {
     std::string msg;
     size_t bytes() const
     {
-        return wp_begin.size() * 8 + wp_t.size() * 4 + wp_q.size() * 8 + (size_t)n_queries * (7 * 4 + 12 + 24);
+        return wp_begin.size() * 8 + wp_t.size() * 4 + wp_q.size() * 8 + (size_t)n_queries * (7 * 4 + 12 + 28);
     }
 };
 
@@ -277,14 +278,15 @@ struct ServeLoop::Impl {
             min_chunk = std::min(min_chunk, r->refs.chunk);
             lds = std::max(lds, r->refs.lds);
         }
-        // one pinned block: wp_begin | wp_t | wp_q | q_team | q_env | q_pathoff
+        // one pinned block: wp_begin | wp_t | wp_q | q_team | q_env | q_pathoff | q_focus
         auto align = [](size_t v) { return (v + 255) & ~size_t(255); };
         const size_t nb = (size_t)(n_paths + 1) * sizeof(long long);
         const size_t nt = (size_t)n_wp * sizeof(int);
         const size_t nqb = (size_t)n_wp * stride * sizeof(double);
         const size_t o_t = align(nb), o_q = align(o_t + nt), o_team = align(o_q + nqb);
         const size_t o_env = align(o_team + (size_t)nq * 8), o_po = align(o_env + (size_t)nq * 8);
-        const size_t total = o_po + (size_t)nq * 8;
+        const size_t o_fo = align(o_po + (size_t)nq * 8);
+        const size_t total = o_fo + (size_t)nq * 4;
         const size_t nout = s.kind == 0 ? (size_t)nq : (size_t)nq * 12;
         s.h_in.ensure(total);
         s.h_out.ensure(nout + 64);
@@ -295,6 +297,7 @@ struct ServeLoop::Impl {
         const TeamDev** hteam = (const TeamDev**)(h + o_team);
         const EnvDev** henv = (const EnvDev**)(h + o_env);
         long long* hpo = (long long*)(h + o_po);
+        unsigned* hfo = (unsigned*)(h + o_fo);
         long long wbase = 0, pbase = 0;
         int qi = 0;
         for (auto& r : s.batch) {
@@ -304,6 +307,7 @@ struct ServeLoop::Impl {
                 hteam[qi] = r->refs.team;
                 henv[qi] = r->refs.env;
                 hpo[qi] = pbase + (long long)k * r->n_robots;
+                hfo[qi] = r->focus;
             }
             std::memcpy(ht + wbase, r->wp_t.data(), r->wp_t.size() * sizeof(int));
             std::memcpy(hq + wbase * stride, r->wp_q.data(), r->wp_q.size() * sizeof(double));
@@ -325,6 +329,7 @@ struct ServeLoop::Impl {
         pl.env0 = nullptr;
         pl.q_env = (const EnvDev* const*)(d + o_env);
         pl.q_pathoff = (const long long*)(d + o_po);
+        pl.q_focus = (const unsigned*)(d + o_fo);
         pl.max_T = max_T;
         pl.min_chunk = min_chunk;
         pl.lds = lds;
@@ -406,6 +411,7 @@ mrv_status ServeLoop::submit(const mrv_request& req, const ServeRefs& refs, uint
     r->env = req.kind == 0 ? req.env : -1;
     r->refs = refs;
     r->flags = req.flags;
+    r->focus = req.kind == 0 ? req.focus : 0u;
     r->n_queries = req.paths.n_queries;
     r->n_robots = refs.n_robots;
     const int n_robots = refs.n_robots;

@@ -27,7 +27,7 @@ EXPORTS = ["mrv_create", "mrv_destroy", "mrv_last_error", "mrv_load_team", "mrv_
            "mrv_mv", "mrv_ffc", "mrv_mv_device", "mrv_ffc_device", "mrv_sync", "mrv_motion_steps",
            "mrv_set_tiling", "mrv_get_tiling", "mrv_last_stats", "mrv_submit", "mrv_poll", "mrv_wait",
            "mrv_cancel", "mrv_autotune", "mrv_graph_create", "mrv_graph_launch", "mrv_graph_destroy",
-           "mrv_spheres"]
+           "mrv_spheres", "mrv_mv_focus", "mrv_mv_focus_device"]
 
 
 class MrvError(RuntimeError):
@@ -80,7 +80,7 @@ class Stats(C.Structure):
 
 class Request(C.Structure):
     _fields_ = [("kind", C.c_int32), ("team", C.c_int32), ("env", C.c_int32), ("flags", C.c_uint32),
-                ("paths", PathsDesc)]
+                ("paths", PathsDesc), ("focus", C.c_uint32)]
 
 
 _lib = None
@@ -105,6 +105,8 @@ def lib():
                 "mrv_mv": [P, I32, I32, C.POINTER(PathsDesc), U32, P],
                 "mrv_ffc": [P, I32, C.POINTER(PathsDesc), U32, P],
                 "mrv_mv_device": [P, I32, I32, C.POINTER(PathsDesc), U32, P],
+                "mrv_mv_focus": [P, I32, I32, C.POINTER(PathsDesc), U32, U32, P],
+                "mrv_mv_focus_device": [P, I32, I32, C.POINTER(PathsDesc), U32, U32, P],
                 "mrv_ffc_device": [P, I32, C.POINTER(PathsDesc), U32, P],
                 "mrv_sync": [P],
                 "mrv_set_tiling": [P, I32, I32, U32, C.POINTER(Tiling)],
@@ -245,10 +247,14 @@ class Context:
         check(lib().mrv_unload(self.h, handle))
 
     # -- host-array calls
-    def mv(self, team: int, env: int, paths, flags: int = CHECK_ENV) -> np.ndarray:
+    def mv(self, team: int, env: int, paths, flags: int = CHECK_ENV, focus: int = 0) -> np.ndarray:
+        """focus != 0: prioritised MV over the robots whose bits are set (mrv_mv_focus)."""
         hp = paths if isinstance(paths, HostPaths) else HostPaths(paths)
         out = np.zeros(max(hp.n_queries, 1), np.uint8)
-        check(lib().mrv_mv(self.h, team, env, C.byref(hp.desc), flags, out.ctypes.data))
+        if focus:
+            check(lib().mrv_mv_focus(self.h, team, env, C.byref(hp.desc), flags, focus, out.ctypes.data))
+        else:
+            check(lib().mrv_mv(self.h, team, env, C.byref(hp.desc), flags, out.ctypes.data))
         return out[:hp.n_queries]
 
     def ffc(self, team: int, paths, flags: int = 0) -> np.ndarray:
@@ -258,8 +264,11 @@ class Context:
         return out[:hp.n_queries]
 
     # -- device-array calls (async on the context stream)
-    def mv_device(self, team: int, env: int, dpaths: DevicePaths, flags: int, out_ptr: int):
-        check(lib().mrv_mv_device(self.h, team, env, C.byref(dpaths.desc), flags, out_ptr))
+    def mv_device(self, team: int, env: int, dpaths: DevicePaths, flags: int, out_ptr: int, focus: int = 0):
+        if focus:
+            check(lib().mrv_mv_focus_device(self.h, team, env, C.byref(dpaths.desc), flags, focus, out_ptr))
+        else:
+            check(lib().mrv_mv_device(self.h, team, env, C.byref(dpaths.desc), flags, out_ptr))
 
     def ffc_device(self, team: int, dpaths: DevicePaths, flags: int, out_ptr: int):
         check(lib().mrv_ffc_device(self.h, team, C.byref(dpaths.desc), flags, out_ptr))
@@ -313,9 +322,9 @@ class Context:
         check(lib().mrv_graph_destroy(self.h, g))
 
     # -- serving
-    def submit(self, kind: int, team: int, env: int, paths, flags: int) -> int:
+    def submit(self, kind: int, team: int, env: int, paths, flags: int, focus: int = 0) -> int:
         hp = paths if isinstance(paths, HostPaths) else HostPaths(paths)
-        req = Request(kind, team, env, flags, hp.desc)
+        req = Request(kind, team, env, flags, hp.desc, focus)
         t = C.c_uint64()
         check(lib().mrv_submit(self.h, C.byref(req), C.byref(t)))
         return t.value

@@ -1,0 +1,118 @@
+"""GPU parity for prioritised MV (the PP-ST-RRT use of MV, §III-C): only robots in
+the focus set get obstacle and self tests, and only robot pairs with a robot in
+the set are tested.  Booleans must equal the FP64 oracle's for every focus set,
+flag set and call form (host arrays, device arrays, served requests)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2604_23960_amd import mrv
+from paper_2604_23960_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FLAG_SETS = [
+    mrv.CHECK_ENV,
+    mrv.CHECK_ENV | mrv.EXHAUSTIVE,
+    mrv.CHECK_ENV | mrv.HIERARCHICAL,
+    mrv.CHECK_ENV | mrv.ORDER_LINEAR,
+    0,
+    mrv.EXHAUSTIVE,
+]
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = mrv.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def arms():
+    w = W.arms_workload(320)
+    return w, oracle.Team(w.team), oracle.Env(w.env), oracle.Paths(w.paths)
+
+
+@pytest.mark.parametrize("focus", [0b0001, 0b0100, 0b0110, 0b1001, 0b1111])
+def test_arms_focus_matches_oracle(ctx, arms, focus):
+    w, ot, oe, op = arms
+    team, env = ctx.load_team(w.team), ctx.load_env(w.env)
+    for flags in FLAG_SETS:
+        say("arms focus", bin(focus), "flags", flags)
+        ref = oracle.mv(ot, oe, op, check_env=bool(flags & mrv.CHECK_ENV), focus=focus)
+        got = ctx.mv(team, env, w.paths, flags, focus=focus)
+        assert np.array_equal(got, ref), (bin(focus), flags, np.flatnonzero(got != ref)[:10])
+    ctx.unload(team)
+    ctx.unload(env)
+
+
+def test_single_robot_sets_decompose_full_mv(ctx, arms):
+    w, ot, oe, op = arms
+    team, env = ctx.load_team(w.team), ctx.load_env(w.env)
+    say("decomposition")
+    full = ctx.mv(team, env, w.paths, mrv.CHECK_ENV)
+    single = [ctx.mv(team, env, w.paths, mrv.CHECK_ENV, focus=1 << r) for r in range(4)]
+    assert np.array_equal(full, np.logical_and.reduce(single).astype(np.uint8))
+    assert np.array_equal(full, oracle.mv(ot, oe, op, check_env=True))
+    assert any(not np.array_equal(s, full) for s in single)     # focus does change answers here
+    ctx.unload(team)
+    ctx.unload(env)
+
+
+def test_hetero_team_focus(ctx):
+    """Four arms and four SE(2) rectangles with timed paths: focus on rectangles,
+    on an arm and a rectangle, and on all but one robot."""
+    w = W.ffc_workload(96)
+    env = W.cube_env(1)
+    ot, oe, op = oracle.Team(w.team), oracle.Env(env), oracle.Paths(w.paths)
+    team, eh = ctx.load_team(w.team), ctx.load_env(env)
+    for focus in (0b11110000, 0b00010001, 0b01111111):
+        for flags in (mrv.CHECK_ENV, mrv.CHECK_ENV | mrv.EXHAUSTIVE, 0):
+            say("hetero focus", bin(focus), "flags", flags)
+            ref = oracle.mv(ot, oe, op, check_env=bool(flags & mrv.CHECK_ENV), focus=focus)
+            assert np.array_equal(ctx.mv(team, eh, w.paths, flags, focus=focus), ref)
+    ctx.unload(team)
+    ctx.unload(eh)
+
+
+def test_disks_focus_and_device_form(ctx):
+    w = W.disks_workload(512)
+    ot, oe, op = oracle.Team(w.team), oracle.Env(w.env), oracle.Paths(w.paths)
+    team, env = ctx.load_team(w.team), ctx.load_env(w.env)
+    dp = mrv.DevicePaths(w.paths)
+    out = torch.zeros(w.paths.n_queries, dtype=torch.uint8, device="cuda")
+    n = len(w.team)
+    for focus in (1, 1 << (n - 1)):
+        for flags in (mrv.CHECK_ENV, mrv.CHECK_ENV | mrv.EXHAUSTIVE):
+            say("disks focus", bin(focus), "flags", flags)
+            ref = oracle.mv(ot, oe, op, check_env=True, focus=focus)
+            assert np.array_equal(ctx.mv(team, env, w.paths, flags, focus=focus), ref)
+            ctx.mv_device(team, env, dp, flags, out.data_ptr(), focus=focus)
+            ctx.sync()
+            assert np.array_equal(out.cpu().numpy(), ref)
+    ctx.unload(team)
+    ctx.unload(env)
+
+
+def test_served_requests_with_mixed_focus(ctx, arms):
+    """Requests with different focus sets share served batches; each answer must
+    be its own focus set's."""
+    w, ot, oe, op = arms
+    team, env = ctx.load_team(w.team), ctx.load_env(w.env)
+    cases = []
+    for k, focus in enumerate([0, 0b0001, 0b0010, 0b1100, 0b0101, 0b1111, 0b1000, 0]):
+        sub = w.paths.subset(np.arange(k * 40, k * 40 + 40))
+        say("served focus", bin(focus))
+        cases.append((focus, sub, ctx.submit(0, team, env, sub, mrv.CHECK_ENV, focus)))
+    for focus, sub, t in cases:
+        got = ctx.poll(t, 0, sub.n_queries, timeout_ms=-1)
+        ref = oracle.mv(ot, oe, oracle.Paths(sub), check_env=True, focus=focus)
+        assert np.array_equal(got, ref), bin(focus)
+    ctx.unload(team)
+    ctx.unload(env)
