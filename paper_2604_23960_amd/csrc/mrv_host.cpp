@@ -656,7 +656,7 @@ void run_plan(mrv_ctx ctx, Scratch& sc, const CallPlan& pl, void* out_dev, hipSt
     cd.valid_out = kind == 0 ? (unsigned char*)out_dev : nullptr;
     cd.conflict_out = kind == 1 ? (int*)out_dev : nullptr;
 
-    const int per_cu = std::max(1, validate_blocks_per_cu(kind, pl.lds));
+    const int per_cu = std::max(1, validate_blocks_per_cu(has_focus(cd) ? 2 : kind, pl.lds));
     const int want = pl.wg_per_cu > 0 ? std::min(pl.wg_per_cu, per_cu) : per_cu;
     const int grid = std::max(1, ctx->n_cu * want);
 
@@ -675,7 +675,9 @@ CallPlan single_plan(const TeamHost& tm, const EnvHost* env, int kind, uint32_t 
     CallPlan pl{};
     pl.kind = kind;
     pl.flags = flags;
-    pl.focus = focus;
+    // a focus set holding every robot is plain MV (and runs the plain MV kernel)
+    const uint32_t all = tm.dev.n_robots >= 32 ? 0xFFFFFFFFu : (1u << tm.dev.n_robots) - 1u;
+    pl.focus = kind == 0 && (focus & all) != all ? focus : 0u;
     pl.dp = dp;
     pl.team0 = tm.d_dev;
     pl.env0 = env ? env->d_dev : nullptr;

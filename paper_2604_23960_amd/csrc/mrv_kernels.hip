@@ -787,6 +787,8 @@ __device__ __forceinline__ void env_tasks(const CallDev& cd, const TeamDev& tm, 
 template <int KIND>
 __global__ __launch_bounds__(kWG, kWGsPerCU) void k_validate(CallDev cd)
 {
+    constexpr bool kMV = KIND != 1;          // MV, with or without a focus set
+    constexpr bool kFocus = KIND == 2;       // MV with a focus set (prioritised MV)
     extern __shared__ float4 dyn[];
 
     __shared__ int s_t[kMaxChunk];
@@ -804,7 +806,7 @@ __global__ __launch_bounds__(kWG, kWGsPerCU) void k_validate(CallDev cd)
     const int wave = wave_uniform(tid >> 6);
     const unsigned flags = cd.flags;
     const bool exhaustive = (flags & MRV_EXHAUSTIVE) != 0;
-    const bool check_env = KIND == 0 && (flags & MRV_CHECK_ENV) != 0;
+    const bool check_env = kMV && (flags & MRV_CHECK_ENV) != 0;
     const bool hier = check_env && (flags & MRV_HIERARCHICAL) != 0;
     const float eps = cd.eps32;
 
@@ -827,7 +829,7 @@ __global__ __launch_bounds__(kWG, kWGsPerCU) void k_validate(CallDev cd)
         if (tid == 0) {
             const long long g = (long long)atomicAdd(&w64[1], 1ull);
             int q = -1, nv = 0, phase = 0, C = 1;
-            unsigned known = KIND == 1 ? 0xFFFFFFFFu : 0u, focus = 0u;
+            unsigned known = !kMV ? 0xFFFFFFFFu : 0u, focus = 0u;
             if (g < gtotal) {
                 long long gg = g;
                 if (hier) {
@@ -855,7 +857,7 @@ __global__ __launch_bounds__(kWG, kWGsPerCU) void k_validate(CallDev cd)
                 s_kcur = lo;
                 const int k = (int)lo;
                 q = cd.sorted_q[gg - off[lo]];
-                focus = cd.q_focus ? cd.q_focus[q] : cd.focus0;
+                if (kFocus) focus = cd.q_focus ? cd.q_focus[q] : cd.focus0;
                 const TeamDev* tq = team_of(cd, q);
                 const EnvDev* eq = env_of(cd, q);
                 s_tp = (unsigned long long)tq;
@@ -864,7 +866,7 @@ __global__ __launch_bounds__(kWG, kWGsPerCU) void k_validate(CallDev cd)
                 const int T = cd.T[q];
                 const int nt = cd.nt[q];
                 int base, stride;
-                if (KIND == 1 || (flags & MRV_ORDER_LINEAR)) {
+                if (!kMV || (flags & MRV_ORDER_LINEAR)) {
                     base = k * C; stride = 1;
                 } else {
                     base = (flags & MRV_ORDER_RAKE) ? k : (int)(((long long)k * cd.gstep[q]) % nt);
@@ -879,14 +881,14 @@ __global__ __launch_bounds__(kWG, kWGsPerCU) void k_validate(CallDev cd)
                 known = load_word(cd.word + q);
                 bool skip = false;
                 if (!exhaustive) {
-                    if (KIND == 0) skip = (known != 0u);
+                    if (kMV) skip = (known != 0u);
                     else skip = (known != 0xFFFFFFFFu) && (known < (unsigned)base * (unsigned)tq->P);
                 }
                 if (skip) { nv = 0; ++s_nskip; }
                 else { ++s_nrun; s_nstates += (unsigned long long)nv * tq->n_robots; }
             }
             s_q = q; s_phase = phase; s_nv = nv; s_chunk = C; s_focus = focus;
-            s_hit = KIND == 0 && known != 0u; s_key = KIND == 1 ? known : 0xFFFFFFFFu; s_rho2 = 0u;
+            s_hit = kMV && known != 0u; s_key = !kMV ? known : 0xFFFFFFFFu; s_rho2 = 0u;
         }
         __syncthreads();
         const int q = s_q;
@@ -903,13 +905,13 @@ __global__ __launch_bounds__(kWG, kWGsPerCU) void k_validate(CallDev cd)
         const int C = wave_uniform(s_chunk);
         // prioritised MV: robots outside the focus set only take part in pairs
         // with a robot in it
-        const unsigned focus = (unsigned)wave_uniform((int)s_focus);
+        const unsigned focus = kFocus ? (unsigned)wave_uniform((int)s_focus) : 0u;
         const int S = tm.S;
         const int F = tm.F;
         const int G = tm.G;
         const int n = tm.n_robots;
         const unsigned all_robots = n >= 32 ? 0xFFFFFFFFu : (1u << n) - 1u;
-        const bool fall = focus == 0u || (focus & all_robots) == all_robots;
+        const bool fall = !kFocus || focus == 0u || (focus & all_robots) == all_robots;
         const long long qp0 = path_of(cd, n, q);
         // LDS of this tile, TS floats per timestep c: five rows of GSp floats over the
         // sphere slots (16 per group, unused slots padded) -- x, y, z relative to the
@@ -1012,7 +1014,7 @@ __global__ __launch_bounds__(kWG, kWGsPerCU) void k_validate(CallDev cd)
         // the higher robots.  Lanes whose minimum lies within the bound's
         // uncertainty revisit their pairs directly.
         const bool do_self = do_env && tm.n_sblocks > 0;
-        if ((do_rr || do_self) && !(KIND == 0 && !exhaustive && flag_read(&s_hit))) {
+        if ((do_rr || do_self) && !(kMV && !exhaustive && flag_read(&s_hit))) {
             const float rho2 = __uint_as_float(s_rho2);
             const float rm = tm.r_max;
             const float u = 5.9604645e-8f;
@@ -1026,7 +1028,7 @@ __global__ __launch_bounds__(kWG, kWGsPerCU) void k_validate(CallDev cd)
             const int i16 = lane & 15;
             const int q4 = lane >> 4;
             for (int k = wave; k < G; k += kWavesPerWG) {
-                if (KIND == 0 && !exhaustive && flag_read(&s_hit)) break;
+                if (kMV && !exhaustive && flag_read(&s_hit)) break;
                 const int* tk = tm.gtask + 8 * k;
                 const int ga = cload(tk + 0);
                 const int ra = cload(tk + 1);
@@ -1043,7 +1045,7 @@ __global__ __launch_bounds__(kWG, kWGsPerCU) void k_validate(CallDev cd)
                 if (sb0 == sb1 && gs >= G) continue;
                 for (int c = 0; c < nv; ++c) {
                     const int t = s_t[c];
-                    if (KIND == 0) {
+                    if (kMV) {
                         if (!exhaustive && flag_read(&s_hit)) break;
                     } else if (!exhaustive) {
                         const unsigned known = flag_read(&s_key);
@@ -1089,7 +1091,7 @@ __global__ __launch_bounds__(kWG, kWGsPerCU) void k_validate(CallDev cd)
                         const floatx4 acc = { cw.x, cw.y, cw.z, cw.w };
                         // MV: all higher robots in one sweep, unless ga's robot is outside the
                         // focus set; then robot by robot, over those in it
-                        const bool sweep = KIND == 0 && a_in;
+                        const bool sweep = kMV && a_in;
                         const int rb_end = sweep ? ra + 2 : n;
                         for (int rb = ra + 1; rb < rb_end; ++rb) {
                             if (!a_in && !((focus >> rb) & 1u)) continue;
@@ -1098,8 +1100,8 @@ __global__ __launch_bounds__(kWG, kWGsPerCU) void k_validate(CallDev cd)
                             if (!a_in)
                                 c_rr += (unsigned long long)ga_n *
                                         (unsigned)(cload(tm.r_sphere_off + rb + 1) - cload(tm.r_sphere_off + rb));
-                            const unsigned key = KIND == 0 ? 0u : (unsigned)t * (unsigned)tm.P + pair_index(ra, rb, n);
-                            if (KIND == 1 && !exhaustive && key >= flag_read(&s_key)) break;
+                            const unsigned key = kMV ? 0u : (unsigned)t * (unsigned)tm.P + pair_index(ra, rb, n);
+                            if (!kMV && !exhaustive && key >= flag_read(&s_key)) break;
                             float best = 3.0e38f;
                             int g = g0;
                             for (; g + 4 <= g1; g += 4) {
@@ -1126,28 +1128,29 @@ __global__ __launch_bounds__(kWG, kWGsPerCU) void k_validate(CallDev cd)
                             if (!__ballot(hit) && __ballot(unsure) && unsure) {
                                 for (int gg = g0; gg < g1 && !hit; ++gg)
                                     hit = direct_block(cd, tm, base, GSp, ga, gg, lane, nullptr, eps, q, t, RK_RR, key,
-                                                       &s_hit, &s_key, KIND == 0);
+                                                       &s_hit, &s_key, kMV);
                             }
                             if (__ballot(hit)) {
                                 found = true;
                                 if (lane == 0) {
-                                    if (KIND == 0) s_hit = 1;
+                                    if (kMV) s_hit = 1;
                                     else atomicMin(&s_key, key);
                                 }
-                                // FFC: higher robots give larger keys; MV: one hit decides
-                                if (!exhaustive) break;
+                                // FFC: higher robots give larger keys; MV robot by robot: one
+                                // hit decides
+                                if (!exhaustive && (!kMV || !sweep)) break;
                             }
                         }
                     }
                     // FFC: this group's later timesteps give larger keys
-                    if (KIND == 1 && found && !exhaustive) break;
+                    if (!kMV && found && !exhaustive) break;
                 }
             }
         }
 
         __syncthreads();
         if (tid == 0) {
-            if (KIND == 0) {
+            if (kMV) {
                 if (s_hit) atomicOr(cd.word + q, 1u);
             } else {
                 if (s_key != 0xFFFFFFFFu) atomicMin(cd.word + q, s_key);
@@ -1244,13 +1247,18 @@ hipError_t launch_validate(const CallDev& cd, int grid, hipStream_t stream)
         if (e == hipSuccess)
             e = hipFuncSetAttribute((const void*)k_validate<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     kLdsBudget - 1024);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)k_validate<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    kLdsBudget - 1024);
         return e;
     }();
     if (lds_opt != hipSuccess && cd.lds_bytes > 64 * 1024) return lds_opt;
-    if (cd.kind == 0)
-        hipLaunchKernelGGL(k_validate<0>, dim3(grid), dim3(kWG), (size_t)cd.lds_bytes, stream, cd);
-    else
+    if (cd.kind == 1)
         hipLaunchKernelGGL(k_validate<1>, dim3(grid), dim3(kWG), (size_t)cd.lds_bytes, stream, cd);
+    else if (has_focus(cd))
+        hipLaunchKernelGGL(k_validate<2>, dim3(grid), dim3(kWG), (size_t)cd.lds_bytes, stream, cd);
+    else
+        hipLaunchKernelGGL(k_validate<0>, dim3(grid), dim3(kWG), (size_t)cd.lds_bytes, stream, cd);
     return hipGetLastError();
 }
 
@@ -1275,9 +1283,9 @@ hipError_t launch_spheres(const CallDev& cd, const int* st_q, const int* st_t, i
 int validate_blocks_per_cu(int kind, size_t lds_bytes)
 {
     int nb = 0;
-    hipError_t e = kind == 0
-        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_validate<0>, kWG, lds_bytes)
-        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_validate<1>, kWG, lds_bytes);
+    hipError_t e = kind == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_validate<1>, kWG, lds_bytes)
+                 : kind == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_validate<2>, kWG, lds_bytes)
+                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_validate<0>, kWG, lds_bytes);
     if (e != hipSuccess || nb < 1) nb = 1;
     return nb;
 }

@@ -300,6 +300,7 @@ struct ServeLoop::Impl {
         unsigned* hfo = (unsigned*)(h + o_fo);
         long long wbase = 0, pbase = 0;
         int qi = 0;
+        bool any_focus = false;
         for (auto& r : s.batch) {
             const size_t np = (size_t)r->n_queries * r->n_robots;
             for (size_t i = 0; i < np; ++i) hb[pbase + i] = r->wp_begin[i] + wbase;
@@ -308,6 +309,7 @@ struct ServeLoop::Impl {
                 henv[qi] = r->refs.env;
                 hpo[qi] = pbase + (long long)k * r->n_robots;
                 hfo[qi] = r->focus;
+                any_focus = any_focus || r->focus != 0u;
             }
             std::memcpy(ht + wbase, r->wp_t.data(), r->wp_t.size() * sizeof(int));
             std::memcpy(hq + wbase * stride, r->wp_q.data(), r->wp_q.size() * sizeof(double));
@@ -329,7 +331,7 @@ struct ServeLoop::Impl {
         pl.env0 = nullptr;
         pl.q_env = (const EnvDev* const*)(d + o_env);
         pl.q_pathoff = (const long long*)(d + o_po);
-        pl.q_focus = (const unsigned*)(d + o_fo);
+        pl.q_focus = any_focus ? (const unsigned*)(d + o_fo) : nullptr;   // plain MV kernel otherwise
         pl.max_T = max_T;
         pl.min_chunk = min_chunk;
         pl.lds = lds;
@@ -411,7 +413,10 @@ mrv_status ServeLoop::submit(const mrv_request& req, const ServeRefs& refs, uint
     r->env = req.kind == 0 ? req.env : -1;
     r->refs = refs;
     r->flags = req.flags;
-    r->focus = req.kind == 0 ? req.focus : 0u;
+    {
+        const uint32_t all = refs.n_robots >= 32 ? 0xFFFFFFFFu : (1u << refs.n_robots) - 1u;
+        r->focus = req.kind == 0 && (req.focus & all) != all ? req.focus : 0u;   // every robot: plain MV
+    }
     r->n_queries = req.paths.n_queries;
     r->n_robots = refs.n_robots;
     const int n_robots = refs.n_robots;
