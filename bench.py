@@ -72,9 +72,9 @@ def per_timestep_flop(team, env, check_env=True):
     return rr + fk + envf
 
 
-def run_device(ctx, team, env, dp, kind, flags, out, steps, warmup):
+def run_device(ctx, team, env, dp, kind, flags, out, steps, warmup, focus=0):
     import torch
-    call = (lambda: ctx.mv_device(team, env, dp, flags, out.data_ptr())) if kind == 0 else \
+    call = (lambda: ctx.mv_device(team, env, dp, flags, out.data_ptr(), focus)) if kind == 0 else \
         (lambda: ctx.ffc_device(team, dp, flags, out.data_ptr()))
     for _ in range(warmup):
         call()
@@ -377,6 +377,13 @@ def main():
         extra["mv_early_exit"] = dict(covered_states_per_s=st2["states_covered"] * 5 / wall2,
                                       evaluated_states_per_s=st2["states_evaluated"] * 5 / wall2,
                                       ms_per_call=wall2 / 5 * 1e3, effort=st2["states_evaluated"] / st2["states_covered"])
+        log("timing prioritised MV (focus on arm 0)")
+        wall4, kms4, st4 = run_device(ctx, team, env, dp, 0, mrv.CHECK_ENV | mrv.EXHAUSTIVE, out, 3, 1, focus=1)
+        wall5, _, st5 = run_device(ctx, team, env, dp, 0, mrv.CHECK_ENV, out, 5, 1, focus=1)
+        extra["mv_focus_arm0"] = dict(
+            exhaustive=dict(kernel_ms=float(np.mean(kms4)), states_per_s=st4["states_evaluated"] * 3 / wall4,
+                            rr_tests=st4["rr_tests"], env_tests=st4["env_tests"], self_tests=st4["self_tests"]),
+            early_exit=dict(ms_per_call=wall5 / 5 * 1e3, covered_states_per_s=st5["states_covered"] * 5 / wall5))
         log("timing FFC on the arm + rectangle workload")
         wf = W.ffc_workload(16384)
         tf = ctx.load_team(wf.team)
