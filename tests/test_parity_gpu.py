@@ -197,6 +197,49 @@ def test_edge_cases(ctx):
     assert np.array_equal(ctx.ffc(team, pu), oracle.ffc(ot, oracle.Paths(pu)))
 
 
+def test_maximum_length_queries(ctx):
+    """Motions of the maximum length (last waypoint time MRV_MAX_T - 1) on two
+    disks of radius 0.05: resting apart (valid); apart until T - 2, then
+    overlapping at T - 1 only (FFC = (T - 1, 0, 1)); a 4,097-waypoint zig-zag
+    that stays clear; and a 3-step query between them.  One step longer is
+    rejected."""
+    import torch
+    say("maximum-length queries")
+    T1 = mrv.MAX_T - 1
+    team = [W.disk_robot(0.05, "d0"), W.disk_robot(0.05, "d1")]
+    rest0 = (np.array([0, T1]), np.array([[0.2, 0.2], [0.2, 0.2]]))
+    zz_t = np.linspace(0, T1, 4097).astype(np.int64)
+    zz_q = np.column_stack([np.where(np.arange(4097) % 2 == 0, 0.6, 0.9), np.linspace(0.6, 0.9, 4097)])
+    rows = [
+        [rest0, (np.array([0, T1]), np.array([[0.8, 0.8], [0.8, 0.8]]))],
+        [rest0, (np.array([0, T1 - 1, T1]), np.array([[0.8, 0.8], [0.8, 0.8], [0.25, 0.2]]))],
+        [rest0, (zz_t, zz_q)],
+        [(np.array([0, 2]), np.array([[0.2, 0.2], [0.3, 0.2]])), (np.array([0]), np.array([[0.35, 0.2]]))],
+    ]
+    paths = W.paths_from_lists(rows, 2)
+    ot, op = oracle.Team(team), oracle.Paths(paths)
+    mv_ref, ffc_ref = oracle.mv(ot, None, op, check_env=False), oracle.ffc(ot, op)
+    assert list(mv_ref) == [1, 0, 1, 0]
+    assert tuple(ffc_ref[1]) == (T1, 0, 1) and ffc_ref[0, 0] == -1 and ffc_ref[2, 0] == -1
+    th = ctx.load_team(team)
+    for flags in (0, mrv.EXHAUSTIVE, mrv.ORDER_LINEAR, mrv.ORDER_RAKE):
+        assert np.array_equal(ctx.mv(th, -1, paths, flags), mv_ref), flags
+    assert np.array_equal(ctx.ffc(th, paths), ffc_ref)
+    assert np.array_equal(ctx.ffc(th, paths, mrv.EXHAUSTIVE), ffc_ref)
+    dp = mrv.DevicePaths(paths)
+    o = torch.zeros(4, dtype=torch.uint8, device="cuda")
+    ctx.mv_device(th, -1, dp, 0, o.data_ptr())
+    ctx.sync()
+    assert np.array_equal(o.cpu().numpy(), mv_ref)
+    # one step beyond the limit
+    too_long = W.paths_from_lists([[(np.array([0, mrv.MAX_T]), np.array([[0.2, 0.2], [0.2, 0.2]])),
+                                    (np.array([0]), np.array([[0.8, 0.8]]))]], 2)
+    with pytest.raises(mrv.MrvError) as e:
+        ctx.mv(th, -1, too_long, 0)
+    assert e.value.status == mrv.MRV_E_INVALID
+    ctx.unload(th)
+
+
 def test_invalid_inputs_rejected(ctx):
     say("invalid inputs")
     w = W.arms_workload(8)
