@@ -826,6 +826,11 @@ __global__ __launch_bounds__(kWG, kWGsPerCU) void k_validate(CallDev cd)
     }
 
     for (;;) {
+        // Wave priorities in exhaustive calls: the serial part of a tile (claim, FK,
+        // records; one busy wave per workgroup) issues first, then the pair phase's
+        // MFMA chains, while the obstacle phase's long VALU streams fill the gaps
+        // (early-terminating calls keep one level: their obstacle verdicts end queries).
+        if (exhaustive) __builtin_amdgcn_s_setprio(2);
         if (tid == 0) {
             const long long g = (long long)atomicAdd(&w64[1], 1ull);
             int q = -1, nv = 0, phase = 0, C = 1;
@@ -979,6 +984,7 @@ __global__ __launch_bounds__(kWG, kWGsPerCU) void k_validate(CallDev cd)
         }
         __syncthreads();
 
+        if (exhaustive) __builtin_amdgcn_s_setprio(0);
         // --- robot-obstacle tests (MV with environment checking): one lane per
         // (timestep, slot); obstacle parameters are wave-uniform scalar loads.
         if (do_env) {
@@ -1004,6 +1010,7 @@ __global__ __launch_bounds__(kWG, kWGsPerCU) void k_validate(CallDev cd)
             }
         }
 
+        if (exhaustive) __builtin_amdgcn_s_setprio(1);
         // --- sphere-pair tests as 16 x 16 blocks on the matrix cores.  For slots a
         // (rows, group ga) and b (columns, group gb) at one timestep,
         //   D(a, b) = w_a + w_b - 2 p_a.p_b - 2 r_a r_b = |p_a - p_b|^2 - (r_a + r_b)^2,
