@@ -992,11 +992,16 @@ __global__ __launch_bounds__(kWG, kWGsPerCU) void k_validate(CallDev cd)
             const int ntask = nv * nch;
             float ro_max = 0.f;
             for (int o = 0; o < env.n_sph; ++o) ro_max = fmaxf(ro_max, cloadf(&env.sph32[o].w));
-            // tasks wave, wave + 4, ... of this wave: exhaustive calls take two at a time
-            // through each obstacle; early-terminating calls one at a time, so a hit
-            // stops the wave before its next task
+            // tasks wave, wave + 4, ... of this wave: exhaustive calls take four (then
+            // two) at a time through each obstacle; early-terminating calls one at a
+            // time, so a hit stops the wave before its next task
             int task = wave;
             if (exhaustive) {
+                for (; task + 3 * kWavesPerWG < ntask; task += 4 * kWavesPerWG) {
+                    const int tk[4] = { task, task + kWavesPerWG, task + 2 * kWavesPerWG, task + 3 * kWavesPerWG };
+                    env_tasks<4>(cd, tm, env, sp, tk, nch, ro_max, eps, exhaustive, q, focus, fall, s_t, &s_hit, c_env,
+                                 lane);
+                }
                 for (; task + kWavesPerWG < ntask; task += 2 * kWavesPerWG) {
                     const int tk[2] = { task, task + kWavesPerWG };
                     env_tasks<2>(cd, tm, env, sp, tk, nch, ro_max, eps, exhaustive, q, focus, fall, s_t, &s_hit, c_env,
