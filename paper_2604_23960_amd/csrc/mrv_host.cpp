@@ -656,7 +656,7 @@ void run_plan(mrv_ctx ctx, Scratch& sc, const CallPlan& pl, void* out_dev, hipSt
     cd.valid_out = kind == 0 ? (unsigned char*)out_dev : nullptr;
     cd.conflict_out = kind == 1 ? (int*)out_dev : nullptr;
 
-    const int per_cu = std::max(1, validate_blocks_per_cu(has_focus(cd) ? 2 : kind, pl.lds));
+    const int per_cu = std::max(1, validate_blocks_per_cu(validate_variant(cd), pl.lds));
     const int want = pl.wg_per_cu > 0 ? std::min(pl.wg_per_cu, per_cu) : per_cu;
     const int grid = std::max(1, ctx->n_cu * want);
 

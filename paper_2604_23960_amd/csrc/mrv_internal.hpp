@@ -145,9 +145,16 @@ hipError_t fill_u32(void* p, unsigned v, size_t n, hipStream_t stream);
 hipError_t launch_spheres(const CallDev& cd, const int* st_q, const int* st_t, int n_states, float4* out, int S,
                           int F, hipStream_t stream);
 // Occupancy-derived workgroups per CU for the validation kernel.
-// kind: 0 MV, 1 FFC, 2 MV with a focus set
-int validate_blocks_per_cu(int kind, size_t lds_bytes);
 // Whether an MV call restricts validation to a focus set (runs the focus kernel).
 inline bool has_focus(const CallDev& cd) { return cd.kind == 0 && (cd.focus0 != 0u || cd.q_focus != nullptr); }
+// Validation kernel of a call: 0 early-terminating MV, 1 FFC, 2 MV with a focus set,
+// 3 exhaustive MV.
+inline int validate_variant(const CallDev& cd)
+{
+    if (cd.kind == 1) return 1;
+    if (has_focus(cd)) return 2;
+    return (cd.flags & MRV_EXHAUSTIVE) ? 3 : 0;
+}
+int validate_blocks_per_cu(int variant, size_t lds_bytes);
 
 }  // namespace mrv

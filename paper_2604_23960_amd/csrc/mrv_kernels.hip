@@ -787,8 +787,10 @@ __device__ __forceinline__ void env_tasks(const CallDev& cd, const TeamDev& tm, 
 template <int KIND>
 __global__ __launch_bounds__(kWG, kWGsPerCU) void k_validate(CallDev cd)
 {
-    constexpr bool kMV = KIND != 1;          // MV, with or without a focus set
-    constexpr bool kFocus = KIND == 2;       // MV with a focus set (prioritised MV)
+    // KIND: 0 early-terminating MV, 1 FFC, 2 MV with a focus set (prioritised MV),
+    // 3 exhaustive MV; the exhaustive mode is a compile-time constant for 0 and 3
+    constexpr bool kMV = KIND != 1;
+    constexpr bool kFocus = KIND == 2;
     extern __shared__ float4 dyn[];
 
     __shared__ int s_t[kMaxChunk];
@@ -805,7 +807,7 @@ __global__ __launch_bounds__(kWG, kWGsPerCU) void k_validate(CallDev cd)
     const int lane = tid & 63;
     const int wave = wave_uniform(tid >> 6);
     const unsigned flags = cd.flags;
-    const bool exhaustive = (flags & MRV_EXHAUSTIVE) != 0;
+    const bool exhaustive = KIND == 3 || (KIND != 0 && (flags & MRV_EXHAUSTIVE) != 0);
     const bool check_env = kMV && (flags & MRV_CHECK_ENV) != 0;
     const bool hier = check_env && (flags & MRV_HIERARCHICAL) != 0;
     const float eps = cd.eps32;
@@ -992,15 +994,24 @@ __global__ __launch_bounds__(kWG, kWGsPerCU) void k_validate(CallDev cd)
             const int ntask = nv * nch;
             float ro_max = 0.f;
             for (int o = 0; o < env.n_sph; ++o) ro_max = fmaxf(ro_max, cloadf(&env.sph32[o].w));
-            // tasks wave, wave + 4, ... of this wave: exhaustive calls take four (then
-            // two) at a time through each obstacle; early-terminating calls one at a
-            // time, so a hit stops the wave before its next task
+            // tasks wave, wave + 4, ... of this wave: exhaustive MV takes five (then
+            // four, two) at a time through each obstacle, exhaustive prioritised MV
+            // two; early-terminating calls one at a time, so a hit stops the wave
+            // before its next task
             int task = wave;
             if (exhaustive) {
-                for (; task + 3 * kWavesPerWG < ntask; task += 4 * kWavesPerWG) {
-                    const int tk[4] = { task, task + kWavesPerWG, task + 2 * kWavesPerWG, task + 3 * kWavesPerWG };
-                    env_tasks<4>(cd, tm, env, sp, tk, nch, ro_max, eps, exhaustive, q, focus, fall, s_t, &s_hit, c_env,
-                                 lane);
+                if constexpr (KIND == 3) {      // the focus kernel keeps its registers for the focus logic
+                    for (; task + 4 * kWavesPerWG < ntask; task += 5 * kWavesPerWG) {
+                        const int tk[5] = { task, task + kWavesPerWG, task + 2 * kWavesPerWG, task + 3 * kWavesPerWG,
+                                            task + 4 * kWavesPerWG };
+                        env_tasks<5>(cd, tm, env, sp, tk, nch, ro_max, eps, exhaustive, q, focus, fall, s_t, &s_hit,
+                                     c_env, lane);
+                    }
+                    for (; task + 3 * kWavesPerWG < ntask; task += 4 * kWavesPerWG) {
+                        const int tk[4] = { task, task + kWavesPerWG, task + 2 * kWavesPerWG, task + 3 * kWavesPerWG };
+                        env_tasks<4>(cd, tm, env, sp, tk, nch, ro_max, eps, exhaustive, q, focus, fall, s_t, &s_hit,
+                                     c_env, lane);
+                    }
                 }
                 for (; task + kWavesPerWG < ntask; task += 2 * kWavesPerWG) {
                     const int tk[2] = { task, task + kWavesPerWG };
@@ -1262,15 +1273,18 @@ hipError_t launch_validate(const CallDev& cd, int grid, hipStream_t stream)
         if (e == hipSuccess)
             e = hipFuncSetAttribute((const void*)k_validate<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     kLdsBudget - 1024);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)k_validate<3>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    kLdsBudget - 1024);
         return e;
     }();
     if (lds_opt != hipSuccess && cd.lds_bytes > 64 * 1024) return lds_opt;
-    if (cd.kind == 1)
-        hipLaunchKernelGGL(k_validate<1>, dim3(grid), dim3(kWG), (size_t)cd.lds_bytes, stream, cd);
-    else if (has_focus(cd))
-        hipLaunchKernelGGL(k_validate<2>, dim3(grid), dim3(kWG), (size_t)cd.lds_bytes, stream, cd);
-    else
-        hipLaunchKernelGGL(k_validate<0>, dim3(grid), dim3(kWG), (size_t)cd.lds_bytes, stream, cd);
+    switch (validate_variant(cd)) {
+    case 1: hipLaunchKernelGGL(k_validate<1>, dim3(grid), dim3(kWG), (size_t)cd.lds_bytes, stream, cd); break;
+    case 2: hipLaunchKernelGGL(k_validate<2>, dim3(grid), dim3(kWG), (size_t)cd.lds_bytes, stream, cd); break;
+    case 3: hipLaunchKernelGGL(k_validate<3>, dim3(grid), dim3(kWG), (size_t)cd.lds_bytes, stream, cd); break;
+    default: hipLaunchKernelGGL(k_validate<0>, dim3(grid), dim3(kWG), (size_t)cd.lds_bytes, stream, cd); break;
+    }
     return hipGetLastError();
 }
 
@@ -1297,6 +1311,7 @@ int validate_blocks_per_cu(int kind, size_t lds_bytes)
     int nb = 0;
     hipError_t e = kind == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_validate<1>, kWG, lds_bytes)
                  : kind == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_validate<2>, kWG, lds_bytes)
+                 : kind == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_validate<3>, kWG, lds_bytes)
                              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_validate<0>, kWG, lds_bytes);
     if (e != hipSuccess || nb < 1) nb = 1;
     return nb;
