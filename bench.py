@@ -365,7 +365,7 @@ def main():
     flop = ts * per_timestep_flop(w.team, w.env, True)
     achieved = flop / (kernel_ms * 1e-3)
     roofline = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_FP32_VALU / 1e12, unit="TFLOP/s",
-                    frac=achieved / PEAK_FP32_VALU, traffic=profiled_traffic(), kernel="k_validate<MV>",
+                    frac=achieved / PEAK_FP32_VALU, traffic=profiled_traffic(), kernel="k_validate<3> (exhaustive MV)",
                     kernel_ms=kernel_ms, flop_per_launch=flop)
     extra = dict(states_covered=st["states_covered"], rr_tests=st["rr_tests"], env_tests=st["env_tests"],
                  self_tests=st["self_tests"], near_rechecks=st["near_rechecks"],
