@@ -159,7 +159,14 @@ enum {
     MRV_HIERARCHICAL = 4,    /* MV: all environment tiles before robot-robot tiles (Alg. 1) */
     MRV_ORDER_BISECT = 0,    /* MV tile order: rake tiles in golden-ratio interleave (default) */
     MRV_ORDER_RAKE = 8,      /* MV tile order: the paper's rake, batches in index order */
-    MRV_ORDER_LINEAR = 16    /* MV tile order: consecutive timesteps (FFC always uses this) */
+    MRV_ORDER_LINEAR = 16,   /* MV tile order: consecutive timesteps (FFC always uses this) */
+    MRV_PAIRS_FIRST = 32,    /* early-terminating MV: within a tile, robot-robot (and self) tests
+                                before robot-obstacle tests */
+    MRV_OBSTACLES_FIRST = 64 /* early-terminating MV: robot-obstacle tests first.  With neither
+                                flag, pairs go first when the environment has a point cloud (its
+                                tests cost most) and obstacles first otherwise.  The order
+                                changes only how soon a collision ends a query, never the answer;
+                                exhaustive calls always test obstacles first. */
 };
 
 /* Near contact.  A test whose FP32 clearance lies within near_eps of zero is

@@ -669,9 +669,18 @@ void run_plan(mrv_ctx ctx, Scratch& sc, const CallPlan& pl, void* out_dev, hipSt
 }
 
 // Plan for a call whose queries all use one team and environment.
+// The default phase order of an early-terminating MV call: robot-robot tests first
+// when the environment has a point cloud (its tests cost most), else obstacles first.
+uint32_t resolve_phase_order(int kind, uint32_t flags, const EnvHost* env)
+{
+    if (kind != 0 || (flags & (MRV_PAIRS_FIRST | MRV_OBSTACLES_FIRST))) return flags;
+    return env && env->dev.n_pts > 0 ? flags | MRV_PAIRS_FIRST : flags;
+}
+
 CallPlan single_plan(const TeamHost& tm, const EnvHost* env, int kind, uint32_t flags, const DevPaths& dp,
                      long long max_T, uint32_t focus = 0)
 {
+    flags = resolve_phase_order(kind, flags, env);
     CallPlan pl{};
     pl.kind = kind;
     pl.flags = flags;
@@ -785,9 +794,12 @@ void device_call(mrv_ctx ctx, int team, int env, int kind, const mrv_paths* p, u
 
 uint32_t check_flags(int kind, uint32_t flags)
 {
-    const uint32_t known = MRV_CHECK_ENV | MRV_EXHAUSTIVE | MRV_HIERARCHICAL | MRV_ORDER_RAKE | MRV_ORDER_LINEAR;
+    const uint32_t known = MRV_CHECK_ENV | MRV_EXHAUSTIVE | MRV_HIERARCHICAL | MRV_ORDER_RAKE | MRV_ORDER_LINEAR |
+                           MRV_PAIRS_FIRST | MRV_OBSTACLES_FIRST;
     if (flags & ~known) throw Err{MRV_E_INVALID, "unknown flag bits"};
     if ((flags & MRV_ORDER_RAKE) && (flags & MRV_ORDER_LINEAR)) throw Err{MRV_E_INVALID, "two tile orders requested"};
+    if ((flags & MRV_PAIRS_FIRST) && (flags & MRV_OBSTACLES_FIRST))
+        throw Err{MRV_E_INVALID, "two phase orders requested"};
     if (kind == 1) flags &= MRV_EXHAUSTIVE;
     return flags;
 }
@@ -1355,12 +1367,13 @@ mrv_status mrv_submit(mrv_ctx ctx, const mrv_request* req, uint64_t* ticket)
                                                           ctx->recheck_records));
         // validate against the resident handles, resolve their device descriptors, then copy
         ServeRefs refs{};
+        mrv_request rq = *req;
         {
             std::lock_guard<std::mutex> lk(ctx->handle_mu);
             if (req->kind != 0 && req->kind != 1) throw Err{MRV_E_INVALID, "kind must be 0 (MV) or 1 (FFC)"};
             TeamHost& tm = find_team(ctx, req->team);
             const EnvHost* ev = req->kind == 0 ? find_env(ctx, req->env) : nullptr;
-            check_flags(req->kind, req->flags);
+            rq.flags = resolve_phase_order(req->kind, check_flags(req->kind, req->flags), ev);
             check_paths_host(tm, &req->paths);
             refs.team = tm.d_dev;
             refs.env = ev ? ev->d_dev : nullptr;
@@ -1371,7 +1384,7 @@ mrv_status mrv_submit(mrv_ctx ctx, const mrv_request* req, uint64_t* ticket)
             tm.inflight++;
             if (req->kind == 0 && req->env >= 0) ctx->envs.find(req->env)->second.inflight++;
         }
-        mrv_status s = ctx->serve->submit(*req, refs, ticket);
+        mrv_status s = ctx->serve->submit(rq, refs, ticket);
         if (s != MRV_OK) {
             std::lock_guard<std::mutex> lk(ctx->handle_mu);
             ctx->teams.find(req->team)->second.inflight--;

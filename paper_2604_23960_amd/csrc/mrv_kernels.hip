@@ -986,189 +986,207 @@ __global__ __launch_bounds__(kWG, kWGsPerCU) void k_validate(CallDev cd)
         }
         __syncthreads();
 
-        if (exhaustive) __builtin_amdgcn_s_setprio(0);
-        // --- robot-obstacle tests (MV with environment checking): one lane per
-        // (timestep, slot); obstacle parameters are wave-uniform scalar loads.
-        if (do_env) {
-            const int nch = (GS + kWave - 1) / kWave;
-            const int ntask = nv * nch;
-            float ro_max = 0.f;
-            for (int o = 0; o < env.n_sph; ++o) ro_max = fmaxf(ro_max, cloadf(&env.sph32[o].w));
-            // tasks wave, wave + 4, ... of this wave: exhaustive MV takes five (then
-            // four, two) at a time through each obstacle, exhaustive prioritised MV
-            // two; early-terminating calls one at a time, so a hit stops the wave
-            // before its next task
-            int task = wave;
-            if (exhaustive) {
-                if constexpr (KIND == 3) {      // the focus kernel keeps its registers for the focus logic
-                    for (; task + 4 * kWavesPerWG < ntask; task += 5 * kWavesPerWG) {
-                        const int tk[5] = { task, task + kWavesPerWG, task + 2 * kWavesPerWG, task + 3 * kWavesPerWG,
-                                            task + 4 * kWavesPerWG };
-                        env_tasks<5>(cd, tm, env, sp, tk, nch, ro_max, eps, exhaustive, q, focus, fall, s_t, &s_hit,
-                                     c_env, lane);
-                    }
-                    for (; task + 3 * kWavesPerWG < ntask; task += 4 * kWavesPerWG) {
-                        const int tk[4] = { task, task + kWavesPerWG, task + 2 * kWavesPerWG, task + 3 * kWavesPerWG };
-                        env_tasks<4>(cd, tm, env, sp, tk, nch, ro_max, eps, exhaustive, q, focus, fall, s_t, &s_hit,
-                                     c_env, lane);
-                    }
-                }
-                for (; task + kWavesPerWG < ntask; task += 2 * kWavesPerWG) {
-                    const int tk[2] = { task, task + kWavesPerWG };
-                    env_tasks<2>(cd, tm, env, sp, tk, nch, ro_max, eps, exhaustive, q, focus, fall, s_t, &s_hit, c_env,
-                             lane);
-                }
-            }
-            for (; task < ntask && !(!exhaustive && flag_read(&s_hit)); task += kWavesPerWG) {
-                const int tk[1] = { task };
-                env_tasks<1>(cd, tm, env, sp, tk, nch, ro_max, eps, exhaustive, q, focus, fall, s_t, &s_hit, c_env,
-                             lane);
-            }
-        }
-
-        if (exhaustive) __builtin_amdgcn_s_setprio(1);
-        // --- sphere-pair tests as 16 x 16 blocks on the matrix cores.  For slots a
-        // (rows, group ga) and b (columns, group gb) at one timestep,
-        //   D(a, b) = w_a + w_b - 2 p_a.p_b - 2 r_a r_b = |p_a - p_b|^2 - (r_a + r_b)^2,
-        // the K = 4 product by one MFMA with the accumulator preset to w_a, then a
-        // column minimum plus w_b on the vector unit.  One task per group ga runs,
-        // timestep by timestep, the self blocks of ga (MV with environment checking;
-        // pairs outside the self list masked) and its blocks against every group of
-        // the higher robots.  Lanes whose minimum lies within the bound's
-        // uncertainty revisit their pairs directly.
-        const bool do_self = do_env && tm.n_sblocks > 0;
-        if ((do_rr || do_self) && !(kMV && !exhaustive && flag_read(&s_hit))) {
-            const float rho2 = __uint_as_float(s_rho2);
-            const float rm = tm.r_max;
-            const float u = 5.9604645e-8f;
-            // |D_fp32 - D| <= 24 u (rho^2 + rm^2) for |p| <= rho, r <= rm: 4 u from each
-            // of w_a and w_b, 12 u from the MFMA's four fused steps (partial sums up to
-            // 3 (rho^2 + rm^2)), 4 u from adding w_b; 32 u leaves a margin
-            const float e_err = 32.f * u * (rho2 + rm * rm) + 1.0e-30f;
-            const float Rm = 2.f * rm;
-            const float e_hi = e_err + fmaf(2.f * Rm, eps, eps * eps);
-            const float e_lo = -(e_err + 2.f * Rm * eps);
-            const int i16 = lane & 15;
-            const int q4 = lane >> 4;
-            for (int k = wave; k < G; k += kWavesPerWG) {
-                if (kMV && !exhaustive && flag_read(&s_hit)) break;
-                const int* tk = tm.gtask + 8 * k;
-                const int ga = cload(tk + 0);
-                const int ra = cload(tk + 1);
-                const bool a_in = fall || ((focus >> ra) & 1u);     // ga's robot in focus
-                const int sb0 = do_self && a_in ? cload(tk + 2) : 0;
-                const int sb1 = do_self && a_in ? cload(tk + 3) : 0;
-                const bool higher_in = ra + 1 < 32 && (focus >> (ra + 1)) != 0u;   // a higher robot in focus
-                const int gs = do_rr && (a_in || higher_in) ? cload(tk + 4) : G;
-                const unsigned long long rr_tests = do_rr && a_in ? (unsigned long long)cload(tk + 5) : 0ull;
-                const unsigned long long self_tests = do_self && a_in ? (unsigned long long)cload(tk + 6) : 0ull;
-                // spheres of group ga, for the test counts of a robot outside the focus set
-                const int ga_n = a_in ? 0 : cload(reinterpret_cast<const int*>(tm.g_range) + 2 * ga + 1) -
-                                            cload(reinterpret_cast<const int*>(tm.g_range) + 2 * ga);
-                if (sb0 == sb1 && gs >= G) continue;
-                for (int c = 0; c < nv; ++c) {
-                    const int t = s_t[c];
-                    if (kMV) {
-                        if (!exhaustive && flag_read(&s_hit)) break;
-                    } else if (!exhaustive) {
-                        const unsigned known = flag_read(&s_key);
-                        if (known != 0xFFFFFFFFu && known < (unsigned)t * (unsigned)tm.P) break;
-                    }
-                    c_rr += rr_tests;
-                    c_self += self_tests;
-                    const float* base = sp + (long long)c * TS;
-                    const float aop = -2.f * base[q4 * GSp + ga * 16 + i16];
-                    const float4 cw = *reinterpret_cast<const float4*>(base + 4 * GSp + ga * 16 + 4 * q4);
-                    bool found = false;
-
-                    // self blocks of ga
-                    if (sb0 < sb1) {
-                        float best = 3.0e38f;
-                        for (int sb = sb0; sb < sb1; ++sb) {
-                            const int gb = cload(tm.sblocks + 8 * sb + 1);
-                            const unsigned long long* mk = tm.sb_mask + 4 * sb;
-                            const floatx4 acc = { lane_select(cload64(mk + 0), cw.x, kFar), lane_select(cload64(mk + 1), cw.y, kFar),
-                                                  lane_select(cload64(mk + 2), cw.z, kFar), lane_select(cload64(mk + 3), cw.w, kFar) };
-                            const float bop = base[q4 * GSp + gb * 16 + i16];
-                            const float wb = base[4 * GSp + gb * 16 + i16];
-                            const floatx4 d = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, bop, acc, 0, 0, 0);
-                            best = block_min(d, wb, best);
+        // The obstacle phase and the pair phase, in the call's order: early-terminating
+        // MV may run the pairs first (MRV_PAIRS_FIRST), so that their hits end a tile
+        // before costly obstacle tests; exhaustive MV and FFC keep a fixed order.
+        auto env_phase = [&]() {
+            if (exhaustive) __builtin_amdgcn_s_setprio(0);
+            // --- robot-obstacle tests (MV with environment checking): one lane per
+            // (timestep, slot); obstacle parameters are wave-uniform scalar loads.
+            if (do_env) {
+                const int nch = (GS + kWave - 1) / kWave;
+                const int ntask = nv * nch;
+                float ro_max = 0.f;
+                for (int o = 0; o < env.n_sph; ++o) ro_max = fmaxf(ro_max, cloadf(&env.sph32[o].w));
+                // tasks wave, wave + 4, ... of this wave: exhaustive MV takes five (then
+                // four, two) at a time through each obstacle, exhaustive prioritised MV
+                // two; early-terminating calls one at a time, so a hit stops the wave
+                // before its next task
+                int task = wave;
+                if (exhaustive) {
+                    if constexpr (KIND == 3) {      // the focus kernel keeps its registers for the focus logic
+                        for (; task + 4 * kWavesPerWG < ntask; task += 5 * kWavesPerWG) {
+                            const int tk[5] = { task, task + kWavesPerWG, task + 2 * kWavesPerWG, task + 3 * kWavesPerWG,
+                                                task + 4 * kWavesPerWG };
+                            env_tasks<5>(cd, tm, env, sp, tk, nch, ro_max, eps, exhaustive, q, focus, fall, s_t, &s_hit,
+                                         c_env, lane);
                         }
-                        bool hit = best < e_lo;
-                        const bool unsure = !hit && best < e_hi;
-                        if (!__ballot(hit) && __ballot(unsure) && unsure) {
-                            for (int sb = sb0; sb < sb1 && !hit; ++sb) {
+                        for (; task + 3 * kWavesPerWG < ntask; task += 4 * kWavesPerWG) {
+                            const int tk[4] = { task, task + kWavesPerWG, task + 2 * kWavesPerWG, task + 3 * kWavesPerWG };
+                            env_tasks<4>(cd, tm, env, sp, tk, nch, ro_max, eps, exhaustive, q, focus, fall, s_t, &s_hit,
+                                         c_env, lane);
+                        }
+                    }
+                    for (; task + kWavesPerWG < ntask; task += 2 * kWavesPerWG) {
+                        const int tk[2] = { task, task + kWavesPerWG };
+                        env_tasks<2>(cd, tm, env, sp, tk, nch, ro_max, eps, exhaustive, q, focus, fall, s_t, &s_hit, c_env,
+                                 lane);
+                    }
+                }
+                for (; task < ntask && !(!exhaustive && flag_read(&s_hit)); task += kWavesPerWG) {
+                    const int tk[1] = { task };
+                    env_tasks<1>(cd, tm, env, sp, tk, nch, ro_max, eps, exhaustive, q, focus, fall, s_t, &s_hit, c_env,
+                                 lane);
+                }
+            }
+
+        };
+        auto pair_phase = [&]() {
+            if (exhaustive) __builtin_amdgcn_s_setprio(1);
+            // --- sphere-pair tests as 16 x 16 blocks on the matrix cores.  For slots a
+            // (rows, group ga) and b (columns, group gb) at one timestep,
+            //   D(a, b) = w_a + w_b - 2 p_a.p_b - 2 r_a r_b = |p_a - p_b|^2 - (r_a + r_b)^2,
+            // the K = 4 product by one MFMA with the accumulator preset to w_a, then a
+            // column minimum plus w_b on the vector unit.  One task per group ga runs,
+            // timestep by timestep, the self blocks of ga (MV with environment checking;
+            // pairs outside the self list masked) and its blocks against every group of
+            // the higher robots.  Lanes whose minimum lies within the bound's
+            // uncertainty revisit their pairs directly.
+            const bool do_self = do_env && tm.n_sblocks > 0;
+            if ((do_rr || do_self) && !(kMV && !exhaustive && flag_read(&s_hit))) {
+                const float rho2 = __uint_as_float(s_rho2);
+                const float rm = tm.r_max;
+                const float u = 5.9604645e-8f;
+                // |D_fp32 - D| <= 24 u (rho^2 + rm^2) for |p| <= rho, r <= rm: 4 u from each
+                // of w_a and w_b, 12 u from the MFMA's four fused steps (partial sums up to
+                // 3 (rho^2 + rm^2)), 4 u from adding w_b; 32 u leaves a margin
+                const float e_err = 32.f * u * (rho2 + rm * rm) + 1.0e-30f;
+                const float Rm = 2.f * rm;
+                const float e_hi = e_err + fmaf(2.f * Rm, eps, eps * eps);
+                const float e_lo = -(e_err + 2.f * Rm * eps);
+                const int i16 = lane & 15;
+                const int q4 = lane >> 4;
+                for (int k = wave; k < G; k += kWavesPerWG) {
+                    if (kMV && !exhaustive && flag_read(&s_hit)) break;
+                    const int* tk = tm.gtask + 8 * k;
+                    const int ga = cload(tk + 0);
+                    const int ra = cload(tk + 1);
+                    const bool a_in = fall || ((focus >> ra) & 1u);     // ga's robot in focus
+                    const int sb0 = do_self && a_in ? cload(tk + 2) : 0;
+                    const int sb1 = do_self && a_in ? cload(tk + 3) : 0;
+                    const bool higher_in = ra + 1 < 32 && (focus >> (ra + 1)) != 0u;   // a higher robot in focus
+                    const int gs = do_rr && (a_in || higher_in) ? cload(tk + 4) : G;
+                    const unsigned long long rr_tests = do_rr && a_in ? (unsigned long long)cload(tk + 5) : 0ull;
+                    const unsigned long long self_tests = do_self && a_in ? (unsigned long long)cload(tk + 6) : 0ull;
+                    // spheres of group ga, for the test counts of a robot outside the focus set
+                    const int ga_n = a_in ? 0 : cload(reinterpret_cast<const int*>(tm.g_range) + 2 * ga + 1) -
+                                                cload(reinterpret_cast<const int*>(tm.g_range) + 2 * ga);
+                    if (sb0 == sb1 && gs >= G) continue;
+                    for (int c = 0; c < nv; ++c) {
+                        const int t = s_t[c];
+                        if (kMV) {
+                            if (!exhaustive && flag_read(&s_hit)) break;
+                        } else if (!exhaustive) {
+                            const unsigned known = flag_read(&s_key);
+                            if (known != 0xFFFFFFFFu && known < (unsigned)t * (unsigned)tm.P) break;
+                        }
+                        c_rr += rr_tests;
+                        c_self += self_tests;
+                        const float* base = sp + (long long)c * TS;
+                        const float aop = -2.f * base[q4 * GSp + ga * 16 + i16];
+                        const float4 cw = *reinterpret_cast<const float4*>(base + 4 * GSp + ga * 16 + 4 * q4);
+                        bool found = false;
+
+                        // self blocks of ga
+                        if (sb0 < sb1) {
+                            float best = 3.0e38f;
+                            for (int sb = sb0; sb < sb1; ++sb) {
                                 const int gb = cload(tm.sblocks + 8 * sb + 1);
                                 const unsigned long long* mk = tm.sb_mask + 4 * sb;
-                                hit = direct_block(cd, tm, base, GSp, ga, gb, lane, mk, eps, q, t, RK_SELF, 0u, &s_hit, &s_key, true);
-                            }
-                        }
-                        if (__ballot(hit)) {
-                            found = true;
-                            if (lane == 0) s_hit = 1;
-                        }
-                    }
-
-                    // robot-robot blocks against the higher robots
-                    if (gs < G && !(found && !exhaustive)) {
-                        const floatx4 acc = { cw.x, cw.y, cw.z, cw.w };
-                        // MV: all higher robots in one sweep, unless ga's robot is outside the
-                        // focus set; then robot by robot, over those in it
-                        const bool sweep = kMV && a_in;
-                        const int rb_end = sweep ? ra + 2 : n;
-                        for (int rb = ra + 1; rb < rb_end; ++rb) {
-                            if (!a_in && !((focus >> rb) & 1u)) continue;
-                            const int g0 = sweep ? gs : cload(tm.r_group_off + rb);
-                            const int g1 = sweep ? G : cload(tm.r_group_off + rb + 1);
-                            if (!a_in)
-                                c_rr += (unsigned long long)ga_n *
-                                        (unsigned)(cload(tm.r_sphere_off + rb + 1) - cload(tm.r_sphere_off + rb));
-                            const unsigned key = kMV ? 0u : (unsigned)t * (unsigned)tm.P + pair_index(ra, rb, n);
-                            if (!kMV && !exhaustive && key >= flag_read(&s_key)) break;
-                            float best = 3.0e38f;
-                            int g = g0;
-                            for (; g + 4 <= g1; g += 4) {
-                                float bop[4], wb[4];
-                                floatx4 d[4];
-#pragma unroll
-                                for (int v = 0; v < 4; ++v) {
-                                    bop[v] = base[q4 * GSp + (g + v) * 16 + i16];
-                                    wb[v] = base[4 * GSp + (g + v) * 16 + i16];
-                                }
-#pragma unroll
-                                for (int v = 0; v < 4; ++v) d[v] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, bop[v], acc, 0, 0, 0);
-                                best = fminf(best, fminf(fminf(col_min(d[0], wb[0]), col_min(d[1], wb[1])),
-                                                         fminf(col_min(d[2], wb[2]), col_min(d[3], wb[3]))));
-                            }
-                            for (; g < g1; ++g) {
-                                const float bop = base[q4 * GSp + g * 16 + i16];
-                                const float wb = base[4 * GSp + g * 16 + i16];
+                                const floatx4 acc = { lane_select(cload64(mk + 0), cw.x, kFar), lane_select(cload64(mk + 1), cw.y, kFar),
+                                                      lane_select(cload64(mk + 2), cw.z, kFar), lane_select(cload64(mk + 3), cw.w, kFar) };
+                                const float bop = base[q4 * GSp + gb * 16 + i16];
+                                const float wb = base[4 * GSp + gb * 16 + i16];
                                 const floatx4 d = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, bop, acc, 0, 0, 0);
                                 best = block_min(d, wb, best);
                             }
                             bool hit = best < e_lo;
                             const bool unsure = !hit && best < e_hi;
                             if (!__ballot(hit) && __ballot(unsure) && unsure) {
-                                for (int gg = g0; gg < g1 && !hit; ++gg)
-                                    hit = direct_block(cd, tm, base, GSp, ga, gg, lane, nullptr, eps, q, t, RK_RR, key,
-                                                       &s_hit, &s_key, kMV);
+                                for (int sb = sb0; sb < sb1 && !hit; ++sb) {
+                                    const int gb = cload(tm.sblocks + 8 * sb + 1);
+                                    const unsigned long long* mk = tm.sb_mask + 4 * sb;
+                                    hit = direct_block(cd, tm, base, GSp, ga, gb, lane, mk, eps, q, t, RK_SELF, 0u, &s_hit, &s_key, true);
+                                }
                             }
                             if (__ballot(hit)) {
                                 found = true;
-                                if (lane == 0) {
-                                    if (kMV) s_hit = 1;
-                                    else atomicMin(&s_key, key);
-                                }
-                                // FFC: higher robots give larger keys; MV robot by robot: one
-                                // hit decides
-                                if (!exhaustive && (!kMV || !sweep)) break;
+                                if (lane == 0) s_hit = 1;
                             }
                         }
+
+                        // robot-robot blocks against the higher robots
+                        if (gs < G && !(found && !exhaustive)) {
+                            const floatx4 acc = { cw.x, cw.y, cw.z, cw.w };
+                            // MV: all higher robots in one sweep, unless ga's robot is outside the
+                            // focus set; then robot by robot, over those in it
+                            const bool sweep = kMV && a_in;
+                            const int rb_end = sweep ? ra + 2 : n;
+                            for (int rb = ra + 1; rb < rb_end; ++rb) {
+                                if (!a_in && !((focus >> rb) & 1u)) continue;
+                                const int g0 = sweep ? gs : cload(tm.r_group_off + rb);
+                                const int g1 = sweep ? G : cload(tm.r_group_off + rb + 1);
+                                if (!a_in)
+                                    c_rr += (unsigned long long)ga_n *
+                                            (unsigned)(cload(tm.r_sphere_off + rb + 1) - cload(tm.r_sphere_off + rb));
+                                const unsigned key = kMV ? 0u : (unsigned)t * (unsigned)tm.P + pair_index(ra, rb, n);
+                                if (!kMV && !exhaustive && key >= flag_read(&s_key)) break;
+                                float best = 3.0e38f;
+                                int g = g0;
+                                for (; g + 4 <= g1; g += 4) {
+                                    float bop[4], wb[4];
+                                    floatx4 d[4];
+    #pragma unroll
+                                    for (int v = 0; v < 4; ++v) {
+                                        bop[v] = base[q4 * GSp + (g + v) * 16 + i16];
+                                        wb[v] = base[4 * GSp + (g + v) * 16 + i16];
+                                    }
+    #pragma unroll
+                                    for (int v = 0; v < 4; ++v) d[v] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, bop[v], acc, 0, 0, 0);
+                                    best = fminf(best, fminf(fminf(col_min(d[0], wb[0]), col_min(d[1], wb[1])),
+                                                             fminf(col_min(d[2], wb[2]), col_min(d[3], wb[3]))));
+                                }
+                                for (; g < g1; ++g) {
+                                    const float bop = base[q4 * GSp + g * 16 + i16];
+                                    const float wb = base[4 * GSp + g * 16 + i16];
+                                    const floatx4 d = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, bop, acc, 0, 0, 0);
+                                    best = block_min(d, wb, best);
+                                }
+                                bool hit = best < e_lo;
+                                const bool unsure = !hit && best < e_hi;
+                                if (!__ballot(hit) && __ballot(unsure) && unsure) {
+                                    for (int gg = g0; gg < g1 && !hit; ++gg)
+                                        hit = direct_block(cd, tm, base, GSp, ga, gg, lane, nullptr, eps, q, t, RK_RR, key,
+                                                           &s_hit, &s_key, kMV);
+                                }
+                                if (__ballot(hit)) {
+                                    found = true;
+                                    if (lane == 0) {
+                                        if (kMV) s_hit = 1;
+                                        else atomicMin(&s_key, key);
+                                    }
+                                    // FFC: higher robots give larger keys; MV robot by robot: one
+                                    // hit decides
+                                    if (!exhaustive && (!kMV || !sweep)) break;
+                                }
+                            }
+                        }
+                        // FFC: this group's later timesteps give larger keys
+                        if (!kMV && found && !exhaustive) break;
                     }
-                    // FFC: this group's later timesteps give larger keys
-                    if (!kMV && found && !exhaustive) break;
                 }
             }
+
+        };
+        if constexpr (KIND == 0 || KIND == 2) {
+            const bool pairs_first = (flags & MRV_PAIRS_FIRST) != 0;
+            for (int ph = 0; ph < 2; ++ph) {
+                if ((ph == 0) != pairs_first) env_phase();
+                else pair_phase();
+            }
+        } else {
+            env_phase();
+            pair_phase();
         }
 
         __syncthreads();

@@ -29,7 +29,7 @@ def test_hetero_cloud_mv_ffc(big):
     try:
         th, eh = ctx.load_team(team), ctx.load_env(env)
         ref = oracle.mv(ot, oe, oracle.Paths(mv))
-        for flags in (mrv.CHECK_ENV, mrv.CHECK_ENV | mrv.EXHAUSTIVE, 0):
+        for flags in (mrv.CHECK_ENV, mrv.CHECK_ENV | mrv.OBSTACLES_FIRST, mrv.CHECK_ENV | mrv.EXHAUSTIVE, 0):
             got = ctx.mv(th, eh, mv, flags)
             exp = ref if flags & mrv.CHECK_ENV else oracle.mv(ot, oe, oracle.Paths(mv), check_env=False)
             assert np.array_equal(got, exp), (flags, np.nonzero(got != exp)[0][:10])
@@ -52,7 +52,8 @@ def test_single_arm_in_cloud():
     ctx = mrv.Context(0)
     try:
         th, eh = ctx.load_team(team), ctx.load_env(env)
-        for flags in (mrv.CHECK_ENV, mrv.CHECK_ENV | mrv.EXHAUSTIVE, mrv.CHECK_ENV | mrv.HIERARCHICAL):
+        for flags in (mrv.CHECK_ENV, mrv.CHECK_ENV | mrv.PAIRS_FIRST, mrv.CHECK_ENV | mrv.EXHAUSTIVE,
+                      mrv.CHECK_ENV | mrv.HIERARCHICAL):
             got = ctx.mv(th, eh, paths, flags)
             assert np.array_equal(got, ref), (flags, np.nonzero(got != ref)[0][:10])
     finally:

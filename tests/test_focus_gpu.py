@@ -14,6 +14,7 @@ pytestmark = pytest.mark.gpu
 
 FLAG_SETS = [
     mrv.CHECK_ENV,
+    mrv.CHECK_ENV | mrv.PAIRS_FIRST,
     mrv.CHECK_ENV | mrv.EXHAUSTIVE,
     mrv.CHECK_ENV | mrv.HIERARCHICAL,
     mrv.CHECK_ENV | mrv.ORDER_LINEAR,

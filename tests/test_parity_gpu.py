@@ -16,6 +16,8 @@ pytestmark = pytest.mark.gpu
 
 FLAG_SETS = [
     mrv.CHECK_ENV,
+    mrv.CHECK_ENV | mrv.PAIRS_FIRST,
+    mrv.CHECK_ENV | mrv.OBSTACLES_FIRST | mrv.ORDER_RAKE,
     mrv.CHECK_ENV | mrv.EXHAUSTIVE,
     mrv.CHECK_ENV | mrv.HIERARCHICAL,
     mrv.CHECK_ENV | mrv.ORDER_RAKE,
@@ -254,6 +256,9 @@ def test_invalid_inputs_rejected(ctx):
     with pytest.raises(mrv.MrvError) as e:
         ctx.mv(team + 1000, env, w.paths, mrv.CHECK_ENV)
     assert e.value.status == mrv.MRV_E_HANDLE
+    with pytest.raises(mrv.MrvError) as e:
+        ctx.mv(team, env, w.paths, mrv.CHECK_ENV | mrv.PAIRS_FIRST | mrv.OBSTACLES_FIRST)
+    assert e.value.status == mrv.MRV_E_INVALID
     # the device path flags the malformed query and reports at sync
     import torch
     dp = mrv.DevicePaths(bad)
