@@ -536,16 +536,16 @@ int default_chunk(const TeamHost& tm, int kind, int exhaustive)
     // early-terminating calls: long tiles, since most queries end in their first
     // tiles, whose fixed cost then dominates -- FFC 16 timesteps; MV the most that
     // keep two workgroups per CU if that is at least 12 (at most 16), else 16 (as
-    // many as fit); exhaustive calls: up to 8,
-    // the largest that keeps five workgroups per CU (the register limit) within its
-    // 160 KiB of LDS if that is at least 2, else four, three, two, one
+    // many as fit); exhaustive calls: up to 8, the largest that keeps as many
+    // workgroups per CU as registers allow (six for MV, five for FFC) within the
+    // CU's 160 KiB of LDS if that is at least 2, else one workgroup fewer, ...
     if (!exhaustive) {
         int c = 16;
         const int c2 = (int)((160 * 1024 / 2 - 1024) / per_t);
         if (kind == 0 && c2 >= 12) c = std::min(16, c2);
         return std::max(1, std::min(cmax, c));
     }
-    for (int wgs = kWGsPerCU; wgs >= 1; --wgs) {
+    for (int wgs = kind == 0 ? kExhWGsPerCU : kWGsPerCU; wgs >= 1; --wgs) {
         const int c = (int)((160 * 1024 / wgs - 1024) / per_t);
         if (c >= 2 || wgs == 1) return std::max(1, std::min(cmax, std::min(8, c)));
     }

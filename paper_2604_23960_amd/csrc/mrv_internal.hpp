@@ -15,6 +15,7 @@ constexpr int kMaxJoints = 8;
 constexpr int kMaxChunk = 64;       // timesteps per tile
 constexpr int kLdsBudget = 160 * 1024;   // LDS one workgroup may use on gfx950
 constexpr int kWGsPerCU = 5;        // validation workgroups per CU the register budget allows
+constexpr int kExhWGsPerCU = 6;     // the same for the exhaustive MV kernel (80 VGPRs)
 
 enum RecheckKind : int { RK_RR = 0, RK_SELF = 1, RK_ENV_SPH = 2, RK_ENV_BOX = 3, RK_ENV_CYL = 4, RK_ENV_PT = 5 };
 

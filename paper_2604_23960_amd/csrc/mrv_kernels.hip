@@ -785,7 +785,7 @@ __device__ __forceinline__ void env_tasks(const CallDev& cd, const TeamDev& tm, 
 }
 
 template <int KIND>
-__global__ __launch_bounds__(kWG, kWGsPerCU) void k_validate(CallDev cd)
+__global__ __launch_bounds__(kWG, KIND == 3 ? kExhWGsPerCU : kWGsPerCU) void k_validate(CallDev cd)
 {
     // KIND: 0 early-terminating MV, 1 FFC, 2 MV with a focus set (prioritised MV),
     // 3 exhaustive MV; the exhaustive mode is a compile-time constant for 0 and 3
@@ -998,19 +998,13 @@ __global__ __launch_bounds__(kWG, kWGsPerCU) void k_validate(CallDev cd)
                 const int ntask = nv * nch;
                 float ro_max = 0.f;
                 for (int o = 0; o < env.n_sph; ++o) ro_max = fmaxf(ro_max, cloadf(&env.sph32[o].w));
-                // tasks wave, wave + 4, ... of this wave: exhaustive MV takes five (then
-                // four, two) at a time through each obstacle, exhaustive prioritised MV
-                // two; early-terminating calls one at a time, so a hit stops the wave
-                // before its next task
+                // tasks wave, wave + 4, ... of this wave: exhaustive MV takes four (then
+                // two) at a time through each obstacle, exhaustive prioritised MV two;
+                // early-terminating calls one at a time, so a hit stops the wave before
+                // its next task
                 int task = wave;
                 if (exhaustive) {
                     if constexpr (KIND == 3) {      // the focus kernel keeps its registers for the focus logic
-                        for (; task + 4 * kWavesPerWG < ntask; task += 5 * kWavesPerWG) {
-                            const int tk[5] = { task, task + kWavesPerWG, task + 2 * kWavesPerWG, task + 3 * kWavesPerWG,
-                                                task + 4 * kWavesPerWG };
-                            env_tasks<5>(cd, tm, env, sp, tk, nch, ro_max, eps, exhaustive, q, focus, fall, s_t, &s_hit,
-                                         c_env, lane);
-                        }
                         for (; task + 3 * kWavesPerWG < ntask; task += 4 * kWavesPerWG) {
                             const int tk[4] = { task, task + kWavesPerWG, task + 2 * kWavesPerWG, task + 3 * kWavesPerWG };
                             env_tasks<4>(cd, tm, env, sp, tk, nch, ro_max, eps, exhaustive, q, focus, fall, s_t, &s_hit,
