@@ -283,6 +283,29 @@ def cloud_bench(log, n_queries=262_144, tune_sample=2048, exhaustive_queries=819
     return res
 
 
+def simd_baseline(w, value, n_sample=16384):
+    """The paper's own design on the host cores (baseline_cpu: rake packing of
+    W = 8 timesteps per batch, FP32, early exit; all host threads): exhaustive MV
+    on the first n_sample motions and early-exit MV on all of them."""
+    import baseline_cpu as B
+    sub = w.paths.subset(np.arange(min(n_sample, w.paths.n_queries)))
+    B.mv(w.team, w.env, w.paths.subset(np.arange(64)), True, True)          # build and start the threads
+    t0 = time.perf_counter()
+    _, states = B.mv(w.team, w.env, sub, True, True)
+    dt = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, st_early = B.mv(w.team, w.env, w.paths, True, False)
+    dt_early = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    rate = states / dt
+    return dict(kind="cpu SIMD rake, W = 8, FP32", threads=threads,
+                exhaustive=dict(robot_states_per_s=rate, sample=f"first {sub.n_queries} motions, {states} robot-states",
+                                seconds=dt),
+                early_exit=dict(ms_per_call=dt_early * 1e3, motions=w.paths.n_queries,
+                                robot_states_evaluated=st_early),
+                gpu_over_simd_exhaustive=value / rate)
+
+
 def cpu_baseline(w, max_queries, target_s=15.0):
     """The FP64 oracle on the host cores, on the same work as the headline: MV with
     robot-obstacle, self and robot-robot checks, every relation at every state
@@ -405,6 +428,8 @@ def main():
     if not args.no_cpu:
         log("timing the FP64 oracle on the host")
         cpu = cpu_baseline(w, args.cpu_queries)
+        log("timing the SIMD rake baseline on the host")
+        extra["cpu_simd_rake"] = simd_baseline(w, value)
         extra["gpu_covered_states_per_s_early_exit_same_metric"] = extra.get("mv_early_exit", {}).get(
             "covered_states_per_s")
     line = dict(metric="robot-states validated/s", value=value, unit="robot-states/s", n_gpus=1,
