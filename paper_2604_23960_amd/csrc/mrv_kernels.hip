@@ -825,6 +825,8 @@ __global__ __launch_bounds__(kWG, KIND == 3 ? kExhWGsPerCU : kWGsPerCU) void k_v
         s_nrun = 0;
         s_nskip = 0;
         s_nstates = 0;
+        s_q = -1;                       // no tile yet whose outcome is to publish
+        s_nv = 0;
     }
 
     for (;;) {
@@ -834,6 +836,15 @@ __global__ __launch_bounds__(kWG, KIND == 3 ? kExhWGsPerCU : kWGsPerCU) void k_v
         // (early-terminating calls keep one level: their obstacle verdicts end queries).
         if (exhaustive) __builtin_amdgcn_s_setprio(2);
         if (tid == 0) {
+            // the previous tile's outcome (all its waves passed the barrier that
+            // ended it) goes to its query's word before the next claim
+            if (s_q >= 0 && s_nv > 0) {
+                if (kMV) {
+                    if (s_hit) atomicOr(cd.word + s_q, 1u);
+                } else {
+                    if (s_key != 0xFFFFFFFFu) atomicMin(cd.word + s_q, s_key);
+                }
+            }
             const long long g = (long long)atomicAdd(&w64[1], 1ull);
             int q = -1, nv = 0, phase = 0, C = 1;
             unsigned known = !kMV ? 0xFFFFFFFFu : 0u, focus = 0u;
@@ -1183,14 +1194,6 @@ __global__ __launch_bounds__(kWG, KIND == 3 ? kExhWGsPerCU : kWGsPerCU) void k_v
             pair_phase();
         }
 
-        __syncthreads();
-        if (tid == 0) {
-            if (kMV) {
-                if (s_hit) atomicOr(cd.word + q, 1u);
-            } else {
-                if (s_key != 0xFFFFFFFFu) atomicMin(cd.word + q, s_key);
-            }
-        }
         __syncthreads();
     }
 
