@@ -534,13 +534,15 @@ int default_chunk(const TeamHost& tm, int kind, int exhaustive)
     cmax = std::min(cmax, kMaxChunk);
     if (cmax < 1) cmax = 1;
     // early-terminating calls: long tiles, since most queries end in their first
-    // tiles, whose fixed cost then dominates -- FFC 16 timesteps; MV the most that
+    // tiles, whose fixed cost then dominates -- FFC as many timesteps as fit, up to
+    // 32 (one 8-wave workgroup per CU; the arm+rectangle team: 24, 20.1 ms against
+    // 26.5 ms at 16); MV the most that
     // keep two workgroups per CU if that is at least 12 (at most 16), else 16 (as
     // many as fit); exhaustive calls: up to 8, the largest that keeps as many
     // workgroups per CU as registers allow (six for MV, five for FFC) within the
     // CU's 160 KiB of LDS if that is at least 2, else one workgroup fewer, ...
     if (!exhaustive) {
-        int c = 16;
+        int c = kind == 1 ? std::min(cmax, 32) : 16;
         const int c2 = (int)((160 * 1024 / 2 - 1024) / per_t);
         if (kind == 0 && c2 >= 12) c = std::min(16, c2);
         return std::max(1, std::min(cmax, c));

@@ -785,12 +785,15 @@ __device__ __forceinline__ void env_tasks(const CallDev& cd, const TeamDev& tm, 
 }
 
 template <int KIND>
-__global__ __launch_bounds__(kWG, KIND == 3 ? kExhWGsPerCU : kWGsPerCU) void k_validate(CallDev cd)
+__global__ __launch_bounds__(validate_wg(KIND), KIND == 1 ? 2 : (KIND == 3 ? kExhWGsPerCU : kWGsPerCU)) void k_validate(CallDev cd)
 {
-    // KIND: 0 early-terminating MV, 1 FFC, 2 MV with a focus set (prioritised MV),
-    // 3 exhaustive MV; the exhaustive mode is a compile-time constant for 0 and 3
-    constexpr bool kMV = KIND != 1;
+    // KIND: 0 early-terminating MV, 1 early-terminating FFC, 2 MV with a focus set
+    // (prioritised MV), 3 exhaustive MV, 4 exhaustive FFC; the exhaustive mode is a
+    // compile-time constant except for 2
+    constexpr bool kMV = KIND != 1 && KIND != 4;
     constexpr bool kFocus = KIND == 2;
+    constexpr int WG = validate_wg(KIND);
+    constexpr int kWaves = WG / kWave;
     extern __shared__ float4 dyn[];
 
     __shared__ int s_t[kMaxChunk];
@@ -807,7 +810,7 @@ __global__ __launch_bounds__(kWG, KIND == 3 ? kExhWGsPerCU : kWGsPerCU) void k_v
     const int lane = tid & 63;
     const int wave = wave_uniform(tid >> 6);
     const unsigned flags = cd.flags;
-    const bool exhaustive = KIND == 3 || (KIND != 0 && (flags & MRV_EXHAUSTIVE) != 0);
+    const bool exhaustive = KIND == 3 || KIND == 4 || (KIND == 2 && (flags & MRV_EXHAUSTIVE) != 0);
     const bool check_env = kMV && (flags & MRV_CHECK_ENV) != 0;
     const bool hier = check_env && (flags & MRV_HIERARCHICAL) != 0;
     const float eps = cd.eps32;
@@ -944,7 +947,7 @@ __global__ __launch_bounds__(kWG, KIND == 3 ? kExhWGsPerCU : kWGsPerCU) void k_v
         float* sp = reinterpret_cast<float*>(dyn);                      // [C][TS]
 
         // --- configurations and FP32 forward kinematics: one lane per (timestep, robot)
-        for (int idx = tid; idx < nv * n; idx += kWG) {
+        for (int idx = tid; idx < nv * n; idx += WG) {
             const int c = idx / n;
             const int r = idx - c * n;
             robot_frames32(tm, cd, cd.wp_begin[qp0 + r], cd.wp_begin[qp0 + r + 1], r, s_t[c],
@@ -953,7 +956,7 @@ __global__ __launch_bounds__(kWG, KIND == 3 ? kExhWGsPerCU : kWGsPerCU) void k_v
         __syncthreads();
 
         // --- sphere centres, one lane per (timestep, slot); padding slots sit at the origin
-        for (int idx = tid; idx < nv * GS; idx += kWG) {
+        for (int idx = tid; idx < nv * GS; idx += WG) {
             const int c = idx / GS;
             const int s = idx - c * GS;
             const int sph = tm.slot_sphere[s];
@@ -976,7 +979,7 @@ __global__ __launch_bounds__(kWG, KIND == 3 ? kExhWGsPerCU : kWGsPerCU) void k_v
         // --- radius and w rows, over the frames
         {
             float r2max = 0.f;
-            for (int idx = tid; idx < nv * GS; idx += kWG) {
+            for (int idx = tid; idx < nv * GS; idx += WG) {
                 const int c = idx / GS;
                 const int s = idx - c * GS;
                 const int sph = tm.slot_sphere[s];
@@ -1016,19 +1019,19 @@ __global__ __launch_bounds__(kWG, KIND == 3 ? kExhWGsPerCU : kWGsPerCU) void k_v
                 int task = wave;
                 if (exhaustive) {
                     if constexpr (KIND == 3) {      // the focus kernel keeps its registers for the focus logic
-                        for (; task + 3 * kWavesPerWG < ntask; task += 4 * kWavesPerWG) {
-                            const int tk[4] = { task, task + kWavesPerWG, task + 2 * kWavesPerWG, task + 3 * kWavesPerWG };
+                        for (; task + 3 * kWaves < ntask; task += 4 * kWaves) {
+                            const int tk[4] = { task, task + kWaves, task + 2 * kWaves, task + 3 * kWaves };
                             env_tasks<4>(cd, tm, env, sp, tk, nch, ro_max, eps, exhaustive, q, focus, fall, s_t, &s_hit,
                                          c_env, lane);
                         }
                     }
-                    for (; task + kWavesPerWG < ntask; task += 2 * kWavesPerWG) {
-                        const int tk[2] = { task, task + kWavesPerWG };
+                    for (; task + kWaves < ntask; task += 2 * kWaves) {
+                        const int tk[2] = { task, task + kWaves };
                         env_tasks<2>(cd, tm, env, sp, tk, nch, ro_max, eps, exhaustive, q, focus, fall, s_t, &s_hit, c_env,
                                  lane);
                     }
                 }
-                for (; task < ntask && !(!exhaustive && flag_read(&s_hit)); task += kWavesPerWG) {
+                for (; task < ntask && !(!exhaustive && flag_read(&s_hit)); task += kWaves) {
                     const int tk[1] = { task };
                     env_tasks<1>(cd, tm, env, sp, tk, nch, ro_max, eps, exhaustive, q, focus, fall, s_t, &s_hit, c_env,
                                  lane);
@@ -1061,7 +1064,7 @@ __global__ __launch_bounds__(kWG, KIND == 3 ? kExhWGsPerCU : kWGsPerCU) void k_v
                 const float e_lo = -(e_err + 2.f * Rm * eps);
                 const int i16 = lane & 15;
                 const int q4 = lane >> 4;
-                for (int k = wave; k < G; k += kWavesPerWG) {
+                for (int k = wave; k < G; k += kWaves) {
                     if (kMV && !exhaustive && flag_read(&s_hit)) break;
                     const int* tk = tm.gtask + 8 * k;
                     const int ga = cload(tk + 0);
@@ -1291,14 +1294,18 @@ hipError_t launch_validate(const CallDev& cd, int grid, hipStream_t stream)
         if (e == hipSuccess)
             e = hipFuncSetAttribute((const void*)k_validate<3>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     kLdsBudget - 1024);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)k_validate<4>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    kLdsBudget - 1024);
         return e;
     }();
     if (lds_opt != hipSuccess && cd.lds_bytes > 64 * 1024) return lds_opt;
     switch (validate_variant(cd)) {
-    case 1: hipLaunchKernelGGL(k_validate<1>, dim3(grid), dim3(kWG), (size_t)cd.lds_bytes, stream, cd); break;
-    case 2: hipLaunchKernelGGL(k_validate<2>, dim3(grid), dim3(kWG), (size_t)cd.lds_bytes, stream, cd); break;
-    case 3: hipLaunchKernelGGL(k_validate<3>, dim3(grid), dim3(kWG), (size_t)cd.lds_bytes, stream, cd); break;
-    default: hipLaunchKernelGGL(k_validate<0>, dim3(grid), dim3(kWG), (size_t)cd.lds_bytes, stream, cd); break;
+    case 1: hipLaunchKernelGGL(k_validate<1>, dim3(grid), dim3(validate_wg(1)), (size_t)cd.lds_bytes, stream, cd); break;
+    case 2: hipLaunchKernelGGL(k_validate<2>, dim3(grid), dim3(validate_wg(2)), (size_t)cd.lds_bytes, stream, cd); break;
+    case 3: hipLaunchKernelGGL(k_validate<3>, dim3(grid), dim3(validate_wg(3)), (size_t)cd.lds_bytes, stream, cd); break;
+    case 4: hipLaunchKernelGGL(k_validate<4>, dim3(grid), dim3(validate_wg(4)), (size_t)cd.lds_bytes, stream, cd); break;
+    default: hipLaunchKernelGGL(k_validate<0>, dim3(grid), dim3(validate_wg(0)), (size_t)cd.lds_bytes, stream, cd); break;
     }
     return hipGetLastError();
 }
@@ -1324,10 +1331,11 @@ hipError_t launch_spheres(const CallDev& cd, const int* st_q, const int* st_t, i
 int validate_blocks_per_cu(int kind, size_t lds_bytes)
 {
     int nb = 0;
-    hipError_t e = kind == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_validate<1>, kWG, lds_bytes)
-                 : kind == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_validate<2>, kWG, lds_bytes)
-                 : kind == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_validate<3>, kWG, lds_bytes)
-                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_validate<0>, kWG, lds_bytes);
+    hipError_t e = kind == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_validate<1>, validate_wg(1), lds_bytes)
+                 : kind == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_validate<2>, validate_wg(2), lds_bytes)
+                 : kind == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_validate<3>, validate_wg(3), lds_bytes)
+                 : kind == 4 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_validate<4>, validate_wg(4), lds_bytes)
+                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_validate<0>, validate_wg(0), lds_bytes);
     if (e != hipSuccess || nb < 1) nb = 1;
     return nb;
 }
