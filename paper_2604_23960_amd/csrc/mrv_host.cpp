@@ -533,20 +533,14 @@ int default_chunk(const TeamHost& tm, int kind, int exhaustive)
     int cmax = (int)((kLdsBudget - 2 * 1024) / per_t);
     cmax = std::min(cmax, kMaxChunk);
     if (cmax < 1) cmax = 1;
-    // early-terminating calls: long tiles, since most queries end in their first
-    // tiles, whose fixed cost then dominates -- FFC as many timesteps as fit, up to
-    // 32 (one 8-wave workgroup per CU; the arm+rectangle team: 24, 20.1 ms against
-    // 26.5 ms at 16); MV the most that
-    // keep two workgroups per CU if that is at least 12 (at most 16), else 16 (as
-    // many as fit); exhaustive calls: up to 8, the largest that keeps as many
-    // workgroups per CU as registers allow (six for MV, five for FFC) within the
-    // CU's 160 KiB of LDS if that is at least 2, else one workgroup fewer, ...
-    if (!exhaustive) {
-        int c = kind == 1 ? std::min(cmax, 32) : 16;
-        const int c2 = (int)((160 * 1024 / 2 - 1024) / per_t);
-        if (kind == 0 && c2 >= 12) c = std::min(16, c2);
-        return std::max(1, std::min(cmax, c));
-    }
+    // early-terminating calls: as many timesteps as fit, up to 32, since most
+    // queries end in their first tiles, whose fixed cost then dominates; one 8-wave
+    // workgroup per CU runs them (FFC on the arm+rectangle team: 24 timesteps,
+    // 20.1 ms against 26.5 ms at 16).  Exhaustive calls: up to 8, the largest that
+    // keeps as many workgroups per CU as registers allow (six for MV, five for FFC)
+    // within the CU's 160 KiB of LDS if that is at least 2, else one workgroup
+    // fewer, ...
+    if (!exhaustive) return std::max(1, std::min(cmax, 32));
     for (int wgs = kind == 0 ? kExhWGsPerCU : kWGsPerCU; wgs >= 1; --wgs) {
         const int c = (int)((160 * 1024 / wgs - 1024) / per_t);
         if (c >= 2 || wgs == 1) return std::max(1, std::min(cmax, std::min(8, c)));

@@ -11,10 +11,10 @@ constexpr int kWG = 256;            // threads per workgroup (4 waves of 64)
 constexpr int kWave = 64;
 constexpr int kWavesPerWG = kWG / kWave;
 // Threads per workgroup of a validation kernel variant (0 early-terminating MV,
-// 1 early-terminating FFC, 2 MV with a focus set, 3 exhaustive MV, 4 exhaustive
-// FFC): early-terminating FFC's long tiles leave room for one workgroup per CU,
-// which then runs 8 waves.
-constexpr int validate_wg(int variant) { return variant == 1 ? 512 : kWG; }
+// 1 early-terminating FFC, 2 early-terminating MV with a focus set, 3 exhaustive
+// MV, 4 exhaustive FFC, 5 exhaustive MV with a focus set): early-terminating
+// calls' long tiles leave room for one workgroup per CU, which then runs 8 waves.
+constexpr int validate_wg(int variant) { return variant <= 2 ? 512 : kWG; }
 constexpr int kMaxRobots = 32;
 constexpr int kMaxJoints = 8;
 constexpr int kMaxChunk = 64;       // timesteps per tile
@@ -153,13 +153,13 @@ hipError_t launch_spheres(const CallDev& cd, const int* st_q, const int* st_t, i
 // Occupancy-derived workgroups per CU for the validation kernel.
 // Whether an MV call restricts validation to a focus set (runs the focus kernel).
 inline bool has_focus(const CallDev& cd) { return cd.kind == 0 && (cd.focus0 != 0u || cd.q_focus != nullptr); }
-// Validation kernel of a call: 0 early-terminating MV, 1 early-terminating FFC,
-// 2 MV with a focus set, 3 exhaustive MV, 4 exhaustive FFC.
+// Validation kernel of a call (variants as for validate_wg).
 inline int validate_variant(const CallDev& cd)
 {
-    if (cd.kind == 1) return (cd.flags & MRV_EXHAUSTIVE) ? 4 : 1;
-    if (has_focus(cd)) return 2;
-    return (cd.flags & MRV_EXHAUSTIVE) ? 3 : 0;
+    const bool exh = (cd.flags & MRV_EXHAUSTIVE) != 0;
+    if (cd.kind == 1) return exh ? 4 : 1;
+    if (has_focus(cd)) return exh ? 5 : 2;
+    return exh ? 3 : 0;
 }
 int validate_blocks_per_cu(int variant, size_t lds_bytes);
 

@@ -785,13 +785,13 @@ __device__ __forceinline__ void env_tasks(const CallDev& cd, const TeamDev& tm, 
 }
 
 template <int KIND>
-__global__ __launch_bounds__(validate_wg(KIND), KIND == 1 ? 2 : (KIND == 3 ? kExhWGsPerCU : kWGsPerCU)) void k_validate(CallDev cd)
+__global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kExhWGsPerCU : kWGsPerCU)) void k_validate(CallDev cd)
 {
-    // KIND: 0 early-terminating MV, 1 early-terminating FFC, 2 MV with a focus set
-    // (prioritised MV), 3 exhaustive MV, 4 exhaustive FFC; the exhaustive mode is a
-    // compile-time constant except for 2
+    // KIND: 0 early-terminating MV, 1 early-terminating FFC, 2 early-terminating MV
+    // with a focus set (prioritised MV), 3 exhaustive MV, 4 exhaustive FFC, 5
+    // exhaustive MV with a focus set
     constexpr bool kMV = KIND != 1 && KIND != 4;
-    constexpr bool kFocus = KIND == 2;
+    constexpr bool kFocus = KIND == 2 || KIND == 5;
     constexpr int WG = validate_wg(KIND);
     constexpr int kWaves = WG / kWave;
     extern __shared__ float4 dyn[];
@@ -810,7 +810,7 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND == 1 ? 2 : (KIND == 3 ? kEx
     const int lane = tid & 63;
     const int wave = wave_uniform(tid >> 6);
     const unsigned flags = cd.flags;
-    const bool exhaustive = KIND == 3 || KIND == 4 || (KIND == 2 && (flags & MRV_EXHAUSTIVE) != 0);
+    const bool exhaustive = KIND >= 3;
     const bool check_env = kMV && (flags & MRV_CHECK_ENV) != 0;
     const bool hier = check_env && (flags & MRV_HIERARCHICAL) != 0;
     const float eps = cd.eps32;
@@ -1297,6 +1297,9 @@ hipError_t launch_validate(const CallDev& cd, int grid, hipStream_t stream)
         if (e == hipSuccess)
             e = hipFuncSetAttribute((const void*)k_validate<4>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     kLdsBudget - 1024);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)k_validate<5>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    kLdsBudget - 1024);
         return e;
     }();
     if (lds_opt != hipSuccess && cd.lds_bytes > 64 * 1024) return lds_opt;
@@ -1305,6 +1308,7 @@ hipError_t launch_validate(const CallDev& cd, int grid, hipStream_t stream)
     case 2: hipLaunchKernelGGL(k_validate<2>, dim3(grid), dim3(validate_wg(2)), (size_t)cd.lds_bytes, stream, cd); break;
     case 3: hipLaunchKernelGGL(k_validate<3>, dim3(grid), dim3(validate_wg(3)), (size_t)cd.lds_bytes, stream, cd); break;
     case 4: hipLaunchKernelGGL(k_validate<4>, dim3(grid), dim3(validate_wg(4)), (size_t)cd.lds_bytes, stream, cd); break;
+    case 5: hipLaunchKernelGGL(k_validate<5>, dim3(grid), dim3(validate_wg(5)), (size_t)cd.lds_bytes, stream, cd); break;
     default: hipLaunchKernelGGL(k_validate<0>, dim3(grid), dim3(validate_wg(0)), (size_t)cd.lds_bytes, stream, cd); break;
     }
     return hipGetLastError();
@@ -1335,6 +1339,7 @@ int validate_blocks_per_cu(int kind, size_t lds_bytes)
                  : kind == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_validate<2>, validate_wg(2), lds_bytes)
                  : kind == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_validate<3>, validate_wg(3), lds_bytes)
                  : kind == 4 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_validate<4>, validate_wg(4), lds_bytes)
+                 : kind == 5 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_validate<5>, validate_wg(5), lds_bytes)
                              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_validate<0>, validate_wg(0), lds_bytes);
     if (e != hipSuccess || nb < 1) nb = 1;
     return nb;
