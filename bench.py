@@ -54,22 +54,22 @@ def profiled_traffic():
     return float(vals["traffic_bytes_per_launch"])
 
 
-def per_timestep_flop(team, env, check_env=True):
-    """Algorithmic FLOP to validate one timestep of the whole team."""
+def executed_flop(team, env, stats):
+    """FLOP of one exhaustive MV launch from its executed-test counters: FK and
+    sphere placement of every robot-state, 10 per sphere-sphere test (robot-robot,
+    self, sphere obstacles), 26 per box or cylinder test actually run (the kernel
+    skips those whose world box misses a row of 16 spheres by more than the near
+    band; that skip is comparisons only and counts no FLOP)."""
     from paper_2604_23960_amd import workloads as W
-    ns = [r.n_spheres for r in team]
-    rr = sum(ns[i] * ns[j] for i in range(len(ns)) for j in range(i + 1, len(ns))) * FLOP_SPHERE_SPHERE
+    assert FLOP_SPHERE_BOX == FLOP_SPHERE_CYL        # one counter covers both
+    ts = stats["states_evaluated"] / len(team)
     fk = 0
     for r in team:
         fk += sum(FLOP_REV_JOINT if jt == W.REV_Z else FLOP_PRI_JOINT for jt in r.joint_type)
         fk += r.n_spheres * FLOP_SPHERE_PLACE
-    envf = 0
-    if check_env:
-        S = sum(ns)
-        envf = S * (len(env.boxes) * FLOP_SPHERE_BOX + len(env.cylinders) * FLOP_SPHERE_CYL +
-                    len(env.spheres) * FLOP_SPHERE_SPHERE)
-        envf += sum(len(r.self_pairs) for r in team) * FLOP_SPHERE_SPHERE
-    return rr + fk + envf
+    sph_tests = ts * sum(r.n_spheres for r in team) * len(env.spheres)
+    return (ts * fk + (stats["rr_tests"] + stats["self_tests"] + sph_tests) * FLOP_SPHERE_SPHERE +
+            (stats["env_tests"] - sph_tests) * FLOP_SPHERE_BOX)
 
 
 def run_device(ctx, team, env, dp, kind, flags, out, steps, warmup, focus=0):
@@ -384,8 +384,7 @@ def main():
     value = states * args.steps / wall
     ms_per_step = wall / args.steps * 1e3
     kernel_ms = float(np.mean(kms))
-    ts = states / len(w.team)
-    flop = ts * per_timestep_flop(w.team, w.env, True)
+    flop = executed_flop(w.team, w.env, st)
     achieved = flop / (kernel_ms * 1e-3)
     roofline = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_FP32_VALU / 1e12, unit="TFLOP/s",
                     frac=achieved / PEAK_FP32_VALU, traffic=profiled_traffic(), kernel="k_validate<3> (exhaustive MV)",

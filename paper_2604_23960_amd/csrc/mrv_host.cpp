@@ -392,6 +392,38 @@ void build_env(const mrv_env_desc* e, EnvHost& out)
         if (y[6] < 0 || y[7] < 0) throw Err{MRV_E_INVALID, "negative cylinder size"};
         for (int k = 0; k < 8; ++k) cyl32.push_back((float)y[k]);
     }
+    // world-axis box of each box, then of each cylinder, in FP64, padded and rounded
+    // outward to FP32: the kernel skips an obstacle whose box misses every sphere of
+    // a slot row by more than the near band
+    std::vector<float> bc_box;
+    auto push_box = [&](const double* c, const double* ext) {
+        float lo[4] = {0, 0, 0, 0}, hi[4] = {0, 0, 0, 0};
+        for (int k = 0; k < 3; ++k) {
+            const double pad = 1e-7 * (1.0 + std::fabs(c[k]) + ext[k]);
+            const double l = c[k] - ext[k] - pad, h = c[k] + ext[k] + pad;
+            lo[k] = (float)l;
+            if ((double)lo[k] > l) lo[k] = std::nextafter(lo[k], -HUGE_VALF);
+            hi[k] = (float)h;
+            if ((double)hi[k] < h) hi[k] = std::nextafter(hi[k], HUGE_VALF);
+        }
+        bc_box.insert(bc_box.end(), lo, lo + 4);
+        bc_box.insert(bc_box.end(), hi, hi + 4);
+    };
+    for (int i = 0; i < e->n_boxes; ++i) {
+        const double* b = e->boxes + i * 15;
+        const double* R = b + 3;
+        double ext[3];
+        for (int k = 0; k < 3; ++k)
+            ext[k] = std::fabs(R[k * 3 + 0]) * b[12] + std::fabs(R[k * 3 + 1]) * b[13] + std::fabs(R[k * 3 + 2]) * b[14];
+        push_box(b, ext);
+    }
+    for (int i = 0; i < e->n_cyls; ++i) {
+        const double* y = e->cylinders + i * 8;
+        double ext[3];
+        for (int k = 0; k < 3; ++k)
+            ext[k] = std::fabs(y[3 + k]) * y[6] + y[7] * std::sqrt(std::max(0.0, 1.0 - y[3 + k] * y[3 + k]));
+        push_box(y, ext);
+    }
     // point cloud: uniform grid, points sorted by cell (x fastest)
     std::vector<float> pts32;
     std::vector<double> pts64;
@@ -446,7 +478,7 @@ void build_env(const mrv_env_desc* e, EnvHost& out)
     Packer pk;
     size_t o_s32 = pk.add(sph32), o_s64 = pk.add(sph64), o_b32 = pk.add(box32), o_b64 = pk.add(box64),
            o_c32 = pk.add(cyl32), o_c64 = pk.add(cyl64), o_p32 = pk.add(pts32), o_p64 = pk.add(pts64),
-           o_cs = pk.add(cell_start);
+           o_cs = pk.add(cell_start), o_bc = pk.add(bc_box);
     const EnvDev blank{};
     const size_t o_self = pk.add(&blank, sizeof(EnvDev));
     void* d = nullptr;
@@ -466,6 +498,7 @@ void build_env(const mrv_env_desc* e, EnvHost& out)
     v.pts32 = (const float4*)at(o_p32);
     v.pts64 = (const double*)at(o_p64);
     v.cell_start = (const int*)at(o_cs);
+    v.bc_box = (const float4*)at(o_bc);
     for (int k = 0; k < 3; ++k) {
         v.grid_lo[k] = grid_lo[k];
         v.grid_dim[k] = dims[k];

@@ -20,7 +20,7 @@ constexpr int kMaxJoints = 8;
 constexpr int kMaxChunk = 64;       // timesteps per tile
 constexpr int kLdsBudget = 160 * 1024;   // LDS one workgroup may use on gfx950
 constexpr int kWGsPerCU = 5;        // validation workgroups per CU the register budget allows
-constexpr int kExhWGsPerCU = 6;     // the same for the exhaustive MV kernel (80 VGPRs)
+constexpr int kExhWGsPerCU = 7;     // the same for the exhaustive MV kernel (72 VGPRs)
 
 enum RecheckKind : int { RK_RR = 0, RK_SELF = 1, RK_ENV_SPH = 2, RK_ENV_BOX = 3, RK_ENV_CYL = 4, RK_ENV_PT = 5 };
 
@@ -83,6 +83,7 @@ struct EnvDev {
     const double* box64;        // [n][15] as given
     const float* cyl32;         // [n][8] centre(3), axis(3), half-length, radius
     const double* cyl64;        // [n][8]
+    const float4* bc_box;       // [n_box + n_cyl][2] world-axis box (lo, hi) of each box, then each cylinder
     // uniform grid over the point cloud (CSR by cell)
     const float4* pts32;        // [n_pts] points sorted by cell (x, y, z, 0)
     const double* pts64;        // [n_pts][3] in the same order

@@ -487,8 +487,6 @@ __device__ __forceinline__ float lane_select(unsigned long long m, float on, flo
     return __builtin_amdgcn_inverse_ballot_w64(m) ? on : off;
 }
 
-// min(best, min_r d[r] + wb) for one MFMA result: adding w_b first makes the
-// operands of the minimum results of arithmetic, which need no NaN quieting
 // Smallest D in a lane's share of a block: its four rows share the column b, so
 // w_b is added once, after the minimum (rounding to nearest is monotonic, so this
 // equals the minimum of the four sums).
@@ -507,6 +505,35 @@ __device__ __forceinline__ float wave_max_f32(float v)
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
     return v;
+}
+
+// Minimum and maximum over each row of 16 lanes, in every lane of the row: lanes
+// exchanged within quads, then rows rotated by 4 and 8 (DPP; all lanes active).
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
+__device__ __forceinline__ float row_min16(float v)
+{
+    v = fminf(v, dpp_f32<0xB1>(v));         // quad_perm [1, 0, 3, 2]
+    v = fminf(v, dpp_f32<0x4E>(v));         // quad_perm [2, 3, 0, 1]
+    v = fminf(v, dpp_f32<0x124>(v));        // row_ror 4
+    return fminf(v, dpp_f32<0x128>(v));     // row_ror 8
+}
+
+__device__ __forceinline__ float row_max16(float v)
+{
+    v = fmaxf(v, dpp_f32<0xB1>(v));
+    v = fmaxf(v, dpp_f32<0x4E>(v));
+    v = fmaxf(v, dpp_f32<0x124>(v));
+    return fmaxf(v, dpp_f32<0x128>(v));
+}
+
+__device__ __forceinline__ float lane_value(float v, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
 // Squared distance from x to a box surface region (0 inside), box in the
@@ -658,9 +685,11 @@ __device__ __forceinline__ float4 place32(const float4* Fp, float4 L)
 }
 
 // Robot-obstacle tests of J (timestep, 64-slot chunk) tasks of one wave, one lane
-// per slot: each obstacle's parameters are loaded once (wave-uniform scalar loads)
-// and applied to all J tasks.  Sets *s_hit on a confirmed hit; near tests below
-// the known outcome are queued for FP64 re-evaluation.
+// per slot, obstacle parameters in wave-uniform scalar loads (each sphere
+// obstacle's loaded once for all J tasks).  Sets *s_hit on a confirmed hit; near
+// tests below the known outcome are queued for FP64 re-evaluation.  The kernel
+// passes one task at a time: with boxes and cylinders selected per task, larger
+// J only adds register pressure.
 template <int J>
 __device__ __forceinline__ void env_tasks(const CallDev& cd, const TeamDev& tm, const EnvDev& env, const float* sp,
                                           const int* task, int nch, float ro_max, float eps, bool exhaustive, int q,
@@ -688,17 +717,55 @@ __device__ __forceinline__ void env_tasks(const CallDev& cd, const TeamDev& tm, 
         mb[j] = 3.0e38f;
         ms[j] = 3.0e38f;
     }
-#pragma unroll 2
-    for (int o = 0; o < env.n_box; ++o) {
-        CFloat* B = (CFloat*)(env.box32 + o * 16);
+    // Boxes and cylinders, task by task, each only where its world-axis box meets
+    // the box of one of the task's four rows of 16 slots, the spheres widened by
+    // 2 eps: every other test lies beyond the near band (the FP32 centres are far
+    // closer than eps to the FP64 ones) and so is clear in FP64 as well.
+    const int nbc = env.n_box + env.n_cyl;
+    unsigned n_tested[J];
 #pragma unroll
-        for (int j = 0; j < J; ++j) mb[j] = fminf(mb[j], box_val(x[j], y[j], z[j], B));
-    }
-#pragma unroll 2
-    for (int o = 0; o < env.n_cyl; ++o) {
-        CFloat* Y = (CFloat*)(env.cyl32 + o * 8);
+    for (int j = 0; j < J; ++j) {
+        n_tested[j] = (unsigned)env.n_sph;
+        if (nbc == 0) continue;
+        const float w = rad[j] + 2.f * eps;
+        const float lx = row_min16(act[j] ? x[j] - w : 3.0e38f), hx = row_max16(act[j] ? x[j] + w : -3.0e38f);
+        const float ly = row_min16(act[j] ? y[j] - w : 3.0e38f), hy = row_max16(act[j] ? y[j] + w : -3.0e38f);
+        const float lz = row_min16(act[j] ? z[j] - w : 3.0e38f), hz = row_max16(act[j] ? z[j] + w : -3.0e38f);
+        float rb[4][6];                     // per row: low x, y, z, high x, y, z (wave-uniform)
 #pragma unroll
-        for (int j = 0; j < J; ++j) mb[j] = fminf(mb[j], cyl_val(x[j], y[j], z[j], Y));
+        for (int r = 0; r < 4; ++r) {
+            rb[r][0] = lane_value(lx, 16 * r);
+            rb[r][1] = lane_value(ly, 16 * r);
+            rb[r][2] = lane_value(lz, 16 * r);
+            rb[r][3] = lane_value(hx, 16 * r);
+            rb[r][4] = lane_value(hy, 16 * r);
+            rb[r][5] = lane_value(hz, 16 * r);
+        }
+        for (int ob = 0; ob < nbc; ob += kWave) {
+            const int o = ob + lane;
+            float4 olo = make_float4(3.0e38f, 3.0e38f, 3.0e38f, 0.f), ohi = make_float4(-3.0e38f, -3.0e38f, -3.0e38f, 0.f);
+            if (o < nbc) {
+                olo = env.bc_box[2 * o];
+                ohi = env.bc_box[2 * o + 1];
+            }
+            bool meet = false;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                meet |= (olo.x <= rb[r][3]) & (ohi.x >= rb[r][0]) & (olo.y <= rb[r][4]) & (ohi.y >= rb[r][1]) &
+                        (olo.z <= rb[r][5]) & (ohi.z >= rb[r][2]);
+            const unsigned long long m = __ballot(meet);
+            n_tested[j] += (unsigned)__popcll(m);
+            const int nb = min(max(env.n_box - ob, 0), kWave);
+            const unsigned long long low = nb >= kWave ? ~0ull : (1ull << nb) - 1ull;
+            for (unsigned long long mm = m & low; mm; mm &= mm - 1ull) {
+                const int b = ob + __builtin_ctzll(mm);
+                mb[j] = fminf(mb[j], box_val(x[j], y[j], z[j], (CFloat*)(env.box32 + b * 16)));
+            }
+            for (unsigned long long mm = m & ~low; mm; mm &= mm - 1ull) {
+                const int b = ob + __builtin_ctzll(mm) - env.n_box;
+                mb[j] = fminf(mb[j], cyl_val(x[j], y[j], z[j], (CFloat*)(env.cyl32 + b * 8)));
+            }
+        }
     }
     for (int o = 0; o < env.n_sph; ++o) {
         const float* ob = &env.sph32[o].x;
@@ -713,7 +780,7 @@ __device__ __forceinline__ void env_tasks(const CallDev& cd, const TeamDev& tm, 
     bool any_hit = false;
 #pragma unroll
     for (int j = 0; j < J; ++j) {
-        if (act[j]) c_env += (unsigned long long)(env.n_sph + env.n_box + env.n_cyl);
+        if (act[j]) c_env += (unsigned long long)n_tested[j];
         const float rlo = fmaxf(rad[j] - eps, 0.f), rhi = rad[j] + eps;
         const float Rb = rad[j] + ro_max;
         bool hit = false, unsure = false;
@@ -1012,25 +1079,9 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
                 const int ntask = nv * nch;
                 float ro_max = 0.f;
                 for (int o = 0; o < env.n_sph; ++o) ro_max = fmaxf(ro_max, cloadf(&env.sph32[o].w));
-                // tasks wave, wave + 4, ... of this wave: exhaustive MV takes four (then
-                // two) at a time through each obstacle, exhaustive prioritised MV two;
-                // early-terminating calls one at a time, so a hit stops the wave before
-                // its next task
+                // tasks wave, wave + kWaves, ... of this wave, one at a time, so that in
+                // early-terminating calls a hit stops the wave before its next task
                 int task = wave;
-                if (exhaustive) {
-                    if constexpr (KIND == 3) {      // the focus kernel keeps its registers for the focus logic
-                        for (; task + 3 * kWaves < ntask; task += 4 * kWaves) {
-                            const int tk[4] = { task, task + kWaves, task + 2 * kWaves, task + 3 * kWaves };
-                            env_tasks<4>(cd, tm, env, sp, tk, nch, ro_max, eps, exhaustive, q, focus, fall, s_t, &s_hit,
-                                         c_env, lane);
-                        }
-                    }
-                    for (; task + kWaves < ntask; task += 2 * kWaves) {
-                        const int tk[2] = { task, task + kWaves };
-                        env_tasks<2>(cd, tm, env, sp, tk, nch, ro_max, eps, exhaustive, q, focus, fall, s_t, &s_hit, c_env,
-                                 lane);
-                    }
-                }
                 for (; task < ntask && !(!exhaustive && flag_read(&s_hit)); task += kWaves) {
                     const int tk[1] = { task };
                     env_tasks<1>(cd, tm, env, sp, tk, nch, ro_max, eps, exhaustive, q, focus, fall, s_t, &s_hit, c_env,
