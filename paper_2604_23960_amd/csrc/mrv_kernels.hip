@@ -531,11 +531,6 @@ __device__ __forceinline__ float row_max16(float v)
     return fmaxf(v, dpp_f32<0x128>(v));
 }
 
-__device__ __forceinline__ float lane_value(float v, int l)
-{
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-}
-
 // Squared distance from x to a box surface region (0 inside), box in the
 // precomputed row form of EnvDev::box32.
 __device__ __forceinline__ float box_val(float x, float y, float z, CFloat* B)
@@ -731,38 +726,27 @@ __device__ __forceinline__ void env_tasks(const CallDev& cd, const TeamDev& tm, 
         const float lx = row_min16(act[j] ? x[j] - w : 3.0e38f), hx = row_max16(act[j] ? x[j] + w : -3.0e38f);
         const float ly = row_min16(act[j] ? y[j] - w : 3.0e38f), hy = row_max16(act[j] ? y[j] + w : -3.0e38f);
         const float lz = row_min16(act[j] ? z[j] - w : 3.0e38f), hz = row_max16(act[j] ? z[j] + w : -3.0e38f);
-        float rb[4][6];                     // per row: low x, y, z, high x, y, z (wave-uniform)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            rb[r][0] = lane_value(lx, 16 * r);
-            rb[r][1] = lane_value(ly, 16 * r);
-            rb[r][2] = lane_value(lz, 16 * r);
-            rb[r][3] = lane_value(hx, 16 * r);
-            rb[r][4] = lane_value(hy, 16 * r);
-            rb[r][5] = lane_value(hz, 16 * r);
-        }
-        for (int ob = 0; ob < nbc; ob += kWave) {
-            const int o = ob + lane;
+        // lane l compares the box of its own row with obstacle ob + l % 16, so a
+        // ballot covers 16 obstacles against all four rows
+        for (int ob = 0; ob < nbc; ob += 16) {
+            const int o = ob + (lane & 15);
             float4 olo = make_float4(3.0e38f, 3.0e38f, 3.0e38f, 0.f), ohi = make_float4(-3.0e38f, -3.0e38f, -3.0e38f, 0.f);
             if (o < nbc) {
                 olo = env.bc_box[2 * o];
                 ohi = env.bc_box[2 * o + 1];
             }
-            bool meet = false;
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                meet |= (olo.x <= rb[r][3]) & (ohi.x >= rb[r][0]) & (olo.y <= rb[r][4]) & (ohi.y >= rb[r][1]) &
-                        (olo.z <= rb[r][5]) & (ohi.z >= rb[r][2]);
-            const unsigned long long m = __ballot(meet);
-            n_tested[j] += (unsigned)__popcll(m);
-            const int nb = min(max(env.n_box - ob, 0), kWave);
-            const unsigned long long low = nb >= kWave ? ~0ull : (1ull << nb) - 1ull;
-            for (unsigned long long mm = m & low; mm; mm &= mm - 1ull) {
-                const int b = ob + __builtin_ctzll(mm);
+            const unsigned long long m4 = __ballot((olo.x <= hx) & (ohi.x >= lx) & (olo.y <= hy) & (ohi.y >= ly) &
+                                                   (olo.z <= hz) & (ohi.z >= lz));
+            const unsigned m = (unsigned)((m4 | (m4 >> 16) | (m4 >> 32) | (m4 >> 48)) & 0xFFFFull);
+            n_tested[j] += (unsigned)__popc(m);
+            const int nb = min(max(env.n_box - ob, 0), 16);
+            const unsigned low = (1u << nb) - 1u;
+            for (unsigned mm = m & low; mm; mm &= mm - 1u) {
+                const int b = ob + __builtin_ctz(mm);
                 mb[j] = fminf(mb[j], box_val(x[j], y[j], z[j], (CFloat*)(env.box32 + b * 16)));
             }
-            for (unsigned long long mm = m & ~low; mm; mm &= mm - 1ull) {
-                const int b = ob + __builtin_ctzll(mm) - env.n_box;
+            for (unsigned mm = m & ~low; mm; mm &= mm - 1u) {
+                const int b = ob + __builtin_ctz(mm) - env.n_box;
                 mb[j] = fminf(mb[j], cyl_val(x[j], y[j], z[j], (CFloat*)(env.cyl32 + b * 8)));
             }
         }
