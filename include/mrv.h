@@ -275,7 +275,8 @@ typedef struct {
     uint64_t tiles_run, tiles_skipped;
     uint64_t states_evaluated;   /* robot-states run through FK and tests */
     uint64_t states_covered;     /* sum over queries of n_robots * T */
-    uint64_t rr_tests, env_tests, self_tests;
+    uint64_t rr_tests, env_tests, self_tests;   /* sphere tests executed (obstacle tests skipped by the
+                                                   bounding-box cull are not counted) */
     uint64_t near_rechecks;      /* tests re-evaluated in FP64 */
     double kernel_ms;            /* validation kernel time of the last call (device events) */
 } mrv_stats;
