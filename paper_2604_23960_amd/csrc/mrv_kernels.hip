@@ -853,7 +853,7 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
     __shared__ unsigned long long s_tp, s_ep;
     __shared__ unsigned s_focus;
     // thread 0's claim state and tile counts, kept in LDS rather than registers
-    __shared__ long long s_kcur;
+    __shared__ long long s_kcur, s_off0, s_off1;   // current rank and its tile range [off[k], off[k + 1])
     __shared__ int s_phase_cur;
     __shared__ unsigned long long s_nrun, s_nskip, s_nstates;
 
@@ -875,6 +875,8 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
     unsigned long long c_rr = 0, c_env = 0, c_self = 0;                 // wave-uniform counters
     if (tid == 0) {
         s_kcur = 0;
+        s_off0 = 0;
+        s_off1 = -1;                    // no rank range cached yet
         s_phase_cur = 0;
         s_nrun = 0;
         s_nskip = 0;
@@ -907,28 +909,36 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
                 if (hier) {
                     phase = g >= total ? 1 : 0;
                     gg = g - (long long)phase * total;
-                    if (phase != s_phase_cur) { s_phase_cur = phase; s_kcur = 0; }
+                    if (phase != s_phase_cur) { s_phase_cur = phase; s_kcur = 0; s_off1 = -1; }
                 }
-                // largest rank k with off[k] <= gg (ranks are non-empty below M; off[M] = total)
-                long long lo = s_kcur;
-                if (off[lo + 1] <= gg) {
-                    long long step = 1, hi;
-                    lo = lo + 1;
-                    for (;;) {
-                        hi = lo + step;
-                        if (hi >= M || off[hi] > gg) break;
-                        lo = hi;
-                        step <<= 1;
+                // largest rank k with off[k] <= gg (ranks are non-empty below M; off[M] =
+                // total).  A workgroup's tile numbers only grow within a phase, so most
+                // claims fall in the cached range of the previous rank and load nothing.
+                long long lo = s_kcur, o0 = s_off0, o1 = s_off1;
+                if (!(gg < o1)) {
+                    if (off[lo + 1] <= gg) {
+                        long long step = 1, hi;
+                        lo = lo + 1;
+                        for (;;) {
+                            hi = lo + step;
+                            if (hi >= M || off[hi] > gg) break;
+                            lo = hi;
+                            step <<= 1;
+                        }
+                        if (hi > M) hi = M;
+                        while (hi - lo > 1) {
+                            long long mid = (lo + hi) >> 1;
+                            if (off[mid] <= gg) lo = mid; else hi = mid;
+                        }
                     }
-                    if (hi > M) hi = M;
-                    while (hi - lo > 1) {
-                        long long mid = (lo + hi) >> 1;
-                        if (off[mid] <= gg) lo = mid; else hi = mid;
-                    }
+                    o0 = off[lo];
+                    o1 = off[lo + 1];
+                    s_kcur = lo;
+                    s_off0 = o0;
+                    s_off1 = o1;
                 }
-                s_kcur = lo;
                 const int k = (int)lo;
-                q = cd.sorted_q[gg - off[lo]];
+                q = cd.sorted_q[gg - o0];
                 if (kFocus) focus = cd.q_focus ? cd.q_focus[q] : cd.focus0;
                 const TeamDev* tq = team_of(cd, q);
                 const EnvDev* eq = env_of(cd, q);
