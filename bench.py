@@ -423,6 +423,9 @@ def main():
         extra["serving"] = serving_bench(log)
         log("16-robot point-cloud workload")
         extra["cloud"] = cloud_bench(log)
+        log("Composite RRT-Connect with served edge checks")
+        from paper_2604_23960_amd import planner
+        extra["planner"] = planner.plan_study(ctx)
     cpu = None
     if not args.no_cpu:
         log("timing the FP64 oracle on the host")
