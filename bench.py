@@ -24,7 +24,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# FLOP per unit of work ("Roofline and FLOP convention").
+# FLOP per unit of work: add, subtract and multiply count 1, a fused multiply-add 2;
+# comparisons, minima and selects count none.
 FLOP_SPHERE_SPHERE = 10     # 3 sub, |d|^2 5, (ra+rb)^2 2
 FLOP_SPHERE_BOX = 26
 FLOP_SPHERE_CYL = 26

@@ -20,7 +20,7 @@ ARCH = "gfx950"
 
 def _common() -> list[str]:
     return [HIPCC, f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
-            # packed FP32 instructions are left to nobody: see the build notes in the design doc
+            # no packed FP32 instructions in any kernel
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-Wno-unused-command-line-argument", "-I", os.path.join(ROOT, "include")]
 
