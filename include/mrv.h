@@ -17,8 +17,15 @@
  *
  * A pair of spheres collides iff its signed clearance is < 0 (touching is
  * free).  Arithmetic is FP32 with an FP64 re-evaluation of every test whose FP32
- * clearance lies within `near_eps` metres of zero, so the booleans and
- * (t, i, j) equal those of an FP64 evaluation.
+ * clearance lies within a near band of zero, so the booleans and (t, i, j)
+ * equal those of an FP64 evaluation.  FP32 coordinates are formed relative to
+ * the team's origin (the centre of its bases' bounding box) and the
+ * environment's (the centre of its obstacles' bounding box), each subtracted in
+ * FP64, so where the cell sits in the world costs no precision.  The band is
+ * `near_eps` for a query whose relative coordinates stay within 4 m (every
+ * frame and sphere of the team, prismatic joint values included, and every
+ * obstacle part); beyond that it widens in proportion to the largest such
+ * magnitude, as FP32 rounding does.
  *
  * Conventions for every entry point:
  *  - Return value: MRV_OK (0) or a negative mrv_status.  On error nothing is
@@ -73,9 +80,21 @@ typedef struct mrv_ctx_s* mrv_ctx;
 typedef struct {
     int32_t device;        /* HIP device ordinal */
     void* stream;          /* hipStream_t to order all work on; NULL = the library creates one */
-    double near_eps;       /* near-contact band in metres; <= 0 selects 1e-5 */
+    void* device_arena;    /* caller-owned device memory of `device` (e.g. a torch uint8 tensor) from
+                            * which every device buffer of the context is sub-allocated: resident teams
+                            * and environments, per-call scratch, the near-contact queue, captured
+                            * graphs and the serving loop's batches.  The library then never calls
+                            * hipMalloc; a call whose memory does not fit fails with MRV_E_NOMEM and
+                            * leaves its outputs untouched, and served requests wait until running
+                            * batches give memory back.  The arena must outlive the context.  NULL:
+                            * the library allocates with hipMalloc as needed. */
+    size_t arena_bytes;    /* size of device_arena (0 iff device_arena is NULL) */
+    double near_eps;       /* near-contact band in metres (widened per query for large relative
+                            * coordinates, see above); <= 0 selects 1e-5; must be < 0.01 */
     int32_t max_inflight;  /* serving: queue capacity in requests; <= 0 selects 1024 */
-    size_t serve_bytes;    /* serving: device bytes for admitted requests; 0 selects 256 MiB */
+    size_t serve_bytes;    /* serving: the most device bytes the batches in flight may hold at once
+                            * (inputs, outputs and scratch as allocated); 0 = no limit besides the
+                            * arena (with an arena) or 1 GiB (without one) */
     int64_t recheck_records; /* initial length of the near-contact re-evaluation queue in
                               * 16-byte records; <= 0 selects 2^21.  Calls that overflow it
                               * enlarge it, up to 2^27 (see mrv_mv, mrv_sync). */
@@ -90,6 +109,11 @@ mrv_status mrv_destroy(mrv_ctx ctx);
 /* Message for the last failing call on this thread ("" if none).  Valid until the
  * next call on this thread. */
 const char* mrv_last_error(void);
+
+/* Device memory of the context in bytes: now allocated, the most ever allocated
+ * at once, and the arena's usable size (0 without an arena).  Any pointer may be
+ * NULL. */
+mrv_status mrv_memory_stats(mrv_ctx ctx, size_t* used, size_t* peak, size_t* capacity);
 
 /* ---------------------------------------------------------------- robots */
 enum { MRV_REV_Z = 0, MRV_PRI_X = 1, MRV_PRI_Y = 2, MRV_PRI_Z = 3 };
@@ -218,7 +242,8 @@ mrv_status mrv_sync(mrv_ctx ctx);
 
 /* FP32 world-frame sphere centres of the team at n_states (query, timestep)
  * pairs of host paths, as the validation kernels compute them (paper §III-A,
- * SpheresFK): out[k][s] = (x, y, z, radius) for sphere s of the flattened team
+ * SpheresFK), i.e. relative to the team origin, plus the origin added in FP32:
+ * out[k][s] = (x, y, z, radius) for sphere s of the flattened team
  * (robots in order), k < n_states; out holds n_states * S * 4 floats, S = the
  * team's total sphere count.  state_query[k] must index a query of paths and
  * state_t[k] >= 0 (timesteps past a path's end give its last configuration). */
@@ -238,7 +263,9 @@ typedef struct {
 /* Set the tiling used for (team, kind), kind 0 = MV, 1 = FFC, by the calls whose
  * MRV_EXHAUSTIVE flag equals that of flags (other flag bits are ignored): calls
  * that run every test favour tiles sized for occupancy, early-terminating calls
- * longer tiles with less fixed cost per tile, so each mode keeps its own. */
+ * longer tiles with less fixed cost per tile, so each mode keeps its own.
+ * Waits for the work queued on the context stream.  MRV_E_BUSY while a served
+ * request or a captured graph uses the team. */
 mrv_status mrv_set_tiling(mrv_ctx ctx, int32_t team, int32_t kind, uint32_t flags, const mrv_tiling* tiling);
 mrv_status mrv_get_tiling(mrv_ctx ctx, int32_t team, int32_t kind, uint32_t flags, mrv_tiling* tiling);
 
@@ -250,7 +277,9 @@ mrv_status mrv_get_tiling(mrv_ctx ctx, int32_t team, int32_t kind, uint32_t flag
  * Results are cached per context by the team's shape (spheres, frames, groups,
  * robots), the environment's obstacle counts and the flags: a later call with
  * an equal key returns the cached tiling without timing.  The answers of MV/FFC
- * never depend on the tiling. */
+ * never depend on the tiling.  Trials run on a private copy of the team's
+ * descriptor; MRV_E_BUSY while a served request or a captured graph uses the
+ * team. */
 mrv_status mrv_autotune(mrv_ctx ctx, int32_t team, int32_t env, int32_t kind, const mrv_paths* sample,
                         uint32_t flags, mrv_tiling* best);
 

@@ -387,7 +387,7 @@ int orc_points_any_hit(const orc_env* E, const double* x, double r)
 /* Robot-obstacle and self collision of one robot state (spheres in world frame). */
 /* Robot r's self pairs and obstacles at one state.  all = 0 stops at the first
  * collision; all = 1 evaluates every relation (exhaustive validation, paper
- * Sec. V: every collision relation at every intermediate state). */
+ * Sec. IV-A: every collision relation at every intermediate state). */
 static int env_self_hit(const orc_team* tm, const orc_env* E, int r, const double* sph, int all)
 {
     int s0 = tm->sphere_off[r], ns = tm->sphere_off[r + 1] - s0;

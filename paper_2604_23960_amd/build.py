@@ -10,9 +10,9 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmrv.so")
 KERNELS = "mrv_kernels.hip"
-HOST_SOURCES = ["mrv_host.cpp", "mrv_serve.cpp"]
+HOST_SOURCES = ["mrv_host.cpp", "mrv_serve.cpp", "mrv_arena.cpp"]
 SOURCES = [KERNELS, *HOST_SOURCES]
-HEADERS = ["mrv_internal.hpp", "mrv_runtime.hpp"]
+HEADERS = ["mrv_internal.hpp", "mrv_runtime.hpp", "mrv_tiles.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

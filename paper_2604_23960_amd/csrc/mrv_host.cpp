@@ -71,6 +71,8 @@ size_t lds_per_t(const TeamHost& tm);
 int default_chunk(const TeamHost& tm, int kind, int exhaustive);
 inline int mode_of(uint32_t flags) { return (flags & MRV_EXHAUSTIVE) ? 1 : 0; }
 
+inline double sq(double v) { return v * v; }
+
 // Finite and within MRV_MAX_COORD (NaN fails the comparison).
 bool bounded_all(const double* p, size_t n)
 {
@@ -82,6 +84,7 @@ bool bounded_all(const double* p, size_t n)
 }  // namespace
 
 struct mrv_ctx_s {
+    DevAlloc alloc;         // every device buffer of the context (caller arena or hipMalloc)
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -94,12 +97,13 @@ struct mrv_ctx_s {
 
     Scratch sc;             // scratch of the synchronous and device-array calls
     DevBuf in_begin, in_t, in_q, out_buf;
+    DevBuf tune_desc;       // the autotuner's private team descriptor
 
     std::map<std::string, mrv_tiling> tune_cache;   // autotuned tilings by team/env shape
 
     std::unique_ptr<ServeLoop> serve;
     int max_inflight = 1024;
-    size_t serve_bytes = 256u << 20;
+    size_t serve_bytes = 0;
     size_t recheck_records = mrv::Scratch::kGlobalRecheckCap;
 };
 
@@ -161,7 +165,7 @@ int build_team(mrv_ctx ctx, const mrv_robot_desc* robots, int n, TeamHost& out)
         r_frame_off[r] = F;
         F += R.n_joints + 1;
         for (int i = 0; i < 12; ++i) {
-            base32[r * 12 + i] = (float)R.base[i];
+            base32[r * 12 + i] = (float)R.base[i];   // translations replaced below, relative to the origin
             base64[r * 12 + i] = R.base[i];
         }
         for (int j = 0; j < R.n_joints; ++j) {
@@ -264,6 +268,46 @@ int build_team(mrv_ctx ctx, const mrv_robot_desc* robots, int n, TeamHost& out)
         for (int j = i + 1; j < n; ++j)
             rr_per_t += (long long)(r_sphere_off[i + 1] - r_sphere_off[i]) * (r_sphere_off[j + 1] - r_sphere_off[j]);
 
+    // team origin o: the centre of the bases' bounding box, rounded to an FP32 value
+    // so that it is exact in both precisions.  The FP32 frames start from base
+    // translations relative to o (subtracted in FP64, rounded once), so no FP32
+    // value depends on where the team sits in the world.
+    float origin32[3];
+    double team_mag = 0.0;
+    std::vector<float> r_mag(n);
+    {
+        double lo[3] = { 1e300, 1e300, 1e300 }, hi[3] = { -1e300, -1e300, -1e300 };
+        for (int r = 0; r < n; ++r)
+            for (int d = 0; d < 3; ++d) {
+                lo[d] = std::min(lo[d], base64[r * 12 + 4 * d + 3]);
+                hi[d] = std::max(hi[d], base64[r * 12 + 4 * d + 3]);
+            }
+        double o[3];
+        for (int d = 0; d < 3; ++d) {
+            origin32[d] = (float)(0.5 * (lo[d] + hi[d]));
+            o[d] = (double)origin32[d];
+        }
+        for (int r = 0; r < n; ++r)
+            for (int d = 0; d < 3; ++d) base32[r * 12 + 4 * d + 3] = (float)(base64[r * 12 + 4 * d + 3] - o[d]);
+        // magnitude bound of the FP32 coordinates relative to o: base offset, joint
+        // translations and the farthest sphere centre plus radius, per robot
+        for (int r = 0; r < n; ++r) {
+            const double* b = base64.data() + r * 12;
+            double m = std::sqrt(sq(b[3] - o[0]) + sq(b[7] - o[1]) + sq(b[11] - o[2]));
+            for (int j = 0; j < r_nj[r]; ++j) {
+                const double* F = j64.data() + (size_t)(r_joint_off[r] + j) * 12;
+                m += std::sqrt(sq(F[3]) + sq(F[7]) + sq(F[11]));
+            }
+            double cmax = 0.0;
+            for (int s2 = r_sphere_off[r]; s2 < r_sphere_off[r + 1]; ++s2) {
+                const double* c = s_local64.data() + (size_t)s2 * 4;
+                cmax = std::max(cmax, std::sqrt(sq(c[0]) + sq(c[1]) + sq(c[2])) + c[3]);
+            }
+            r_mag[r] = (float)(m + cmax);
+            team_mag = std::max(team_mag, m + cmax);
+        }
+    }
+
     Packer pk;
     const size_t o_nj = pk.add(r_nj), o_jo = pk.add(r_joint_off), o_so = pk.add(r_sphere_off),
                  o_fo = pk.add(r_frame_off), o_b32 = pk.add(base32), o_b64 = pk.add(base64),
@@ -271,11 +315,11 @@ int build_team(mrv_ctx ctx, const mrv_robot_desc* robots, int n, TeamHost& out)
                  o_ss = pk.add(s_slot), o_sl = pk.add(s_lframe), o_l32 = pk.add(s_local32),
                  o_l64 = pk.add(s_local64), o_rt = pk.add(gtask), o_sg = pk.add(s_group),
                  o_gr = pk.add(g_range), o_rg = pk.add(r_group_off), o_ss2 = pk.add(slot_sphere),
-                 o_sb = pk.add(sblocks), o_sm = pk.add(sb_mask);
+                 o_sb = pk.add(sblocks), o_sm = pk.add(sb_mask), o_rm = pk.add(r_mag);
     const TeamDev blank{};
     const size_t o_self = pk.add(&blank, sizeof(TeamDev));
     void* d = nullptr;
-    if (hipMalloc(&d, pk.bytes.size()) != hipSuccess) throw Err{MRV_E_NOMEM, "team upload allocation failed"};
+    d = ctx->alloc.alloc(pk.bytes.size());
     auto at = [&](size_t o) { return (unsigned char*)d + o; };
     TeamDev& t = out.dev;
     t.n_robots = n;
@@ -290,16 +334,12 @@ int build_team(mrv_ctx ctx, const mrv_robot_desc* robots, int n, TeamHost& out)
     t.max_dof = max_dof;
     t.G = G;
     t.r_max = r_max;
-    {
-        float lo[3] = { 3e38f, 3e38f, 3e38f }, hi[3] = { -3e38f, -3e38f, -3e38f };
-        for (int r = 0; r < n; ++r)
-            for (int d = 0; d < 3; ++d) {
-                lo[d] = std::min(lo[d], base32[r * 12 + 4 * d + 3]);
-                hi[d] = std::max(hi[d], base32[r * 12 + 4 * d + 3]);
-            }
-        for (int d = 0; d < 3; ++d) t.origin[d] = 0.5f * (lo[d] + hi[d]);
-        t.origin[3] = 0.f;
+    for (int k = 0; k < 3; ++k) {
+        t.origin[k] = origin32[k];
+        t.origin64[k] = (double)origin32[k];
     }
+    t.origin[3] = 0.f;
+    t.mag = (float)team_mag;
     t.rr_tests_per_t = rr_per_t;
     t.s_group = (const int*)at(o_sg);
     t.g_range = (const int2*)at(o_gr);
@@ -308,6 +348,7 @@ int build_team(mrv_ctx ctx, const mrv_robot_desc* robots, int n, TeamHost& out)
     t.r_joint_off = (const int*)at(o_jo);
     t.r_sphere_off = (const int*)at(o_so);
     t.r_frame_off = (const int*)at(o_fo);
+    t.r_mag = (const float*)at(o_rm);
     t.r_base32 = (const float*)at(o_b32);
     t.r_base64 = (const double*)at(o_b64);
     t.j_type = (const int*)at(o_jt);
@@ -331,17 +372,16 @@ int build_team(mrv_ctx ctx, const mrv_robot_desc* robots, int n, TeamHost& out)
         for (int m = 0; m < 2; ++m) t.chunk[k][m] = default_chunk(out, k, m);
     std::memcpy(pk.bytes.data() + o_self, &t, sizeof(TeamDev));
     if (hipMemcpy(d, pk.bytes.data(), pk.bytes.size(), hipMemcpyHostToDevice) != hipSuccess) {
-        (void)hipFree(d);
+        ctx->alloc.free(d);
         throw Err{MRV_E_DEVICE, "team upload failed"};
     }
-    (void)ctx;
     return 0;
 }
 
 // ---------------------------------------------------------------------------
 // environments
 
-void build_env(const mrv_env_desc* e, EnvHost& out)
+void build_env(mrv_ctx ctx, const mrv_env_desc* e, EnvHost& out)
 {
     if (!e) throw Err{MRV_E_INVALID, "null environment"};
     if (e->n_spheres < 0 || e->n_boxes < 0 || e->n_cyls < 0 || e->n_points < 0)
@@ -354,10 +394,34 @@ void build_env(const mrv_env_desc* e, EnvHost& out)
     if (e->n_cyls && !bounded_all(e->cylinders, (size_t)e->n_cyls * 8)) throw Err{MRV_E_INVALID, "cylinder not finite or beyond MRV_MAX_COORD"};
     if (e->n_points && !bounded_all(e->points, (size_t)e->n_points * 3)) throw Err{MRV_E_INVALID, "point not finite or beyond MRV_MAX_COORD"};
     if (!bounded_all(&e->point_radius, 1) || e->point_radius < 0) throw Err{MRV_E_INVALID, "bad point radius"};
+    // Environment origin o: the centre of the bounding box of every obstacle centre
+    // and point, rounded to an FP32 value.  Every FP32 coordinate of the environment
+    // is taken relative to o in FP64 and rounded once.
+    double o[3] = { 0.0, 0.0, 0.0 };
+    {
+        double lo[3] = { 1e300, 1e300, 1e300 }, hi[3] = { -1e300, -1e300, -1e300 };
+        auto grow = [&](const double* c) {
+            for (int k = 0; k < 3; ++k) {
+                lo[k] = std::min(lo[k], c[k]);
+                hi[k] = std::max(hi[k], c[k]);
+            }
+        };
+        for (int i = 0; i < e->n_spheres; ++i) grow(e->spheres + i * 4);
+        for (int i = 0; i < e->n_boxes; ++i) grow(e->boxes + i * 15);
+        for (int i = 0; i < e->n_cyls; ++i) grow(e->cylinders + i * 8);
+        for (long long i = 0; i < e->n_points; ++i) grow(e->points + i * 3);
+        if (lo[0] <= hi[0])
+            for (int k = 0; k < 3; ++k) o[k] = (double)(float)(0.5 * (lo[k] + hi[k]));
+    }
+    double env_mag = 0.0;      // largest |coordinate relative to o| of any obstacle part
+    auto rel_norm = [&](const double* c) { return std::sqrt(sq(c[0] - o[0]) + sq(c[1] - o[1]) + sq(c[2] - o[2])); };
     std::vector<float> sph32;
     for (int i = 0; i < e->n_spheres; ++i) {
-        if (e->spheres[i * 4 + 3] < 0) throw Err{MRV_E_INVALID, "negative obstacle radius"};
-        for (int k = 0; k < 4; ++k) sph32.push_back((float)e->spheres[i * 4 + k]);
+        const double* c = e->spheres + i * 4;
+        if (c[3] < 0) throw Err{MRV_E_INVALID, "negative obstacle radius"};
+        for (int k = 0; k < 3; ++k) sph32.push_back((float)(c[k] - o[k]));
+        sph32.push_back((float)c[3]);
+        env_mag = std::max(env_mag, rel_norm(c) + c[3]);
     }
     std::vector<float> box32;
     for (int i = 0; i < e->n_boxes; ++i) {
@@ -370,14 +434,17 @@ void build_env(const mrv_env_desc* e, EnvHost& out)
                     throw Err{MRV_E_INVALID, "box rotation is not orthonormal"};
             }
         if (b[12] < 0 || b[13] < 0 || b[14] < 0) throw Err{MRV_E_INVALID, "negative box half-extent"};
-        // box frame coordinates p_k = (R^T)_k . x - (R^T c)_k: row k of R^T is column k of R
+        // box frame coordinates p_k = (R^T)_k . x - (R^T (c - o))_k for x relative to o:
+        // row k of R^T is column k of R
         float row[16];
+        const double cr[3] = { b[0] - o[0], b[1] - o[1], b[2] - o[2] };
         for (int k = 0; k < 3; ++k) {
             row[4 * k + 0] = (float)R[0 * 3 + k];
             row[4 * k + 1] = (float)R[1 * 3 + k];
             row[4 * k + 2] = (float)R[2 * 3 + k];
-            row[4 * k + 3] = (float)(-(R[0 * 3 + k] * b[0] + R[1 * 3 + k] * b[1] + R[2 * 3 + k] * b[2]));
+            row[4 * k + 3] = (float)(-(R[0 * 3 + k] * cr[0] + R[1 * 3 + k] * cr[1] + R[2 * 3 + k] * cr[2]));
         }
+        env_mag = std::max(env_mag, rel_norm(b) + std::sqrt(sq(b[12]) + sq(b[13]) + sq(b[14])));
         row[12] = (float)b[12];
         row[13] = (float)b[13];
         row[14] = (float)b[14];
@@ -390,7 +457,9 @@ void build_env(const mrv_env_desc* e, EnvHost& out)
         double nrm = y[3] * y[3] + y[4] * y[4] + y[5] * y[5];
         if (std::fabs(nrm - 1.0) > 1e-9) throw Err{MRV_E_INVALID, "cylinder axis is not a unit vector"};
         if (y[6] < 0 || y[7] < 0) throw Err{MRV_E_INVALID, "negative cylinder size"};
-        for (int k = 0; k < 8; ++k) cyl32.push_back((float)y[k]);
+        for (int k = 0; k < 3; ++k) cyl32.push_back((float)(y[k] - o[k]));
+        for (int k = 3; k < 8; ++k) cyl32.push_back((float)y[k]);
+        env_mag = std::max(env_mag, rel_norm(y) + y[6] + y[7]);
     }
     // world-axis box of each box, then of each cylinder, in FP64, padded and rounded
     // outward to FP32: the kernel skips an obstacle whose box misses every sphere of
@@ -399,8 +468,9 @@ void build_env(const mrv_env_desc* e, EnvHost& out)
     auto push_box = [&](const double* c, const double* ext) {
         float lo[4] = {0, 0, 0, 0}, hi[4] = {0, 0, 0, 0};
         for (int k = 0; k < 3; ++k) {
-            const double pad = 1e-7 * (1.0 + std::fabs(c[k]) + ext[k]);
-            const double l = c[k] - ext[k] - pad, h = c[k] + ext[k] + pad;
+            const double ck = c[k] - o[k];
+            const double pad = 1e-7 * (1.0 + std::fabs(ck) + ext[k]);
+            const double l = ck - ext[k] - pad, h = ck + ext[k] + pad;
             lo[k] = (float)l;
             if ((double)lo[k] > l) lo[k] = std::nextafter(lo[k], -HUGE_VALF);
             hi[k] = (float)h;
@@ -433,12 +503,15 @@ void build_env(const mrv_env_desc* e, EnvHost& out)
     double cell = e->grid_cell > 0 ? e->grid_cell : 0.05;
     if (e->n_points > 0) {
         if (e->n_points > (1ll << 30)) throw Err{MRV_E_INVALID, "too many points"};
+        // the grid in coordinates relative to o
         double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
-        for (long long i = 0; i < e->n_points; ++i)
+        for (long long i = 0; i < e->n_points; ++i) {
             for (int d = 0; d < 3; ++d) {
-                lo[d] = std::min(lo[d], e->points[i * 3 + d]);
-                hi[d] = std::max(hi[d], e->points[i * 3 + d]);
+                lo[d] = std::min(lo[d], e->points[i * 3 + d] - o[d]);
+                hi[d] = std::max(hi[d], e->points[i * 3 + d] - o[d]);
             }
+            env_mag = std::max(env_mag, rel_norm(e->points + i * 3) + e->point_radius);
+        }
         long long total = 1;
         for (int d = 0; d < 3; ++d) {
             dims[d] = (int)std::floor((hi[d] - lo[d]) / cell) + 1;
@@ -453,7 +526,7 @@ void build_env(const mrv_env_desc* e, EnvHost& out)
             int ci[3];
             for (int d = 0; d < 3; ++d) {
                 // bin with the same FP32 arithmetic the kernel uses for its lookups
-                int v = (int)std::floor(((float)e->points[i * 3 + d] - grid_lo[d]) * inv);
+                int v = (int)std::floor(((float)(e->points[i * 3 + d] - o[d]) - grid_lo[d]) * inv);
                 ci[d] = std::min(std::max(v, 0), dims[d] - 1);
             }
             cell_of[i] = (ci[2] * dims[1] + ci[1]) * dims[0] + ci[0];
@@ -467,7 +540,7 @@ void build_env(const mrv_env_desc* e, EnvHost& out)
         for (long long i = 0; i < e->n_points; ++i) {
             int p = cursor[cell_of[i]]++;
             for (int d = 0; d < 3; ++d) {
-                pts32[(size_t)p * 4 + d] = (float)e->points[i * 3 + d];
+                pts32[(size_t)p * 4 + d] = (float)(e->points[i * 3 + d] - o[d]);
                 pts64[(size_t)p * 3 + d] = e->points[i * 3 + d];
             }
         }
@@ -482,7 +555,7 @@ void build_env(const mrv_env_desc* e, EnvHost& out)
     const EnvDev blank{};
     const size_t o_self = pk.add(&blank, sizeof(EnvDev));
     void* d = nullptr;
-    if (hipMalloc(&d, pk.bytes.size()) != hipSuccess) throw Err{MRV_E_NOMEM, "environment upload allocation failed"};
+    d = ctx->alloc.alloc(pk.bytes.size());
     auto at = [&](size_t o) { return (unsigned char*)d + o; };
     EnvDev& v = out.dev;
     v.n_sph = e->n_spheres;
@@ -507,11 +580,13 @@ void build_env(const mrv_env_desc* e, EnvHost& out)
     v.grid_inv = (float)(1.0 / cell);
     v.pt_radius = (float)e->point_radius;
     v.pt_radius64 = e->point_radius;
+    for (int k = 0; k < 3; ++k) v.origin64[k] = o[k];
+    v.mag = (float)env_mag;
     out.dmem = d;
     out.d_dev = (EnvDev*)at(o_self);
     std::memcpy(pk.bytes.data() + o_self, &v, sizeof(EnvDev));
     if (hipMemcpy(d, pk.bytes.data(), pk.bytes.size(), hipMemcpyHostToDevice) != hipSuccess) {
-        (void)hipFree(d);
+        ctx->alloc.free(d);
         throw Err{MRV_E_DEVICE, "environment upload failed"};
     }
 }
@@ -620,6 +695,7 @@ void ensure_scratch(Scratch& sc, size_t bins, size_t queries, hipStream_t stream
     sc.q_nt.ensure(Q * 4);
     sc.q_g.ensure(Q * 4);
     sc.q_chunk.ensure(Q * 4);
+    sc.q_eps.ensure(Q * 4);
     sc.q_status.ensure(Q * 4);
     sc.q_word.ensure(Q * 4);
     sc.q_drop.ensure(Q * 4);
@@ -642,12 +718,12 @@ bool grow_recheck(Scratch& sc, size_t pushed)
 namespace {
 
 
-// Queue the whole pipeline for one call on `stream`.
-void run_plan(mrv_ctx ctx, Scratch& sc, const CallPlan& pl, void* out_dev, hipStream_t stream, bool timing = true)
+// Queue the whole pipeline for one call on `stream`, with its scratch at the
+// device pointers of `v`; ev0/ev1 (may be null) bracket the validation kernel.
+void launch_plan(mrv_ctx ctx, const ScratchView& v, const CallPlan& pl, void* out_dev, hipStream_t stream,
+                 hipEvent_t ev0, hipEvent_t ev1)
 {
     const int kind = pl.kind;
-    const int min_chunk = std::max(1, pl.min_chunk);
-    ensure_scratch(sc, (size_t)((pl.max_T + min_chunk - 1) / min_chunk) + 2, (size_t)pl.dp.n_queries, stream);
     CallDev cd{};
     cd.n_queries = pl.dp.n_queries;
     cd.dof_stride = pl.dp.dof_stride;
@@ -662,26 +738,28 @@ void run_plan(mrv_ctx ctx, Scratch& sc, const CallPlan& pl, void* out_dev, hipSt
     cd.focus0 = pl.focus;
     cd.q_focus = pl.q_focus;
     cd.eps32 = (float)ctx->eps;
-    cd.eps64 = ctx->eps;
+    cd.chunk_floor = std::max(1, pl.min_chunk);
+    cd.max_nt = (long long)v.bins - 2;
     cd.n_wp = pl.dp.n_wp;
     cd.wp_begin = pl.dp.wp_begin;
     cd.wp_t = pl.dp.wp_t;
     cd.wp_q = pl.dp.wp_q;
-    cd.T = (int*)sc.q_T.p;
-    cd.nt = (int*)sc.q_nt.p;
-    cd.gstep = (int*)sc.q_g.p;
-    cd.q_chunk = (int*)sc.q_chunk.p;
-    cd.status = (int*)sc.q_status.p;
-    cd.word = (unsigned*)sc.q_word.p;
-    cd.drop = (unsigned*)sc.q_drop.p;
-    cd.sorted_q = (int*)sc.q_sorted.p;
-    cd.hist = (int*)sc.hist.p;
-    cd.start = (int*)sc.start.p;
-    cd.off = (int*)sc.off.p;
-    cd.ctrl = (int*)sc.ctrl.p;
-    cd.gq = (int4*)sc.gq.p;
-    cd.gq_cap = (int)sc.gq_records;
-    cd.stats = (unsigned long long*)((char*)sc.ctrl.p + 64);
+    cd.T = v.q_T;
+    cd.nt = v.q_nt;
+    cd.gstep = v.q_g;
+    cd.q_chunk = v.q_chunk;
+    cd.q_eps = v.q_eps;
+    cd.status = v.q_status;
+    cd.word = v.q_word;
+    cd.drop = v.q_drop;
+    cd.sorted_q = v.q_sorted;
+    cd.hist = v.hist;
+    cd.start = v.start;
+    cd.off = v.off;
+    cd.ctrl = v.ctrl;
+    cd.gq = v.gq;
+    cd.gq_cap = (int)v.gq_records;
+    cd.stats = (unsigned long long*)((char*)v.ctrl + 64);
     cd.valid_out = kind == 0 ? (unsigned char*)out_dev : nullptr;
     cd.conflict_out = kind == 1 ? (int*)out_dev : nullptr;
 
@@ -690,11 +768,19 @@ void run_plan(mrv_ctx ctx, Scratch& sc, const CallPlan& pl, void* out_dev, hipSt
     const int grid = std::max(1, ctx->n_cu * want);
 
     HIPCHK(launch_prepare(cd, stream));
-    if (timing) HIPCHK(hipEventRecord(sc.ev0, stream));
+    if (ev0) HIPCHK(hipEventRecord(ev0, stream));
     HIPCHK(launch_validate(cd, grid, stream));
-    if (timing) HIPCHK(hipEventRecord(sc.ev1, stream));
+    if (ev1) HIPCHK(hipEventRecord(ev1, stream));
     HIPCHK(launch_finalize(cd, stream));
-    if (timing) sc.last_kind = kind;
+}
+
+// Queue the whole pipeline for one call on `stream`, scratch from sc (grown to fit).
+void run_plan(mrv_ctx ctx, Scratch& sc, const CallPlan& pl, void* out_dev, hipStream_t stream, bool timing = true)
+{
+    const int min_chunk = std::max(1, pl.min_chunk);
+    ensure_scratch(sc, (size_t)tile_bins(pl.max_T, min_chunk), (size_t)pl.dp.n_queries, stream);
+    launch_plan(ctx, sc.view(), pl, out_dev, stream, timing ? sc.ev0 : nullptr, timing ? sc.ev1 : nullptr);
+    if (timing) sc.last_kind = pl.kind;
 }
 
 // Plan for a call whose queries all use one team and environment.
@@ -866,6 +952,13 @@ extern "C" {
 
 const char* mrv_last_error(void) { return g_err.c_str(); }
 
+mrv_status mrv_memory_stats(mrv_ctx ctx, size_t* used, size_t* peak, size_t* capacity)
+{
+    if (guard(ctx)) return MRV_E_HANDLE;
+    ctx->alloc.stats(used, peak, capacity);
+    return MRV_OK;
+}
+
 mrv_status mrv_create(const mrv_ctx_opts* opts, mrv_ctx* out)
 {
     if (!out) return fail(MRV_E_INVALID, "null output handle");
@@ -885,6 +978,17 @@ mrv_status mrv_create(const mrv_ctx_opts* opts, mrv_ctx* out)
         if (!(c->eps < 1e-2)) throw Err{MRV_E_INVALID, "near_eps must be < 0.01 m"};
         if (opts && opts->max_inflight > 0) c->max_inflight = opts->max_inflight;
         if (opts && opts->serve_bytes > 0) c->serve_bytes = opts->serve_bytes;
+        if (opts && (opts->device_arena != nullptr) != (opts->arena_bytes > 0))
+            throw Err{MRV_E_INVALID, "device_arena and arena_bytes must be given together"};
+        if (opts && opts->device_arena) {
+            hipPointerAttribute_t attr{};
+            if (hipPointerGetAttributes(&attr, opts->device_arena) != hipSuccess ||
+                attr.type != hipMemoryTypeDevice || attr.device != dev)
+                throw Err{MRV_E_INVALID, "device_arena is not device memory of the context's device"};
+            c->alloc.use_arena(opts->device_arena, opts->arena_bytes);
+        }
+        c->sc.bind(&c->alloc);
+        for (DevBuf* b : {&c->in_begin, &c->in_t, &c->in_q, &c->out_buf, &c->tune_desc}) b->a = &c->alloc;
         if (opts && opts->recheck_records > 0) {
             if ((uint64_t)opts->recheck_records > Scratch::kMaxRecheckCap)
                 throw Err{MRV_E_INVALID, "recheck_records above 2^27"};
@@ -909,10 +1013,10 @@ mrv_status mrv_destroy(mrv_ctx ctx)
         if (ctx->serve) ctx->serve.reset();
         (void)hipSetDevice(ctx->device);
         (void)hipStreamSynchronize(ctx->stream);
-        for (auto& kv : ctx->teams) (void)hipFree(kv.second.dmem);
-        for (auto& kv : ctx->envs) (void)hipFree(kv.second.dmem);
+        for (auto& kv : ctx->teams) ctx->alloc.free(kv.second.dmem);
+        for (auto& kv : ctx->envs) ctx->alloc.free(kv.second.dmem);
         ctx->sc.release();
-        for (DevBuf* b : {&ctx->in_begin, &ctx->in_t, &ctx->in_q, &ctx->out_buf}) b->release();
+        for (DevBuf* b : {&ctx->in_begin, &ctx->in_t, &ctx->in_q, &ctx->out_buf, &ctx->tune_desc}) b->release();
         if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     });
     delete ctx;
@@ -941,7 +1045,7 @@ mrv_status mrv_load_env(mrv_ctx ctx, const mrv_env_desc* env, int32_t* env_out)
     return wrap([&] {
         set_device(ctx);
         EnvHost eh;
-        build_env(env, eh);
+        build_env(ctx, env, eh);
         std::lock_guard<std::mutex> lk(ctx->handle_mu);
         const int h = ctx->next_handle++;
         ctx->envs.emplace(h, eh);
@@ -959,7 +1063,7 @@ mrv_status mrv_unload(mrv_ctx ctx, int32_t handle)
         if (t != ctx->teams.end()) {
             if (t->second.inflight > 0) throw Err{MRV_E_BUSY, "team is used by a queued request"};
             HIPCHK(hipStreamSynchronize(ctx->stream));
-            (void)hipFree(t->second.dmem);
+            ctx->alloc.free(t->second.dmem);
             ctx->teams.erase(t);
             return;
         }
@@ -967,7 +1071,7 @@ mrv_status mrv_unload(mrv_ctx ctx, int32_t handle)
         if (e != ctx->envs.end()) {
             if (e->second.inflight > 0) throw Err{MRV_E_BUSY, "environment is used by a queued request"};
             HIPCHK(hipStreamSynchronize(ctx->stream));
-            (void)hipFree(e->second.dmem);
+            ctx->alloc.free(e->second.dmem);
             ctx->envs.erase(e);
             return;
         }
@@ -1095,11 +1199,15 @@ mrv_status mrv_set_tiling(mrv_ctx ctx, int32_t team, int32_t kind, uint32_t flag
         if (!tiling || (kind != 0 && kind != 1)) throw Err{MRV_E_INVALID, "bad tiling arguments"};
         std::lock_guard<std::mutex> lk(ctx->handle_mu);
         TeamHost& tm = find_team(ctx, team);
+        if (tm.inflight > 0) throw Err{MRV_E_BUSY, "team is used by a served request or a captured graph"};
         if (tiling->chunk < 0 || tiling->chunk > kMaxChunk) throw Err{MRV_E_INVALID, "chunk out of range"};
         if (tiling->chunk > 0 && lds_bytes_for(tm, tiling->chunk) > (size_t)kLdsBudget - 2 * 1024)
             throw Err{MRV_E_INVALID, "chunk does not fit in LDS for this team"};
         if (tiling->wg_per_cu < 0 || tiling->wg_per_cu > 32) throw Err{MRV_E_INVALID, "wg_per_cu out of range"};
         const int m = mode_of(flags);
+        set_device(ctx);
+        // calls queued on the context stream read the descriptor: let them finish first
+        HIPCHK(hipStreamSynchronize(ctx->stream));
         tm.tiling[kind][m] = *tiling;
         tm.dev.chunk[kind][m] = tiling->chunk > 0 ? tiling->chunk : default_chunk(tm, kind, m);
         HIPCHK(hipMemcpy(tm.d_dev, &tm.dev, sizeof(TeamDev), hipMemcpyHostToDevice));
@@ -1172,6 +1280,7 @@ mrv_status mrv_spheres(mrv_ctx ctx, int32_t team, const mrv_paths* paths, int32_
         ctx->in_t.ensure(ntb);
         ctx->in_q.ensure(nqb);
         DevBuf st, o;
+        st.a = o.a = &ctx->alloc;
         st.ensure((size_t)n_states * 8);
         o.ensure(nout);
         try {
@@ -1220,6 +1329,7 @@ mrv_status mrv_autotune(mrv_ctx ctx, int32_t team, int32_t env, int32_t kind, co
         {
             std::lock_guard<std::mutex> lk(ctx->handle_mu);
             tm = find_team(ctx, team);
+            if (tm.inflight > 0) throw Err{MRV_E_BUSY, "team is used by a served request or a captured graph"};
             if (kind == 0 && find_env(ctx, env)) {
                 evh = *find_env(ctx, env);
                 ev = &evh;
@@ -1260,12 +1370,16 @@ mrv_status mrv_autotune(mrv_ctx ctx, int32_t team, int32_t env, int32_t kind, co
                 if (c <= cmax) chunks.push_back(c);
             if (chunks.empty() || chunks.back() != cmax) chunks.push_back(cmax);
             float best_ms = 1e30f;
+            // trials run on a private copy of the team's descriptor, so calls and served
+            // requests that use the team meanwhile keep its tiling
             TeamHost trial = tm;
+            ctx->tune_desc.ensure(sizeof(TeamDev));
+            trial.d_dev = (TeamDev*)ctx->tune_desc.p;
             for (int c : chunks) {
                 for (int wg : {0, 1, 2}) {
                     trial.dev.chunk[kind][mode_of(f)] = c;
                     trial.tiling[kind][mode_of(f)] = mrv_tiling{c, wg};
-                    HIPCHK(hipMemcpyAsync(tm.d_dev, &trial.dev, sizeof(TeamDev), hipMemcpyHostToDevice, ctx->stream));
+                    HIPCHK(hipMemcpyAsync(trial.d_dev, &trial.dev, sizeof(TeamDev), hipMemcpyHostToDevice, ctx->stream));
                     float ms_min = 1e30f;
                     for (int rep = 0; rep < 3; ++rep) {
                         run_plan(ctx, ctx->sc, single_plan(trial, ev, kind, f, dp, mT), ctx->out_buf.p, ctx->stream);
@@ -1282,9 +1396,11 @@ mrv_status mrv_autotune(mrv_ctx ctx, int32_t team, int32_t env, int32_t kind, co
             }
             ctx->tune_cache[key] = choice;
         }
-        // apply the choice to the team (restores its descriptor)
+        // apply the choice to the team
         std::lock_guard<std::mutex> lk(ctx->handle_mu);
         TeamHost& live = find_team(ctx, team);
+        if (live.inflight > 0) throw Err{MRV_E_BUSY, "team is used by a served request or a captured graph"};
+        HIPCHK(hipStreamSynchronize(ctx->stream));
         live.tiling[kind][mode_of(f)] = choice;
         live.dev.chunk[kind][mode_of(f)] = choice.chunk;
         HIPCHK(hipMemcpy(live.d_dev, &live.dev, sizeof(TeamDev), hipMemcpyHostToDevice));
@@ -1323,6 +1439,7 @@ mrv_status mrv_graph_create(mrv_ctx ctx, int32_t team, int32_t env, int32_t kind
         CallPlan pl = single_plan(tm, ev, kind, f, dp, MRV_MAX_T);
         // every buffer exists before capture: nothing is allocated inside the graph
         g->sc.gq_records = ctx->sc.gq_records;
+        g->sc.bind(&ctx->alloc);
         ensure_scratch(g->sc, (size_t)MRV_MAX_T + 2, (size_t)paths->n_queries, ctx->stream);
         HIPCHK(hipStreamSynchronize(ctx->stream));
         HIPCHK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
@@ -1392,8 +1509,12 @@ mrv_status mrv_submit(mrv_ctx ctx, const mrv_request* req, uint64_t* ticket)
     if (guard(ctx)) return MRV_E_HANDLE;
     if (!req || !ticket) return fail(MRV_E_INVALID, "null argument");
     return wrap([&] {
-        if (!ctx->serve) ctx->serve.reset(new ServeLoop(ctx, ctx->device, ctx->max_inflight, ctx->serve_bytes,
-                                                          ctx->recheck_records));
+        if (!ctx->serve) {
+            // serving budget: as given, else the arena (no further limit) or 1 GiB
+            const size_t budget = ctx->serve_bytes ? ctx->serve_bytes : ctx->alloc.arena() ? SIZE_MAX : (size_t(1) << 30);
+            ctx->serve.reset(new ServeLoop(ctx, ctx->device, ctx->max_inflight, budget, ctx->recheck_records,
+                                           &ctx->alloc));
+        }
         // validate against the resident handles, resolve their device descriptors, then copy
         ServeRefs refs{};
         mrv_request rq = *req;

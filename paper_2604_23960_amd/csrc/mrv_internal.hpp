@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
+#include "mrv_tiles.hpp"
+
 namespace mrv {
 
 constexpr int kWG = 256;            // threads per workgroup (4 waves of 64)
@@ -21,6 +23,9 @@ constexpr int kMaxChunk = 64;       // timesteps per tile
 constexpr int kLdsBudget = 160 * 1024;   // LDS one workgroup may use on gfx950
 constexpr int kWGsPerCU = 5;        // validation workgroups per CU the register budget allows
 constexpr int kExhWGsPerCU = 7;     // the same for the exhaustive MV kernel (72 VGPRs)
+// The near band of a query widens in proportion to the largest coordinate magnitude
+// its FP32 arithmetic sees beyond this scale (metres); see k_query_info.
+constexpr double kEpsRefScale = 4.0;
 
 enum RecheckKind : int { RK_RR = 0, RK_SELF = 1, RK_ENV_SPH = 2, RK_ENV_BOX = 3, RK_ENV_CYL = 4, RK_ENV_PT = 5 };
 
@@ -47,12 +52,17 @@ struct TeamDev {
     int chunk[2][2];       // timesteps per tile: [MV / FFC][early-terminating / exhaustive]
     int lds_per_t;         // LDS bytes one timestep of a tile needs
     float r_max;           // largest sphere radius of the team
-    float origin[4];       // reference point of the FP32 sphere records (centre of the bases' bounding box)
+    float origin[4];       // team origin o (centre of the bases' bounding box, an FP32 value): FK, sphere
+                           // records and pair tests run on coordinates relative to it
+    double origin64[3];    // o exactly, for the FP64 offset to an environment's origin
+    float mag;             // largest of r_mag
     long long rr_tests_per_t;   // sum_{i<j} n_i n_j
     const int* r_nj;            // [n]
     const int* r_joint_off;     // [n]
     const int* r_sphere_off;    // [n+1]
     const int* r_frame_off;     // [n]
+    const float* r_mag;         // [n] bound on |FP32 coordinate| of the robot's frames and spheres relative
+                                // to o, without prismatic joint values (those are added per query)
     const float* r_base32;      // [n][12]
     const double* r_base64;     // [n][12]
     const int* j_type;          // [joints]
@@ -84,6 +94,9 @@ struct EnvDev {
     const float* cyl32;         // [n][8] centre(3), axis(3), half-length, radius
     const double* cyl64;        // [n][8]
     const float4* bc_box;       // [n_box + n_cyl][2] world-axis box (lo, hi) of each box, then each cylinder
+    // every FP32 coordinate above and below is relative to the environment's origin
+    double origin64[3];         // the environment origin (centre of its obstacles' bounding box, an FP32 value)
+    float mag;                  // bound on |FP32 coordinate| of any obstacle part relative to the origin
     // uniform grid over the point cloud (CSR by cell)
     const float4* pts32;        // [n_pts] points sorted by cell (x, y, z, 0)
     const double* pts64;        // [n_pts][3] in the same order
@@ -112,8 +125,9 @@ struct CallDev {
     const long long* q_pathoff;
     unsigned focus0;            // robots validated (bit r), 0 = all: prioritised MV
     const unsigned* q_focus;    // per query, or null: focus0 for every query
-    float eps32;
-    double eps64;
+    float eps32;                // near band in metres before per-query scaling
+    int chunk_floor;            // smallest tile length the call's scratch was sized for
+    long long max_nt;           // most tiles a query may have (tile bins - 2)
     long long n_wp;
     const long long* wp_begin;
     const int* wp_t;
@@ -123,11 +137,12 @@ struct CallDev {
     int* nt;
     int* gstep;
     int* q_chunk;               // timesteps per tile chosen for each query
+    float* q_eps;               // near band of each query (eps32 widened for large coordinates)
     int* status;                // 0 ok, 1 invalid input
     unsigned* word;             // MV: hit flag; FFC: best key t*P + pair
     unsigned* drop;             // smallest key (MV: 0) of a near test the full queue dropped
     int* sorted_q;
-    // tile enumeration scratch (sized for MRV_MAX_T / 1 + 2 bins)
+    // tile enumeration scratch: max_nt + 2 bins (see mrv_tiles.hpp)
     int* hist;
     int* start;
     int* off;

@@ -308,10 +308,11 @@ __global__ void k_query_info(CallDev cd)
     const TeamDev& tm = *team_of(cd, q);
     const int n = tm.n_robots;
     const long long p0 = path_of(cd, n, q);
-    int chunk = min(tm.chunk[cd.kind][(cd.flags & MRV_EXHAUSTIVE) ? 1 : 0], (cd.lds_bytes - 64) / tm.lds_per_t);
-    chunk = max(1, min(chunk, kMaxChunk));
+    const int chunk = query_chunk(tm.chunk[cd.kind][(cd.flags & MRV_EXHAUSTIVE) ? 1 : 0], cd.lds_bytes, tm.lds_per_t,
+                                  cd.chunk_floor, kMaxChunk);
     int T = 0;
-    bool ok = true;
+    bool ok = chunk * tm.lds_per_t + 64 <= cd.lds_bytes;   // holds by the plan; checked, never assumed
+    double mag = 0.0;            // bound on the |FP32 coordinates| of the query's frames and spheres
     for (int r = 0; r < n && ok; ++r) {
         const long long b = cd.wp_begin[p0 + r];
         const long long e = cd.wp_begin[p0 + r + 1];
@@ -319,25 +320,50 @@ __global__ void k_query_info(CallDev cd)
         int prev = cd.wp_t[b];
         if (prev != 0) { ok = false; break; }
         const int dof = tm.r_nj[r];
+        const int j0 = tm.r_joint_off[r];
+        double prism = 0.0;      // largest sum of |prismatic joint value| over the robot's waypoints
         for (long long i = b; i < e && ok; ++i) {
             const int ti = cd.wp_t[i];
             if (i > b && ti <= prev) ok = false;
             prev = ti;
-            for (int d = 0; d < dof; ++d)
-                if (!bounded64(cd.wp_q[i * cd.dof_stride + d])) ok = false;
+            double ps = 0.0;
+            for (int d = 0; d < dof; ++d) {
+                const double v = cd.wp_q[i * cd.dof_stride + d];
+                if (!bounded64(v)) ok = false;
+                else if (tm.j_type[j0 + d] != MRV_REV_Z) ps += fabs(v);
+            }
+            prism = fmax(prism, ps);
         }
         if (prev >= MRV_MAX_T) ok = false;
         if (prev + 1 > T) T = prev + 1;
+        mag = fmax(mag, (double)tm.r_mag[r] + prism);
     }
-    int nt = 0, g = 1;
+    long long nt = 0;
+    int g = 1;
     if (ok) {
-        nt = (T + chunk - 1) / chunk;
-        g = golden_step(nt);
+        nt = tiles_of(T, chunk);
+        if (nt > cd.max_nt) ok = false;     // cannot happen: T <= max_T and chunk >= chunk_floor
+        else g = golden_step((int)nt);
     }
+    // Near band.  Every FP32 coordinate the kernels form is relative to the team's
+    // origin (frames, spheres) or to the environment's (obstacles, and the spheres
+    // moved there by the FP64-rounded offset of the two origins), so FP32 rounding
+    // grows with those relative magnitudes, never with where the cell sits in the
+    // world.  The band eps holds with a wide margin up to kEpsRefScale metres
+    // (measured); beyond it the band grows in proportion, as FP32 error does.
+    double m = mag;
+    const EnvDev* ep = cd.kind == 0 && (cd.flags & MRV_CHECK_ENV) ? env_of(cd, q) : nullptr;
+    if (ep) {
+        const double dx = tm.origin64[0] - ep->origin64[0], dy = tm.origin64[1] - ep->origin64[1],
+                     dz = tm.origin64[2] - ep->origin64[2];
+        m = fmax(m + sqrt(dx * dx + dy * dy + dz * dz), (double)ep->mag);
+    }
+    const float eps_q = (float)((double)cd.eps32 * fmax(1.0, m / kEpsRefScale));
     cd.T[q] = ok ? T : 0;
-    cd.nt[q] = nt;
+    cd.nt[q] = ok ? (int)nt : 0;
     cd.gstep[q] = g;
     cd.q_chunk[q] = chunk;
+    cd.q_eps[q] = eps_q;
     cd.status[q] = ok ? 0 : 1;
     cd.word[q] = cd.kind == 1 ? 0xFFFFFFFFu : 0u;
     cd.drop[q] = 0xFFFFFFFFu;
@@ -345,7 +371,7 @@ __global__ void k_query_info(CallDev cd)
         atomicAdd(&cd.ctrl[3], 1);
     } else {
         atomicAdd(&cd.hist[nt], 1);
-        atomicMax(&cd.ctrl[0], nt);
+        atomicMax(&cd.ctrl[0], (int)nt);
         atomicAdd(&cd.stats[ST_STATES_COVERED], (unsigned long long)n * (unsigned long long)T);
     }
 }
@@ -596,9 +622,11 @@ __device__ bool direct_block(const CallDev& cd, const TeamDev& tm, const float* 
     return hit;
 }
 
-// FP32 frames of robot r at timestep t: the configuration is interpolated in FP64
-// from path waypoints [pb, pe) and rounded once; the chain Frame_k =
-// Frame_{k-1} F_k J_k(q_k) then runs in FP32 registers.  out receives
+// FP32 frames of robot r at timestep t, relative to the team origin: the
+// configuration is interpolated in FP64 from path waypoints [pb, pe), revolute
+// angles are reduced to [-pi, pi] in FP64, and each value is rounded once; the
+// chain Frame_k = Frame_{k-1} F_k J_k(q_k) then runs in FP32 registers from the
+// base frame (translation relative to the origin).  out receives
 // (n_joints + 1) frames as 3 float4 rows (R row, p) each, the base first.
 __device__ __forceinline__ void robot_frames32(const TeamDev& tm, const CallDev& cd, long long pb, long long pe,
                                                int r, int t, float4* out)
@@ -608,6 +636,7 @@ __device__ __forceinline__ void robot_frames32(const TeamDev& tm, const CallDev&
     double sfrac = 0.0;
     if (!last) sfrac = (double)(t - cd.wp_t[kseg]) / (double)(cd.wp_t[kseg + 1] - cd.wp_t[kseg]);
     const int nj = tm.r_nj[r];
+    const int j0 = tm.r_joint_off[r];
     float qv[kMaxJoints];
 #pragma unroll
     for (int j = 0; j < kMaxJoints; ++j) {
@@ -616,6 +645,9 @@ __device__ __forceinline__ void robot_frames32(const TeamDev& tm, const CallDev&
             double qa = cd.wp_q[kseg * cd.dof_stride + j];
             double qj = qa;
             if (!last) qj = qa + sfrac * (cd.wp_q[(kseg + 1) * cd.dof_stride + j] - qa);
+            // an angle enters only through sin and cos: take it modulo 2 pi while it
+            // is exact, so its FP32 rounding error stays below 2^-24 pi
+            if (tm.j_type[j0 + j] == MRV_REV_Z) qj = fma(-6.283185307179586, rint(qj * 0.15915494309189535), qj);
             qv[j] = (float)qj;
         }
     }
@@ -625,7 +657,6 @@ __device__ __forceinline__ void robot_frames32(const TeamDev& tm, const CallDev&
     out[0] = make_float4(Mx[0], Mx[1], Mx[2], Mx[3]);
     out[1] = make_float4(Mx[4], Mx[5], Mx[6], Mx[7]);
     out[2] = make_float4(Mx[8], Mx[9], Mx[10], Mx[11]);
-    const int j0 = tm.r_joint_off[r];
 #pragma unroll
     for (int j = 0; j < kMaxJoints; ++j) {
         if (j < nj) {
@@ -680,7 +711,8 @@ __device__ __forceinline__ float4 place32(const float4* Fp, float4 L)
 }
 
 // Robot-obstacle tests of J (timestep, 64-slot chunk) tasks of one wave, one lane
-// per slot, obstacle parameters in wave-uniform scalar loads (each sphere
+// per slot, in the environment's frame (`off` = team origin minus environment
+// origin), obstacle parameters in wave-uniform scalar loads (each sphere
 // obstacle's loaded once for all J tasks).  Sets *s_hit on a confirmed hit; near
 // tests below the known outcome are queued for FP64 re-evaluation.  The kernel
 // passes one task at a time: with boxes and cylinders selected per task, larger
@@ -689,7 +721,7 @@ template <int J>
 __device__ __forceinline__ void env_tasks(const CallDev& cd, const TeamDev& tm, const EnvDev& env, const float* sp,
                                           const int* task, int nch, float ro_max, float eps, bool exhaustive, int q,
                                           unsigned focus, bool fall, const int* s_t, int* s_hit,
-                                          unsigned long long& c_env, int lane)
+                                          unsigned long long& c_env, int lane, float3 off)
 {
     const int GS = tm.GS, GSp = tm.GSp, TS = tm.TS;
     int c[J], a[J];
@@ -705,9 +737,10 @@ __device__ __forceinline__ void env_tasks(const CallDev& cd, const TeamDev& tm, 
         if (act[j] && !fall) act[j] = ((focus >> tm.s_robot[tm.slot_sphere[a[j]]]) & 1u) != 0;
         x[j] = 1.0e18f; y[j] = 1.0e18f; z[j] = 1.0e18f;
         if (act[j]) {
-            x[j] = row[0] + tm.origin[0];
-            y[j] = row[GSp] + tm.origin[1];
-            z[j] = row[2 * GSp] + tm.origin[2];
+            // team-origin coordinates moved to the environment's frame
+            x[j] = row[0] + off.x;
+            y[j] = row[GSp] + off.y;
+            z[j] = row[2 * GSp] + off.z;
         }
         mb[j] = 3.0e38f;
         ms[j] = 3.0e38f;
@@ -850,6 +883,7 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
     __shared__ int s_t[kMaxChunk];
     __shared__ int s_q, s_nv, s_phase, s_hit, s_chunk;
     __shared__ unsigned s_key, s_rho2;
+    __shared__ float s_eps;
     __shared__ unsigned long long s_tp, s_ep;
     __shared__ unsigned s_focus;
     // thread 0's claim state and tile counts, kept in LDS rather than registers
@@ -864,7 +898,6 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
     const bool exhaustive = KIND >= 3;
     const bool check_env = kMV && (flags & MRV_CHECK_ENV) != 0;
     const bool hier = check_env && (flags & MRV_HIERARCHICAL) != 0;
-    const float eps = cd.eps32;
 
     unsigned long long* w64 = reinterpret_cast<unsigned long long*>(cd.ctrl + 4);
     const long long total = (long long)__hip_atomic_load(&w64[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -945,6 +978,7 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
                 s_tp = (unsigned long long)tq;
                 s_ep = (unsigned long long)eq;
                 C = cd.q_chunk[q];
+                s_eps = cd.q_eps[q];
                 const int T = cd.T[q];
                 const int nt = cd.nt[q];
                 int base, stride;
@@ -985,6 +1019,7 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
         const unsigned long long epu = uniform_u64(s_ep);
         const EnvDev env = epu ? load_descriptor<EnvDev>(epu) : EnvDev{};
         const int C = wave_uniform(s_chunk);
+        const float eps = __int_as_float(wave_uniform(__float_as_int(s_eps)));   // this query's near band
         // prioritised MV: robots outside the focus set only take part in pairs
         // with a robot in it
         const unsigned focus = kFocus ? (unsigned)wave_uniform((int)s_focus) : 0u;
@@ -1004,7 +1039,6 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
         const int GSp = tm.GSp;
         const int TS = tm.TS;
         const int fr_off = TS - 12 * F;
-        const float ox = tm.origin[0], oy = tm.origin[1], oz = tm.origin[2];
         float* sp = reinterpret_cast<float*>(dyn);                      // [C][TS]
 
         // --- configurations and FP32 forward kinematics: one lane per (timestep, robot)
@@ -1016,7 +1050,8 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
         }
         __syncthreads();
 
-        // --- sphere centres, one lane per (timestep, slot); padding slots sit at the origin
+        // --- sphere centres relative to the team origin, one lane per (timestep, slot);
+        // padding slots sit at the origin
         for (int idx = tid; idx < nv * GS; idx += WG) {
             const int c = idx / GS;
             const int s = idx - c * GS;
@@ -1026,9 +1061,9 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
                 const float4 X = place32(reinterpret_cast<const float4*>(sp + (long long)c * TS + fr_off) +
                                              tm.s_slot[sph] * 3,
                                          tm.s_local32[sph]);
-                x = X.x - ox;
-                y = X.y - oy;
-                z = X.z - oz;
+                x = X.x;
+                y = X.y;
+                z = X.z;
             }
             float* row = sp + (long long)c * TS + s;
             row[0] = x;
@@ -1069,6 +1104,10 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
             // --- robot-obstacle tests (MV with environment checking): one lane per
             // (timestep, slot); obstacle parameters are wave-uniform scalar loads.
             if (do_env) {
+                // the team origin in the environment's frame, rounded once from FP64
+                const float3 off = make_float3((float)(tm.origin64[0] - env.origin64[0]),
+                                               (float)(tm.origin64[1] - env.origin64[1]),
+                                               (float)(tm.origin64[2] - env.origin64[2]));
                 const int nch = (GS + kWave - 1) / kWave;
                 const int ntask = nv * nch;
                 float ro_max = 0.f;
@@ -1079,7 +1118,7 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
                 for (; task < ntask && !(!exhaustive && flag_read(&s_hit)); task += kWaves) {
                     const int tk[1] = { task };
                     env_tasks<1>(cd, tm, env, sp, tk, nch, ro_max, eps, exhaustive, q, focus, fall, s_t, &s_hit, c_env,
-                                 lane);
+                                 lane, off);
                 }
             }
 
@@ -1258,8 +1297,9 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
 }
 
 // FP32 sphere centres of requested (query, timestep) states, computed by the same
-// device code as the validation kernel.  One workgroup per state; LDS holds the
-// frames of one timestep.
+// device code as the validation kernel (relative to the team origin), then moved
+// to the world frame by one FP32 addition of the origin.  One workgroup per state;
+// LDS holds the frames of one timestep.
 __global__ void k_spheres(CallDev cd, const int* st_q, const int* st_t, int n_states, float4* out, int S_out)
 {
     extern __shared__ float4 frames[];
@@ -1270,8 +1310,10 @@ __global__ void k_spheres(CallDev cd, const int* st_q, const int* st_t, int n_st
         for (int r = threadIdx.x; r < tm.n_robots; r += blockDim.x)
             robot_frames32(tm, cd, cd.wp_begin[p0 + r], cd.wp_begin[p0 + r + 1], r, st_t[k], frames + tm.r_frame_off[r] * 3);
         __syncthreads();
-        for (int s = threadIdx.x; s < tm.S; s += blockDim.x)
-            out[(long long)k * S_out + s] = place32(frames + tm.s_slot[s] * 3, tm.s_local32[s]);
+        for (int s = threadIdx.x; s < tm.S; s += blockDim.x) {
+            const float4 X = place32(frames + tm.s_slot[s] * 3, tm.s_local32[s]);
+            out[(long long)k * S_out + s] = make_float4(X.x + tm.origin[0], X.y + tm.origin[1], X.z + tm.origin[2], X.w);
+        }
         __syncthreads();
     }
 }

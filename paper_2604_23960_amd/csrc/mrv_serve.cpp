@@ -5,12 +5,17 @@
 // buffers and pinned staging memory.  Whenever a slot is free and requests wait,
 // the thread merges the waiting requests that share (kind, flags) with the oldest
 // one into a single call -- requests of different teams and environments mix,
-// each query carrying its own team and environment descriptor -- as many as fit
-// the slot's share of the device-memory budget, stages their paths in pinned
-// memory, and queues one upload, the validation kernels and the download on the
-// slot stream.  Batches on different
-// slots overlap on the device, and requests that arrive while others run are
-// admitted as soon as a slot and its memory free up (continuous batching).
+// each query carrying its own team and environment descriptor -- stages their
+// paths in pinned memory, reserves the batch's device memory (inputs, outputs,
+// scratch and near-contact queue) from the context's allocator, and queues one
+// upload, the validation kernels and the download on the slot stream.  Batches
+// on different slots overlap on the device, and requests that arrive while
+// others run are admitted as soon as a slot and memory free up (continuous
+// batching).  Admission counts the bytes batches actually hold: a batch starts
+// only if the memory held by the batches in flight, its own included, stays
+// within the serving budget and the allocator (the caller's arena, if any) can
+// supply it; otherwise its requests wait for a running batch to give memory
+// back.  With an arena, a slot returns its device memory when its batch ends.
 // Completion is detected with HIP events; results are handed to the waiting
 // pollers through a condition variable.
 #include <chrono>
@@ -46,11 +51,54 @@ struct Req {
     bool cancel_requested = false;
     mrv_status err = MRV_OK;
     std::string msg;
-    size_t bytes() const
+};
+
+// What a batch holds on the device, from the requests it merges.
+struct BatchShape {
+    int nq = 0, kind = 0, stride = 0;
+    long long n_paths = 0, n_wp = 0, max_T = 1;
+    int min_chunk = 1 << 30;
+    void add(const Req& r)
     {
-        return wp_begin.size() * 8 + wp_t.size() * 4 + wp_q.size() * 8 + (size_t)n_queries * (7 * 4 + 12 + 28);
+        nq += r.n_queries;
+        kind = r.kind;
+        stride = r.dof_stride;
+        n_paths += (long long)r.n_queries * r.n_robots;
+        n_wp += (long long)r.wp_t.size();
+        max_T = std::max(max_T, r.max_T);
+        min_chunk = std::min(min_chunk, r.refs.chunk);
     }
 };
+
+inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Pinned/device input block of a batch: wp_begin | wp_t | wp_q | q_team | q_env |
+// q_pathoff | q_focus, each piece 256-byte aligned.
+struct InputLayout {
+    size_t o_t, o_q, o_team, o_env, o_po, o_fo, total;
+    explicit InputLayout(const BatchShape& b)
+    {
+        const size_t nb = (size_t)(b.n_paths + 1) * sizeof(long long);
+        o_t = align256(nb);
+        o_q = align256(o_t + (size_t)b.n_wp * sizeof(int));
+        o_team = align256(o_q + (size_t)b.n_wp * b.stride * sizeof(double));
+        o_env = align256(o_team + (size_t)b.nq * 8);
+        o_po = align256(o_env + (size_t)b.nq * 8);
+        o_fo = align256(o_po + (size_t)b.nq * 8);
+        total = o_fo + (size_t)b.nq * 4;
+    }
+};
+
+// Device bytes a batch of this shape holds on a slot with the given near-contact
+// queue length: inputs, outputs and scratch, each buffer as the allocator rounds it.
+size_t batch_bytes(const BatchShape& b, size_t gq_records)
+{
+    auto buf = [](size_t v) { return align256(std::max<size_t>(v, 256)); };
+    const size_t Q = std::max(b.nq, 1);
+    const size_t bins = (size_t)tile_bins(b.max_T, b.min_chunk == (1 << 30) ? 1 : b.min_chunk);
+    return buf(InputLayout(b).total) + buf(b.kind == 0 ? Q : Q * 12) + buf(64 + 8 * ST_COUNT + 64) +
+           2 * buf(bins * 4) + buf(bins * 8) + 9 * buf(Q * 4) + buf(gq_records * 16);
+}
 
 struct PinnedBuf {
     void* p = nullptr;
@@ -81,6 +129,7 @@ struct Slot {
     hipEvent_t done = nullptr;
     Scratch sc;
     DevBuf d_in, d_out;
+    size_t held = 0;          // device bytes of the running batch (buffers as allocated)
     PinnedBuf h_in, h_out;
     std::vector<std::shared_ptr<Req>> batch;
     std::vector<int> q_off;   // first query of each request in the batch
@@ -97,7 +146,11 @@ struct ServeLoop::Impl {
     mrv_ctx ctx;
     int device;
     int max_inflight;
-    size_t budget;
+    size_t budget;                      // most device bytes the batches in flight may hold
+    DevAlloc* alloc;
+    bool mem_wait = false;              // the queue head waits for memory a running batch holds
+    bool solo_next = false;             // the next batch is the queue head alone
+    size_t recheck_records;             // initial near-contact queue length of a slot
     std::mutex mu;
     std::condition_variable cv_work;    // serve thread waits here when idle
     std::condition_variable cv_done;    // pollers wait here
@@ -112,12 +165,15 @@ struct ServeLoop::Impl {
     static constexpr int kSlots = 4;
     static constexpr int kMaxBatchQueries = 1 << 16;
 
-    Impl(mrv_ctx c, int dev, int mi, size_t b, size_t rq) : ctx(c), device(dev), max_inflight(mi), budget(b)
+    Impl(mrv_ctx c, int dev, int mi, size_t b, size_t rq, DevAlloc* a)
+        : ctx(c), device(dev), max_inflight(mi), budget(b), alloc(a), recheck_records(rq)
     {
         HIPCHK(hipSetDevice(device));
         slots.resize(kSlots);
         for (Slot& s : slots) {
             s.sc.gq_records = rq;
+            s.sc.bind(alloc);
+            s.d_in.a = s.d_out.a = alloc;
             HIPCHK(hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking));
             HIPCHK(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
         }
@@ -161,9 +217,9 @@ struct ServeLoop::Impl {
                 complete(s);
                 progress = true;
             }
-            // admissions
+            // admissions (none while the queue head waits for a running batch's memory)
             for (Slot& s : slots) {
-                if (stop) break;
+                if (stop || mem_wait) break;
                 if (s.busy) continue;
                 drop_cancelled();
                 if (queue.empty()) break;
@@ -176,9 +232,7 @@ struct ServeLoop::Impl {
                 if (!any) break;
             }
             if (progress) continue;
-            bool any_busy = false;
-            for (Slot& s : slots) any_busy = any_busy || s.busy;
-            if (any_busy) {
+            if (any_busy()) {
                 // a batch is on the device: poll its event shortly
                 lk.unlock();
                 std::this_thread::sleep_for(std::chrono::microseconds(20));
@@ -214,22 +268,45 @@ struct ServeLoop::Impl {
         cv_done.notify_all();
     }
 
+    size_t held_by_batches() const
+    {
+        size_t h = 0;
+        for (const Slot& s : slots) h += s.busy ? s.held : 0;
+        return h;
+    }
+    bool any_busy() const
+    {
+        for (const Slot& s : slots)
+            if (s.busy) return true;
+        return false;
+    }
+
     // Form a batch from the queue head and queue it on slot s.  Called with mu held;
-    // the staging copies and launches run with mu released.
+    // the staging copies and launches run with mu released.  Requests join while the
+    // memory the batch will hold (estimated as its allocations) keeps every batch in
+    // flight within the budget; the head always joins.  If the allocator cannot
+    // supply the batch, its requests go back to the queue front: they wait for a
+    // running batch to return memory or, with nothing running, run one at a time,
+    // and a request that cannot run even alone fails with MRV_E_NOMEM.
     void launch(Slot& s, std::unique_lock<std::mutex>& lk)
     {
         std::vector<std::shared_ptr<Req>> batch;
         const std::shared_ptr<Req> head = queue.front();
-        const size_t slot_budget = std::max<size_t>(budget / kSlots, 1);
-        size_t bytes = 0;
-        int nq = 0;
+        const size_t others = held_by_batches();
+        const size_t room = budget > others ? budget - others : 0;
+        BatchShape sh;
         for (auto it = queue.begin(); it != queue.end();) {
             const auto& r = *it;
             const bool same = r->kind == head->kind && r->flags == head->flags && r->dof_stride == head->dof_stride &&
                               !r->cancel_requested;
-            if (same && (batch.empty() || (bytes + r->bytes() <= slot_budget && nq + r->n_queries <= kMaxBatchQueries))) {
-                bytes += r->bytes();
-                nq += r->n_queries;
+            bool take = same && (batch.empty() || !solo_next);
+            if (take && !batch.empty()) {
+                BatchShape t = sh;
+                t.add(*r);
+                take = t.nq <= kMaxBatchQueries && batch_bytes(t, s.sc.gq_records) <= room;
+            }
+            if (take) {
+                sh.add(*r);
                 r->state = RS_RUNNING;
                 batch.push_back(r);
                 it = queue.erase(it);
@@ -237,9 +314,18 @@ struct ServeLoop::Impl {
                 ++it;
             }
         }
+        const bool solo = solo_next;
+        solo_next = false;
+        if (batch_bytes(sh, s.sc.gq_records) > room && any_busy()) {
+            // the head alone does not fit beside the running batches: wait for them
+            requeue(batch);
+            mem_wait = true;
+            return;
+        }
         s.busy = true;
         s.batch = batch;
         s.kind = head->kind;
+        s.held = 0;
         lk.unlock();
         mrv_status err = MRV_OK;
         std::string msg;
@@ -255,17 +341,45 @@ struct ServeLoop::Impl {
         lk.lock();
         if (err != MRV_OK) {
             (void)hipStreamSynchronize(s.stream);
-            for (auto& r : s.batch) finish(r, RS_ERROR, err, msg);
-            s.batch.clear();
             s.busy = false;
+            if (alloc->arena()) release_slot(s);
+            if (err == MRV_E_NOMEM && (any_busy() || (!solo && s.batch.size() > 1))) {
+                // out of device memory now: back to the queue front, to run when a batch
+                // returns memory, or one at a time when none is running
+                requeue(s.batch);
+                if (any_busy()) mem_wait = true;
+                else solo_next = true;
+            } else {
+                for (auto& r : s.batch) finish(r, RS_ERROR, err, msg);
+            }
+            s.batch.clear();
         }
+    }
+
+    void requeue(std::vector<std::shared_ptr<Req>>& batch)
+    {
+        for (auto it = batch.rbegin(); it != batch.rend(); ++it) {
+            (*it)->state = RS_QUEUED;
+            queue.push_front(*it);
+        }
+        batch.clear();
+    }
+
+    // Give the slot's device memory back to the allocator (its events and pinned
+    // staging stay).
+    void release_slot(Slot& s)
+    {
+        s.sc.release_buffers();
+        s.d_in.release();
+        s.d_out.release();
+        s.held = 0;
     }
 
     void stage_and_run(Slot& s)
     {
         const auto& head = s.batch.front();
         const int stride = head->dof_stride;
-        long long n_wp = 0, max_T = 1, n_paths = 0;
+        long long n_wp = 0, max_T = 1;
         int nq = 0, min_chunk = 1 << 30;
         size_t lds = 0;
         s.q_off.clear();
@@ -273,20 +387,16 @@ struct ServeLoop::Impl {
             s.q_off.push_back(nq);
             nq += r->n_queries;
             n_wp += (long long)r->wp_t.size();
-            n_paths += (long long)r->n_queries * r->n_robots;
             max_T = std::max(max_T, r->max_T);
             min_chunk = std::min(min_chunk, r->refs.chunk);
             lds = std::max(lds, r->refs.lds);
         }
         // one pinned block: wp_begin | wp_t | wp_q | q_team | q_env | q_pathoff | q_focus
-        auto align = [](size_t v) { return (v + 255) & ~size_t(255); };
-        const size_t nb = (size_t)(n_paths + 1) * sizeof(long long);
-        const size_t nt = (size_t)n_wp * sizeof(int);
-        const size_t nqb = (size_t)n_wp * stride * sizeof(double);
-        const size_t o_t = align(nb), o_q = align(o_t + nt), o_team = align(o_q + nqb);
-        const size_t o_env = align(o_team + (size_t)nq * 8), o_po = align(o_env + (size_t)nq * 8);
-        const size_t o_fo = align(o_po + (size_t)nq * 8);
-        const size_t total = o_fo + (size_t)nq * 4;
+        BatchShape sh;
+        for (auto& r : s.batch) sh.add(*r);
+        const InputLayout L(sh);
+        const size_t o_t = L.o_t, o_q = L.o_q, o_team = L.o_team, o_env = L.o_env, o_po = L.o_po, o_fo = L.o_fo;
+        const size_t total = L.total;
         const size_t nout = s.kind == 0 ? (size_t)nq : (size_t)nq * 12;
         s.h_in.ensure(total);
         s.h_out.ensure(nout + 64);
@@ -319,6 +429,8 @@ struct ServeLoop::Impl {
         hb[pbase] = wbase;
         s.d_in.ensure(total);
         s.d_out.ensure(nout);
+        ensure_scratch(s.sc, (size_t)tile_bins(max_T, min_chunk), (size_t)nq, s.stream);
+        s.held = s.sc.bytes() + s.d_in.cap + s.d_out.cap;
         char* d = (char*)s.d_in.p;
         HIPCHK(hipSetDevice(device));
         HIPCHK(hipMemcpyAsync(d, h, total, hipMemcpyHostToDevice, s.stream));
@@ -378,6 +490,8 @@ struct ServeLoop::Impl {
             }
             if (again) return;
         }
+        if (alloc->arena()) release_slot(s);
+        mem_wait = false;            // memory came back: admissions resume
         for (size_t k = 0; k < s.batch.size(); ++k) {
             auto& r = s.batch[k];
             const size_t off = (size_t)s.q_off[k] * per;
@@ -398,8 +512,9 @@ struct ServeLoop::Impl {
     }
 };
 
-ServeLoop::ServeLoop(mrv_ctx ctx, int device, int max_inflight, size_t budget_bytes, size_t recheck_records)
-    : impl_(new Impl(ctx, device, max_inflight, budget_bytes, recheck_records))
+ServeLoop::ServeLoop(mrv_ctx ctx, int device, int max_inflight, size_t budget_bytes, size_t recheck_records,
+                     DevAlloc* alloc)
+    : impl_(new Impl(ctx, device, max_inflight, budget_bytes, recheck_records, alloc))
 {
 }
 
@@ -429,7 +544,15 @@ mrv_status ServeLoop::submit(const mrv_request& req, const ServeRefs& refs, uint
         for (size_t i = 0; i < np; ++i)
             r->max_T = std::max<long long>(r->max_T, (long long)r->wp_t[r->wp_begin[i + 1] - 1] + 1);
     }
-    if (r->bytes() > impl_->budget) return MRV_E_NOMEM;
+    {
+        // the request alone must fit the serving budget and the allocator's capacity
+        BatchShape one;
+        one.add(*r);
+        const size_t need = batch_bytes(one, impl_->recheck_records);
+        size_t cap = 0;
+        impl_->alloc->stats(nullptr, nullptr, &cap);
+        if (need > impl_->budget || (impl_->alloc->arena() && need > cap)) return MRV_E_NOMEM;
+    }
     std::lock_guard<std::mutex> lk(impl_->mu);
     if (impl_->inflight >= impl_->max_inflight) return MRV_E_BUSY;
     r->id = impl_->next_id++;

@@ -28,7 +28,7 @@ EXPORTS = ["mrv_create", "mrv_destroy", "mrv_last_error", "mrv_load_team", "mrv_
            "mrv_mv", "mrv_ffc", "mrv_mv_device", "mrv_ffc_device", "mrv_sync", "mrv_motion_steps",
            "mrv_set_tiling", "mrv_get_tiling", "mrv_last_stats", "mrv_submit", "mrv_poll", "mrv_wait",
            "mrv_cancel", "mrv_autotune", "mrv_graph_create", "mrv_graph_launch", "mrv_graph_destroy",
-           "mrv_spheres", "mrv_mv_focus", "mrv_mv_focus_device"]
+           "mrv_spheres", "mrv_mv_focus", "mrv_mv_focus_device", "mrv_memory_stats"]
 
 
 class MrvError(RuntimeError):
@@ -38,7 +38,8 @@ class MrvError(RuntimeError):
 
 
 class CtxOpts(C.Structure):
-    _fields_ = [("device", C.c_int32), ("stream", C.c_void_p), ("near_eps", C.c_double),
+    _fields_ = [("device", C.c_int32), ("stream", C.c_void_p), ("device_arena", C.c_void_p),
+                ("arena_bytes", C.c_size_t), ("near_eps", C.c_double),
                 ("max_inflight", C.c_int32), ("serve_bytes", C.c_size_t), ("recheck_records", C.c_int64),
                 ("flags", C.c_uint32)]
 
@@ -122,6 +123,7 @@ def lib():
                 "mrv_graph_launch": [P, P],
                 "mrv_graph_destroy": [P, P],
                 "mrv_spheres": [P, I32, C.POINTER(PathsDesc), I32, P, P, P],
+                "mrv_memory_stats": [P, P, P, P],
             }
             for name, args in sig.items():
                 f = getattr(L, name)
@@ -183,13 +185,27 @@ class DevicePaths:
 
 
 class Context:
+    """device_arena: a torch uint8 CUDA tensor whose memory the library sub-allocates
+    for every device buffer of the context (kept alive by the context)."""
+
     def __init__(self, device: int = 0, stream=None, near_eps: float = 0.0, max_inflight: int = 0,
-                 serve_bytes: int = 0, recheck_records: int = 0):
+                 serve_bytes: int = 0, recheck_records: int = 0, device_arena=None):
         self._keep = []
+        arena_ptr, arena_bytes = None, 0
+        if device_arena is not None:
+            arena_ptr, arena_bytes = device_arena.data_ptr(), device_arena.numel() * device_arena.element_size()
+            self._keep.append(device_arena)
         h = C.c_void_p()
-        opts = CtxOpts(device, stream, near_eps, max_inflight, serve_bytes, recheck_records, 0)
+        opts = CtxOpts(device, stream, arena_ptr, arena_bytes, near_eps, max_inflight, serve_bytes,
+                       recheck_records, 0)
         check(lib().mrv_create(C.byref(opts), C.byref(h)))
         self.h = h
+
+    def memory_stats(self) -> dict:
+        """Device bytes now allocated, the most allocated at once, the arena's usable size."""
+        v = [C.c_size_t() for _ in range(3)]
+        check(lib().mrv_memory_stats(self.h, *[C.byref(x) for x in v]))
+        return dict(used=v[0].value, peak=v[1].value, capacity=v[2].value)
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:

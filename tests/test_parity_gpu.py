@@ -243,32 +243,55 @@ def test_maximum_length_queries(ctx):
 
 
 def test_invalid_inputs_rejected(ctx):
+    """Malformed inputs are rejected before any device work, and the caller's
+    outputs are left untouched (checked through the raw C entry points with
+    outputs pre-filled with a sentinel)."""
+    import ctypes as C
+    import torch
     say("invalid inputs")
+    L = mrv.lib()
     w = W.arms_workload(8)
     team, env = ctx.load_team(w.team), ctx.load_env(w.env)
     bad = W.paths_from_lists([[w.paths.path(q, r) for r in range(4)] for q in range(8)], 7)
     bad.wp_t = bad.wp_t.copy()
     bad.wp_t[1] = 0          # non-increasing time in the first path
+    hb, hg = mrv.HostPaths(bad), mrv.HostPaths(w.paths)
     out = np.full(8, 7, np.uint8)
-    with pytest.raises(mrv.MrvError) as e:
-        ctx.mv(team, env, bad, mrv.CHECK_ENV)
-    assert e.value.status == mrv.MRV_E_INVALID
-    with pytest.raises(mrv.MrvError) as e:
-        ctx.mv(team + 1000, env, w.paths, mrv.CHECK_ENV)
-    assert e.value.status == mrv.MRV_E_HANDLE
-    with pytest.raises(mrv.MrvError) as e:
-        ctx.mv(team, env, w.paths, mrv.CHECK_ENV | mrv.PAIRS_FIRST | mrv.OBSTACLES_FIRST)
-    assert e.value.status == mrv.MRV_E_INVALID
-    # the device path flags the malformed query and reports at sync
-    import torch
+    assert L.mrv_mv(ctx.h, team, env, C.byref(hb.desc), mrv.CHECK_ENV, out.ctypes.data) == mrv.MRV_E_INVALID
+    assert np.all(out == 7)
+    assert L.mrv_mv(ctx.h, team + 1000, env, C.byref(hg.desc), mrv.CHECK_ENV, out.ctypes.data) == mrv.MRV_E_HANDLE
+    assert np.all(out == 7)
+    assert L.mrv_mv(ctx.h, team, env, C.byref(hg.desc), mrv.CHECK_ENV | mrv.PAIRS_FIRST | mrv.OBSTACLES_FIRST,
+                    out.ctypes.data) == mrv.MRV_E_INVALID
+    assert np.all(out == 7)
+    assert L.mrv_mv(ctx.h, team, env, C.byref(hg.desc), 1 << 20, out.ctypes.data) == mrv.MRV_E_INVALID
+    assert np.all(out == 7)
+    assert L.mrv_mv_focus(ctx.h, team, env, C.byref(hb.desc), mrv.CHECK_ENV, 1, out.ctypes.data) == mrv.MRV_E_INVALID
+    assert np.all(out == 7)
+    cf = np.full((8, 3), 7, np.int32)
+    assert L.mrv_ffc(ctx.h, team, C.byref(hb.desc), 0, cf.ctypes.data) == mrv.MRV_E_INVALID
+    assert np.all(cf == 7)
+    assert L.mrv_ffc(ctx.h, team + 1000, C.byref(hg.desc), 0, cf.ctypes.data) == mrv.MRV_E_HANDLE
+    assert np.all(cf == 7)
+    # a sound call still works afterwards
+    assert np.array_equal(ctx.mv(team, env, w.paths, mrv.CHECK_ENV),
+                          oracle.mv(oracle.Team(w.team), oracle.Env(w.env), oracle.Paths(w.paths)))
+    # device calls: argument errors leave the output untouched as well
+    dg = mrv.DevicePaths(w.paths)
+    o = torch.full((8,), 7, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    assert L.mrv_mv_device(ctx.h, team, env, C.byref(dg.desc), mrv.PAIRS_FIRST | mrv.OBSTACLES_FIRST,
+                           o.data_ptr()) == mrv.MRV_E_INVALID
+    assert L.mrv_mv_device(ctx.h, team + 1000, env, C.byref(dg.desc), 0, o.data_ptr()) == mrv.MRV_E_HANDLE
+    ctx.sync()
+    assert np.all(o.cpu().numpy() == 7)
+    # malformed path data on the device: the query is flagged and reported at sync
     dp = mrv.DevicePaths(bad)
-    o = torch.zeros(8, dtype=torch.uint8, device="cuda")
     ctx.mv_device(team, env, dp, mrv.CHECK_ENV, o.data_ptr())
     with pytest.raises(mrv.MrvError):
         ctx.sync()
     assert o.cpu().numpy()[0] == 2
     ctx.sync()   # error reported once
-    del out
 
 
 @pytest.mark.parametrize("value", [float("nan"), float("inf"), 2.0e6])
