@@ -221,6 +221,27 @@ mrv_status mrv_mv_device(mrv_ctx ctx, int32_t team, int32_t env, const mrv_paths
 mrv_status mrv_ffc_device(mrv_ctx ctx, int32_t team, const mrv_paths* paths, uint32_t flags,
                           mrv_conflict* out);
 
+/* Allocation-free MV, for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.  As
+ * mrv_mv_device (same arguments, answers and asynchrony), but the call's scratch
+ * (control words, tile enumeration, per-query state, near-contact queue) lives
+ * in one fixed array of about 29 MiB (at most 30 MiB) that the library holds on
+ * every device it runs on until the process ends, and the call neither allocates
+ * nor frees device memory.  Limits: n_queries <= MRV_NOALLOC_MAX_QUERIES
+ * (larger calls fail with MRV_E_INVALID and leave valid_out untouched); the
+ * near-contact queue holds MRV_NOALLOC_RECHECK_RECORDS tests, and a query whose
+ * answer depends on a test that did not fit gets valid_out = 3 (repeat it with
+ * mrv_mv_device).  A query with malformed path data gets valid_out = 2.  Neither
+ * is reported by mrv_sync, and mrv_last_stats does not describe these calls.
+ * Every call on a device shares that device's array and leaves its contents
+ * behind (each call clears what must start at zero): calls that overlap on one
+ * device, from any context or thread, race and give undefined results, so
+ * order them on one stream or synchronise between them. */
+#define MRV_NOALLOC_MAX_QUERIES (1 << 18)
+#define MRV_NOALLOC_RECHECK_RECORDS (1 << 18)
+mrv_status mrv_mv_device_noalloc(mrv_ctx ctx, int32_t team, int32_t env, const mrv_paths* paths,
+                                 uint32_t flags, uint8_t* valid_out);
+
 /* Prioritised MV (the PP-ST-RRT use of MV in §III-C: a robot is planned against
  * the fixed paths of higher-priority robots).  As mrv_mv / mrv_mv_device, but
  * only the robots in `focus` (bit r = robot r of the team) are validated: their

@@ -907,6 +907,56 @@ void device_call(mrv_ctx ctx, int team, int env, int kind, const mrv_paths* p, u
     run_plan(ctx, ctx->sc, single_plan(tm, ev, kind, flags, dp, MRV_MAX_T, focus), out_dev, ctx->stream);
 }
 
+// Scratch view over the fixed per-device array (layout in mrv_internal.hpp), with
+// `bins` tile-count bins.
+ScratchView noalloc_view(void* base, size_t bins)
+{
+    char* b = (char*)base;
+    ScratchView v{};
+    v.ctrl = (int*)b;
+    v.hist = (int*)(b + kNaHist);
+    v.start = (int*)(b + kNaStart);
+    v.off = (int*)(b + kNaOff);
+    v.bins = bins;
+    int** q[] = {&v.q_T, &v.q_nt, &v.q_g, &v.q_chunk, (int**)&v.q_eps, &v.q_status, (int**)&v.q_word,
+                 (int**)&v.q_drop, &v.q_sorted};
+    for (size_t k = 0; k < 9; ++k) *q[k] = (int*)(b + kNaQuery + k * kNaQueryBytes);
+    v.gq = (int4*)(b + kNaRecheck);
+    v.gq_records = MRV_NOALLOC_RECHECK_RECORDS;
+    return v;
+}
+
+// mrv_mv_device on the fixed scratch: no device memory is allocated or freed.  The
+// handles' descriptors are read in place under the handle lock (no copies).
+void noalloc_call(mrv_ctx ctx, int team, int env, const mrv_paths* p, uint32_t flags, void* out_dev)
+{
+    set_device(ctx);
+    if (!p) throw Err{MRV_E_INVALID, "null paths"};
+    if (p->n_queries < 0) throw Err{MRV_E_INVALID, "negative n_queries"};
+    if (p->n_queries > MRV_NOALLOC_MAX_QUERIES)
+        throw Err{MRV_E_INVALID, "n_queries above MRV_NOALLOC_MAX_QUERIES; use mrv_mv_device"};
+    if (p->n_queries == 0) return;
+    if (!p->wp_begin || !p->wp_t || !p->wp_q || !out_dev) throw Err{MRV_E_INVALID, "null device pointer"};
+    if (p->n_wp < 1) throw Err{MRV_E_INVALID, "n_wp must be positive"};
+    void* base = noalloc_scratch(ctx->device);
+    if (!base) throw Err{MRV_E_DEVICE, "fixed scratch is not set up on the context's device"};
+    CallPlan pl{};
+    {
+        std::lock_guard<std::mutex> lk(ctx->handle_mu);
+        const TeamHost& tm = find_team(ctx, team);
+        const EnvHost* ev = find_env(ctx, env);
+        if (p->dof_stride < tm.max_dof) throw Err{MRV_E_INVALID, "dof_stride smaller than the team's largest dof"};
+        const DevPaths dp{(const long long*)p->wp_begin, p->wp_t, p->wp_q, p->n_wp, p->n_queries, p->dof_stride};
+        pl = single_plan(tm, ev, 0, flags, dp, MRV_MAX_T);
+    }
+    const size_t bins = (size_t)tile_bins(MRV_MAX_T, std::max(1, pl.min_chunk));
+    if (bins > kNaBins) throw Err{MRV_E_DEVICE, "tile bins beyond the fixed scratch"};   // chunk >= 1: never
+    // control words and the bins this call may touch start at zero (k_scan leaves the
+    // bins zero again, but an earlier call may not have run to its end)
+    HIPCHK(fill_u32(base, 0u, (kNaHist + bins * sizeof(int)) / 4, ctx->stream));
+    launch_plan(ctx, noalloc_view(base, bins), pl, out_dev, ctx->stream, nullptr, nullptr);
+}
+
 uint32_t check_flags(int kind, uint32_t flags)
 {
     const uint32_t known = MRV_CHECK_ENV | MRV_EXHAUSTIVE | MRV_HIERARCHICAL | MRV_ORDER_RAKE | MRV_ORDER_LINEAR |
@@ -974,6 +1024,8 @@ mrv_status mrv_create(const mrv_ctx_opts* opts, mrv_ctx* out)
         hipDeviceProp_t prop;
         HIPCHK(hipGetDeviceProperties(&prop, dev));
         c->n_cu = prop.multiProcessorCount;
+        // the device's fixed scratch (mrv_mv_device_noalloc), looked up once per device
+        HIPCHK(noalloc_scratch_setup(dev));
         if (opts && opts->near_eps > 0) c->eps = opts->near_eps;
         if (!(c->eps < 1e-2)) throw Err{MRV_E_INVALID, "near_eps must be < 0.01 m"};
         if (opts && opts->max_inflight > 0) c->max_inflight = opts->max_inflight;
@@ -1118,6 +1170,16 @@ mrv_status mrv_ffc(mrv_ctx ctx, int32_t team, const mrv_paths* paths, uint32_t f
     return wrap([&] {
         const uint32_t f = check_flags(1, flags);
         host_call(ctx, team, -1, 1, paths, f, out);
+    });
+}
+
+mrv_status mrv_mv_device_noalloc(mrv_ctx ctx, int32_t team, int32_t env, const mrv_paths* paths, uint32_t flags,
+                                 uint8_t* valid_out)
+{
+    if (guard(ctx)) return MRV_E_HANDLE;
+    return wrap([&] {
+        const uint32_t f = check_flags(0, flags);
+        noalloc_call(ctx, team, env, paths, f, valid_out);
     });
 }
 

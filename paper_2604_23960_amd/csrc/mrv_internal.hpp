@@ -3,8 +3,10 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <cstddef>
 #include <cstdint>
 
+#include "../../include/mrv.h"
 #include "mrv_tiles.hpp"
 
 namespace mrv {
@@ -26,6 +28,22 @@ constexpr int kExhWGsPerCU = 7;     // the same for the exhaustive MV kernel (72
 // The near band of a query widens in proportion to the largest coordinate magnitude
 // its FP32 arithmetic sees beyond this scale (metres); see k_query_info.
 constexpr double kEpsRefScale = 4.0;
+
+// Fixed scratch of mrv_mv_device_noalloc, one array per device (byte offsets):
+// control words as in every call's scratch, then the tile-count bins (hist,
+// start, off) of any call, tile_bins(MRV_MAX_T, 1) of them, so the hist bins
+// directly follow the control words and one fill clears both; nine per-query
+// arrays of MRV_NOALLOC_MAX_QUERIES entries; the near-contact queue.
+constexpr size_t na_align(size_t v) { return (v + 255) & ~size_t(255); }
+constexpr size_t kNaBins = (size_t)MRV_MAX_T + 2;
+constexpr size_t kNaHist = 256;
+constexpr size_t kNaStart = kNaHist + na_align(kNaBins * 4);
+constexpr size_t kNaOff = kNaStart + na_align(kNaBins * 4);
+constexpr size_t kNaQuery = kNaOff + na_align(kNaBins * 8);
+constexpr size_t kNaQueryBytes = na_align((size_t)MRV_NOALLOC_MAX_QUERIES * 4);
+constexpr size_t kNaRecheck = kNaQuery + 9 * kNaQueryBytes;
+constexpr size_t kNoAllocScratchBytes = kNaRecheck + (size_t)MRV_NOALLOC_RECHECK_RECORDS * 16;
+static_assert(kNoAllocScratchBytes <= (size_t(30) << 20), "fixed scratch above its stated bound of 30 MiB");
 
 enum RecheckKind : int { RK_RR = 0, RK_SELF = 1, RK_ENV_SPH = 2, RK_ENV_BOX = 3, RK_ENV_CYL = 4, RK_ENV_PT = 5 };
 
@@ -178,5 +196,10 @@ inline int validate_variant(const CallDev& cd)
     return exh ? 3 : 0;
 }
 int validate_blocks_per_cu(int variant, size_t lds_bytes);
+// Device address of the fixed scratch on `device`.  noalloc_scratch_setup looks it
+// up once per device (that device current) and keeps it; noalloc_scratch returns
+// the kept address, null before set-up.
+hipError_t noalloc_scratch_setup(int device);
+void* noalloc_scratch(int device);
 
 }  // namespace mrv

@@ -25,6 +25,7 @@
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
+#include <mutex>
 
 #include "../../include/mrv.h"
 #include "mrv_internal.hpp"
@@ -1417,6 +1418,46 @@ hipError_t launch_spheres(const CallDev& cd, const int* st_q, const int* st_t, i
     const unsigned blocks = (unsigned)std::min(n_states, 4096);
     hipLaunchKernelGGL(k_spheres, dim3(blocks), dim3(64), (size_t)F * 48, stream, cd, st_q, st_t, n_states, out, S);
     return hipGetLastError();
+}
+
+}  // namespace mrv
+
+// The fixed scratch of mrv_mv_device_noalloc (layout in mrv_internal.hpp).  Each
+// device holds its own copy from module load until the process ends.  Host code
+// never passes this name to a kernel: it stands for no device address there.
+// Kernels get the address that noalloc_scratch_setup looked up for the device.
+static __device__ __align__(256) unsigned char scratch[mrv::kNoAllocScratchBytes];
+
+namespace mrv {
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch_setup(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;       // the caller makes `device` current
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = p;
+    return hipSuccess;
+}
+
+void* noalloc_scratch(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[device];
 }
 
 int validate_blocks_per_cu(int kind, size_t lds_bytes)

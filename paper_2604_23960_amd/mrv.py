@@ -23,12 +23,13 @@ CHECK_ENV, EXHAUSTIVE, HIERARCHICAL = 1, 2, 4
 ORDER_BISECT, ORDER_RAKE, ORDER_LINEAR = 0, 8, 16
 PAIRS_FIRST, OBSTACLES_FIRST = 32, 64
 MAX_T = 1 << 20
+NOALLOC_MAX_QUERIES = 1 << 18
 
 EXPORTS = ["mrv_create", "mrv_destroy", "mrv_last_error", "mrv_load_team", "mrv_load_env", "mrv_unload",
            "mrv_mv", "mrv_ffc", "mrv_mv_device", "mrv_ffc_device", "mrv_sync", "mrv_motion_steps",
            "mrv_set_tiling", "mrv_get_tiling", "mrv_last_stats", "mrv_submit", "mrv_poll", "mrv_wait",
            "mrv_cancel", "mrv_autotune", "mrv_graph_create", "mrv_graph_launch", "mrv_graph_destroy",
-           "mrv_spheres", "mrv_mv_focus", "mrv_mv_focus_device", "mrv_memory_stats"]
+           "mrv_spheres", "mrv_mv_focus", "mrv_mv_focus_device", "mrv_memory_stats", "mrv_mv_device_noalloc"]
 
 
 class MrvError(RuntimeError):
@@ -107,6 +108,7 @@ def lib():
                 "mrv_mv": [P, I32, I32, C.POINTER(PathsDesc), U32, P],
                 "mrv_ffc": [P, I32, C.POINTER(PathsDesc), U32, P],
                 "mrv_mv_device": [P, I32, I32, C.POINTER(PathsDesc), U32, P],
+                "mrv_mv_device_noalloc": [P, I32, I32, C.POINTER(PathsDesc), U32, P],
                 "mrv_mv_focus": [P, I32, I32, C.POINTER(PathsDesc), U32, U32, P],
                 "mrv_mv_focus_device": [P, I32, I32, C.POINTER(PathsDesc), U32, U32, P],
                 "mrv_ffc_device": [P, I32, C.POINTER(PathsDesc), U32, P],
@@ -286,6 +288,10 @@ class Context:
             check(lib().mrv_mv_focus_device(self.h, team, env, C.byref(dpaths.desc), flags, focus, out_ptr))
         else:
             check(lib().mrv_mv_device(self.h, team, env, C.byref(dpaths.desc), flags, out_ptr))
+
+    def mv_device_noalloc(self, team: int, env: int, dpaths: DevicePaths, flags: int, out_ptr: int):
+        """mv_device with the library's fixed per-device scratch: allocates nothing."""
+        check(lib().mrv_mv_device_noalloc(self.h, team, env, C.byref(dpaths.desc), flags, out_ptr))
 
     def ffc_device(self, team: int, dpaths: DevicePaths, flags: int, out_ptr: int):
         check(lib().mrv_ffc_device(self.h, team, C.byref(dpaths.desc), flags, out_ptr))
