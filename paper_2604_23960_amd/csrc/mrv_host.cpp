@@ -134,7 +134,7 @@ int build_team(mrv_ctx ctx, const mrv_robot_desc* robots, int n, TeamHost& out)
     std::vector<int> r_nj(n), r_joint_off(n), r_sphere_off(n + 1, 0), r_frame_off(n);
     std::vector<float> base32(n * 12);
     std::vector<double> base64(n * 12);
-    std::vector<int> j_type;
+    std::vector<int> j_type, j_robot;
     std::vector<float> j32;
     std::vector<double> j64;
     std::vector<int> s_robot, s_slot, s_lframe;
@@ -172,6 +172,7 @@ int build_team(mrv_ctx ctx, const mrv_robot_desc* robots, int n, TeamHost& out)
             int jt = R.joint_type[j];
             if (jt < MRV_REV_Z || jt > MRV_PRI_Z) throw Err{MRV_E_INVALID, who + "unknown joint type"};
             j_type.push_back(jt);
+            j_robot.push_back(r);
             for (int i = 0; i < 12; ++i) {
                 j32.push_back((float)R.joint_fixed[j * 12 + i]);
                 j64.push_back(R.joint_fixed[j * 12 + i]);
@@ -217,11 +218,15 @@ int build_team(mrv_ctx ctx, const mrv_robot_desc* robots, int n, TeamHost& out)
     r_group_off[n] = G;
     // slots: 16 per group, unused ones padded, so a group is one 16-wide MFMA operand
     const int GS = G * 16;
-    std::vector<int> slot_sphere(GS, -1), sphere_slot(S);
+    std::vector<int> slot_sphere(GS, -1), sphere_slot(S), slot_frame(GS, -1);
+    std::vector<float> slot_local((size_t)GS * 4, 0.f);
     for (int g = 0; g < G; ++g)
         for (int s2 = g_range[2 * g]; s2 < g_range[2 * g + 1]; ++s2) {
-            slot_sphere[g * 16 + (s2 - g_range[2 * g])] = s2;
-            sphere_slot[s2] = g * 16 + (s2 - g_range[2 * g]);
+            const int sl = g * 16 + (s2 - g_range[2 * g]);
+            slot_sphere[sl] = s2;
+            sphere_slot[s2] = sl;
+            slot_frame[sl] = s_slot[s2];
+            for (int i = 0; i < 4; ++i) slot_local[(size_t)sl * 4 + i] = s_local32[(size_t)s2 * 4 + i];
         }
     // self blocks: for each pair of groups (ga <= gb) holding self pairs, one lane
     // mask per accumulator register r: bit l set when the pair (row 4 (l / 16) + r
@@ -315,7 +320,8 @@ int build_team(mrv_ctx ctx, const mrv_robot_desc* robots, int n, TeamHost& out)
                  o_ss = pk.add(s_slot), o_sl = pk.add(s_lframe), o_l32 = pk.add(s_local32),
                  o_l64 = pk.add(s_local64), o_rt = pk.add(gtask), o_sg = pk.add(s_group),
                  o_gr = pk.add(g_range), o_rg = pk.add(r_group_off), o_ss2 = pk.add(slot_sphere),
-                 o_sb = pk.add(sblocks), o_sm = pk.add(sb_mask), o_rm = pk.add(r_mag);
+                 o_sb = pk.add(sblocks), o_sm = pk.add(sb_mask), o_rm = pk.add(r_mag),
+                 o_jr = pk.add(j_robot), o_sf = pk.add(slot_frame), o_slc = pk.add(slot_local);
     const TeamDev blank{};
     const size_t o_self = pk.add(&blank, sizeof(TeamDev));
     void* d = nullptr;
@@ -329,7 +335,11 @@ int build_team(mrv_ctx ctx, const mrv_robot_desc* robots, int n, TeamHost& out)
     t.n_sblocks = (int)sblocks.size() / 8;
     t.GS = GS;
     t.GSp = GS + 16;
-    t.TS = std::max(5 * t.GSp, 3 * t.GSp + 12 * F);
+    t.J = (int)j_type.size();
+    // a timestep's LDS slice holds, over one tile: the joint transforms (start) and
+    // the frames (tail) during forward kinematics, then the x, y, z rows over the
+    // transforms while the frames are read, then the radius and w rows over the frames
+    t.TS = std::max({5 * t.GSp, 3 * t.GSp + 12 * F, 12 * (t.J + F)});
     t.P = n * (n - 1) / 2;
     t.max_dof = max_dof;
     t.G = G;
@@ -352,6 +362,7 @@ int build_team(mrv_ctx ctx, const mrv_robot_desc* robots, int n, TeamHost& out)
     t.r_base32 = (const float*)at(o_b32);
     t.r_base64 = (const double*)at(o_b64);
     t.j_type = (const int*)at(o_jt);
+    t.j_robot = (const int*)at(o_jr);
     t.j_fixed32 = (const float*)at(o_j32);
     t.j_fixed64 = (const double*)at(o_j64);
     t.s_robot = (const int*)at(o_sr);
@@ -361,6 +372,8 @@ int build_team(mrv_ctx ctx, const mrv_robot_desc* robots, int n, TeamHost& out)
     t.s_local64 = (const double*)at(o_l64);
     t.gtask = (const int*)at(o_rt);
     t.slot_sphere = (const int*)at(o_ss2);
+    t.slot_frame = (const int*)at(o_sf);
+    t.slot_local = (const float4*)at(o_slc);
     t.sblocks = (const int*)at(o_sb);
     t.sb_mask = (const unsigned long long*)at(o_sm);
     out.dmem = d;
@@ -1361,7 +1374,7 @@ mrv_status mrv_spheres(mrv_ctx ctx, int32_t team, const mrv_paths* paths, int32_
             cd.wp_t = (const int*)ctx->in_t.p;
             cd.wp_q = (const double*)ctx->in_q.p;
             HIPCHK(launch_spheres(cd, (const int*)st.p, (const int*)st.p + n_states, n_states, (float4*)o.p, S,
-                                  tm.dev.F, ctx->stream));
+                                  tm.dev.F + tm.dev.J, ctx->stream));
             HIPCHK(hipMemcpyAsync(out, o.p, nout, hipMemcpyDeviceToHost, ctx->stream));
             HIPCHK(hipStreamSynchronize(ctx->stream));
         } catch (...) {

@@ -59,6 +59,7 @@ struct TeamDev {
     int n_robots;
     int S;                 // total spheres
     int F;                 // frame slots per timestep: sum over robots of (n_joints + 1)
+    int J;                 // joints of the team (the sum of n_joints)
     int n_self;            // distinct self-collision pairs
     int n_sblocks;         // 16 x 16 self blocks per timestep
     int P;                 // robot pairs n(n-1)/2
@@ -66,7 +67,8 @@ struct TeamDev {
     int G;                 // sphere groups per timestep (16 consecutive spheres of one robot)
     int GS;                // sphere slots, 16 per group
     int GSp;               // LDS row stride of the slot arrays (GS + 16, against bank conflicts)
-    int TS;                // LDS floats per timestep of a tile: five slot rows, or three and the FK frames
+    int TS;                // LDS floats per timestep of a tile: five slot rows, or three and the FK frames,
+                           // or the joint transforms and the frames, whichever is largest
     int chunk[2][2];       // timesteps per tile: [MV / FFC][early-terminating / exhaustive]
     int lds_per_t;         // LDS bytes one timestep of a tile needs
     float r_max;           // largest sphere radius of the team
@@ -84,6 +86,7 @@ struct TeamDev {
     const float* r_base32;      // [n][12]
     const double* r_base64;     // [n][12]
     const int* j_type;          // [joints]
+    const int* j_robot;         // [joints] robot of each joint
     const float* j_fixed32;     // [joints][12]
     const double* j_fixed64;    // [joints][12]
     const int* s_robot;         // [S]
@@ -97,6 +100,8 @@ struct TeamDev {
     const int* gtask;           // [G][8] pair task of group ga: ga, its robot, self blocks [sb0, sb1),
                                 // first group of the higher robots, robot-robot tests, self tests, 0
     const int* slot_sphere;     // [GS] sphere of each slot, -1 for padding
+    const int* slot_frame;      // [GS] frame slot of each slot's sphere, -1 for padding
+    const float4* slot_local;   // [GS] local centre and radius of each slot's sphere, zeros for padding
     const int* sblocks;         // [n_sblocks][8] row group, column group, pairs, robot, 0, 0, 0, 0
     const unsigned long long* sb_mask;   // [n_sblocks][4] lane masks, one per accumulator register
 };
@@ -182,8 +187,9 @@ hipError_t launch_prepare(const CallDev& cd, hipStream_t stream);
 hipError_t launch_validate(const CallDev& cd, int grid, hipStream_t stream);
 hipError_t launch_finalize(const CallDev& cd, hipStream_t stream);
 hipError_t fill_u32(void* p, unsigned v, size_t n, hipStream_t stream);
+// n_mats: the team's joints plus frames (J + F), 48 bytes of LDS each.
 hipError_t launch_spheres(const CallDev& cd, const int* st_q, const int* st_t, int n_states, float4* out, int S,
-                          int F, hipStream_t stream);
+                          int n_mats, hipStream_t stream);
 // Occupancy-derived workgroups per CU for the validation kernel.
 // Whether an MV call restricts validation to a focus set (runs the focus kernel).
 inline bool has_focus(const CallDev& cd) { return cd.kind == 0 && (cd.focus0 != 0u || cd.q_focus != nullptr); }

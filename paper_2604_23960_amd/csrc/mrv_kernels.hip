@@ -623,82 +623,75 @@ __device__ bool direct_block(const CallDev& cd, const TeamDev& tm, const float* 
     return hit;
 }
 
-// FP32 frames of robot r at timestep t, relative to the team origin: the
-// configuration is interpolated in FP64 from path waypoints [pb, pe), revolute
-// angles are reduced to [-pi, pi] in FP64, and each value is rounded once; the
-// chain Frame_k = Frame_{k-1} F_k J_k(q_k) then runs in FP32 registers from the
-// base frame (translation relative to the origin).  out receives
-// (n_joints + 1) frames as 3 float4 rows (R row, p) each, the base first.
-__device__ __forceinline__ void robot_frames32(const TeamDev& tm, const CallDev& cd, long long pb, long long pe,
-                                               int r, int t, float4* out)
+// FP32 forward kinematics in two steps (the chain Frame_k = Frame_{k-1} F_k
+// J_k(q_k) of the sphere model, paper §II-B), both relative to the team origin.
+//
+// joint_matrix32: the transform F_j J_j(q_j(t)) of global joint jg at timestep t,
+// as three float4 rows [R | p].  The joint value is interpolated in FP64 from the
+// robot's path waypoints of the query (paths from qp0), a revolute angle is
+// reduced to [-pi, pi] in FP64, and the value is rounded once to FP32.
+__device__ __forceinline__ void joint_matrix32(const TeamDev& tm, const CallDev& cd, long long qp0, int jg, int t,
+                                               float4* out)
 {
+    const int r = tm.j_robot[jg];
+    const int j = jg - tm.r_joint_off[r];
+    const long long pb = cd.wp_begin[qp0 + r], pe = cd.wp_begin[qp0 + r + 1];
     const long long kseg = find_segment(cd.wp_t, pb, pe, t);
-    const bool last = (kseg == pe - 1);
-    double sfrac = 0.0;
-    if (!last) sfrac = (double)(t - cd.wp_t[kseg]) / (double)(cd.wp_t[kseg + 1] - cd.wp_t[kseg]);
-    const int nj = tm.r_nj[r];
-    const int j0 = tm.r_joint_off[r];
-    float qv[kMaxJoints];
-#pragma unroll
-    for (int j = 0; j < kMaxJoints; ++j) {
-        qv[j] = 0.f;
-        if (j < nj) {
-            double qa = cd.wp_q[kseg * cd.dof_stride + j];
-            double qj = qa;
-            if (!last) qj = qa + sfrac * (cd.wp_q[(kseg + 1) * cd.dof_stride + j] - qa);
-            // an angle enters only through sin and cos: take it modulo 2 pi while it
-            // is exact, so its FP32 rounding error stays below 2^-24 pi
-            if (tm.j_type[j0 + j] == MRV_REV_Z) qj = fma(-6.283185307179586, rint(qj * 0.15915494309189535), qj);
-            qv[j] = (float)qj;
-        }
+    double qj = cd.wp_q[kseg * cd.dof_stride + j];
+    if (kseg != pe - 1) {
+        const double sfrac = (double)(t - cd.wp_t[kseg]) / (double)(cd.wp_t[kseg + 1] - cd.wp_t[kseg]);
+        qj = qj + sfrac * (cd.wp_q[(kseg + 1) * cd.dof_stride + j] - qj);
     }
-    float Mx[12];
+    const int jt = tm.j_type[jg];
+    // an angle enters only through sin and cos: take it modulo 2 pi while it is
+    // exact, so its FP32 rounding error stays below 2^-24 pi
+    if (jt == MRV_REV_Z) qj = fma(-6.283185307179586, rint(qj * 0.15915494309189535), qj);
+    const float qf = (float)qj;
+    const float4* Fp = reinterpret_cast<const float4*>(tm.j_fixed32 + (long long)jg * 12);
+    float4 m[3] = { Fp[0], Fp[1], Fp[2] };
+    if (jt == MRV_REV_Z) {
+        // F Rz(q): columns 0 and 1 of F rotated by q
+        float sn, cs;
+        sincosf(qf, &sn, &cs);
 #pragma unroll
-    for (int i = 0; i < 12; ++i) Mx[i] = tm.r_base32[r * 12 + i];
-    out[0] = make_float4(Mx[0], Mx[1], Mx[2], Mx[3]);
-    out[1] = make_float4(Mx[4], Mx[5], Mx[6], Mx[7]);
-    out[2] = make_float4(Mx[8], Mx[9], Mx[10], Mx[11]);
-#pragma unroll
-    for (int j = 0; j < kMaxJoints; ++j) {
-        if (j < nj) {
-            const float* Fj = tm.j_fixed32 + (long long)(j0 + j) * 12;
-            float A[12];
-#pragma unroll
-            for (int row = 0; row < 3; ++row) {
-#pragma unroll
-                for (int col = 0; col < 4; ++col) {
-                    float v = Mx[row * 4 + 0] * Fj[col] + Mx[row * 4 + 1] * Fj[4 + col] + Mx[row * 4 + 2] * Fj[8 + col];
-                    A[row * 4 + col] = (col == 3) ? v + Mx[row * 4 + 3] : v;
-                }
-            }
-            const int jt = tm.j_type[j0 + j];
-            if (jt == MRV_REV_Z) {
-                float sn, cs;
-                sincosf(qv[j], &sn, &cs);
-#pragma unroll
-                for (int row = 0; row < 3; ++row) {
-                    const float a0 = A[row * 4 + 0], a1 = A[row * 4 + 1];
-                    Mx[row * 4 + 0] = a0 * cs + a1 * sn;
-                    Mx[row * 4 + 1] = a1 * cs - a0 * sn;
-                    Mx[row * 4 + 2] = A[row * 4 + 2];
-                    Mx[row * 4 + 3] = A[row * 4 + 3];
-                }
-            } else {
-                const int ax = jt - 1;
-#pragma unroll
-                for (int row = 0; row < 3; ++row) {
-                    const float axv = ax == 0 ? A[row * 4 + 0] : (ax == 1 ? A[row * 4 + 1] : A[row * 4 + 2]);
-                    Mx[row * 4 + 0] = A[row * 4 + 0];
-                    Mx[row * 4 + 1] = A[row * 4 + 1];
-                    Mx[row * 4 + 2] = A[row * 4 + 2];
-                    Mx[row * 4 + 3] = axv * qv[j] + A[row * 4 + 3];
-                }
-            }
-            float4* o = out + (j + 1) * 3;
-            o[0] = make_float4(Mx[0], Mx[1], Mx[2], Mx[3]);
-            o[1] = make_float4(Mx[4], Mx[5], Mx[6], Mx[7]);
-            o[2] = make_float4(Mx[8], Mx[9], Mx[10], Mx[11]);
+        for (int i = 0; i < 3; ++i) {
+            const float a0 = m[i].x, a1 = m[i].y;
+            m[i].x = a0 * cs + a1 * sn;
+            m[i].y = a1 * cs - a0 * sn;
         }
+    } else {
+        // F T(q e_axis): the translation column gains q times that axis' column
+        const int ax = jt - 1;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) m[i].w = fmaf(ax == 0 ? m[i].x : (ax == 1 ? m[i].y : m[i].z), qf, m[i].w);
+    }
+    out[0] = m[0];
+    out[1] = m[1];
+    out[2] = m[2];
+}
+
+// chain_row32: row `row` of every frame of robot r from the joint transforms M of
+// one timestep (three float4 rows per global joint).  Row i of Frame_k depends
+// only on row i of Frame_{k-1}, so the three rows of a chain run on three lanes.
+// frames receives (n_joints + 1) frames as three float4 rows each, the base first.
+__device__ __forceinline__ void chain_row32(const TeamDev& tm, int r, int row, const float4* M, float4* frames)
+{
+    const float4 b = *reinterpret_cast<const float4*>(tm.r_base32 + r * 12 + row * 4);
+    float x = b.x, y = b.y, z = b.z, w = b.w;
+    frames[row] = b;
+    const int nj = tm.r_nj[r];
+    const float4* Mk = M + tm.r_joint_off[r] * 3;
+    for (int k = 0; k < nj; ++k, Mk += 3) {
+        const float4 m0 = Mk[0], m1 = Mk[1], m2 = Mk[2];
+        const float nx = fmaf(z, m2.x, fmaf(y, m1.x, x * m0.x));
+        const float ny = fmaf(z, m2.y, fmaf(y, m1.y, x * m0.y));
+        const float nz = fmaf(z, m2.z, fmaf(y, m1.z, x * m0.z));
+        const float nw = fmaf(z, m2.w, fmaf(y, m1.w, fmaf(x, m0.w, w)));
+        x = nx;
+        y = ny;
+        z = nz;
+        w = nw;
+        frames[(k + 1) * 3 + row] = make_float4(x, y, z, w);
     }
 }
 
@@ -1042,55 +1035,73 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
         const int fr_off = TS - 12 * F;
         float* sp = reinterpret_cast<float*>(dyn);                      // [C][TS]
 
-        // --- configurations and FP32 forward kinematics: one lane per (timestep, robot)
-        for (int idx = tid; idx < nv * n; idx += WG) {
-            const int c = idx / n;
-            const int r = idx - c * n;
-            robot_frames32(tm, cd, cd.wp_begin[qp0 + r], cd.wp_begin[qp0 + r + 1], r, s_t[c],
-                           reinterpret_cast<float4*>(sp + (long long)c * TS + fr_off) + tm.r_frame_off[r] * 3);
+        // --- FP32 forward kinematics.  First each joint's transform, one lane per
+        // (timestep, joint), into the start of the timestep's slice (the x, y, z rows,
+        // written only later); then the chains, one lane per (timestep, robot, frame
+        // row), into the frames at the slice's tail.
+        const int J = tm.J;
+        for (int idx = tid; idx < nv * J; idx += WG) {
+            const int c = idx / J;
+            const int jg = idx - c * J;
+            joint_matrix32(tm, cd, qp0, jg, s_t[c], reinterpret_cast<float4*>(sp + (long long)c * TS) + jg * 3);
+        }
+        __syncthreads();
+        for (int idx = tid; idx < nv * n * 3; idx += WG) {
+            const int c = idx / (3 * n);
+            const int rr = idx - c * 3 * n;
+            const int r = rr / 3;
+            chain_row32(tm, r, rr - 3 * r, reinterpret_cast<const float4*>(sp + (long long)c * TS),
+                        reinterpret_cast<float4*>(sp + (long long)c * TS + fr_off) + tm.r_frame_off[r] * 3);
         }
         __syncthreads();
 
-        // --- sphere centres relative to the team origin, one lane per (timestep, slot);
-        // padding slots sit at the origin
-        for (int idx = tid; idx < nv * GS; idx += WG) {
-            const int c = idx / GS;
-            const int s = idx - c * GS;
-            const int sph = tm.slot_sphere[s];
-            float x = 0.f, y = 0.f, z = 0.f;
-            if (sph >= 0) {
-                const float4 X = place32(reinterpret_cast<const float4*>(sp + (long long)c * TS + fr_off) +
-                                             tm.s_slot[sph] * 3,
-                                         tm.s_local32[sph]);
-                x = X.x;
-                y = X.y;
-                z = X.z;
+        // --- sphere records, slot-major: lane idx keeps slot idx mod GS over the
+        // tile's timesteps c0, c0 + cstep, ... (c0 = idx / GS), so a slot's frame
+        // index and local centre are loaded once per tile.  First the centres
+        // relative to the team origin (padding slots at the origin) ...
+        const int cstep = GS < WG ? WG / GS : 1;
+        const int span = cstep * GS;
+        for (int idx = tid; idx < span; idx += WG) {
+            const int c0 = idx / GS;
+            const int s = idx - c0 * GS;
+            const int fs = tm.slot_frame[s];
+            const float4 L = tm.slot_local[s];
+            for (int c = c0; c < nv; c += cstep) {
+                float x = 0.f, y = 0.f, z = 0.f;
+                if (fs >= 0) {
+                    const float4 X = place32(reinterpret_cast<const float4*>(sp + (long long)c * TS + fr_off) + fs * 3, L);
+                    x = X.x;
+                    y = X.y;
+                    z = X.z;
+                }
+                float* row = sp + (long long)c * TS + s;
+                row[0] = x;
+                row[GSp] = y;
+                row[2 * GSp] = z;
             }
-            float* row = sp + (long long)c * TS + s;
-            row[0] = x;
-            row[GSp] = y;
-            row[2 * GSp] = z;
         }
         __syncthreads();
 
-        // --- radius and w rows, over the frames
+        // ... then, over the frames, the radius and w = |p|^2 - r^2 rows (radius 0 and
+        // w far away for padding)
         {
             float r2max = 0.f;
-            for (int idx = tid; idx < nv * GS; idx += WG) {
-                const int c = idx / GS;
-                const int s = idx - c * GS;
-                const int sph = tm.slot_sphere[s];
-                float* row = sp + (long long)c * TS + s;
-                float r = 0.f, w = kFar;
-                if (sph >= 0) {
-                    const float x = row[0], y = row[GSp], z = row[2 * GSp];
-                    r = tm.s_local32[sph].w;
-                    const float d2 = fmaf(x, x, fmaf(y, y, z * z));
-                    w = fmaf(-r, r, d2);
-                    r2max = fmaxf(r2max, d2);
+            for (int idx = tid; idx < span; idx += WG) {
+                const int c0 = idx / GS;
+                const int s = idx - c0 * GS;
+                const float r = tm.slot_local[s].w;
+                for (int c = c0; c < nv; c += cstep) {
+                    float* row = sp + (long long)c * TS + s;
+                    float w = kFar;
+                    if (r > 0.f) {
+                        const float x = row[0], y = row[GSp], z = row[2 * GSp];
+                        const float d2 = fmaf(x, x, fmaf(y, y, z * z));
+                        w = fmaf(-r, r, d2);
+                        r2max = fmaxf(r2max, d2);
+                    }
+                    row[3 * GSp] = r;
+                    row[4 * GSp] = w;
                 }
-                row[3 * GSp] = r;
-                row[4 * GSp] = w;
             }
             r2max = wave_max_f32(r2max);
             if (lane == 0) atomicMax(&s_rho2, __float_as_uint(r2max));
@@ -1308,11 +1319,16 @@ __global__ void k_spheres(CallDev cd, const int* st_q, const int* st_t, int n_st
         const int q = st_q[k];
         const TeamDev& tm = *team_of(cd, q);
         const long long p0 = path_of(cd, tm.n_robots, q);
-        for (int r = threadIdx.x; r < tm.n_robots; r += blockDim.x)
-            robot_frames32(tm, cd, cd.wp_begin[p0 + r], cd.wp_begin[p0 + r + 1], r, st_t[k], frames + tm.r_frame_off[r] * 3);
+        // the joint transforms first, the frames after them (the same two steps as
+        // the validation kernel)
+        float4* fr = frames + tm.J * 3;
+        for (int jg = threadIdx.x; jg < tm.J; jg += blockDim.x) joint_matrix32(tm, cd, p0, jg, st_t[k], frames + jg * 3);
+        __syncthreads();
+        for (int i = threadIdx.x; i < tm.n_robots * 3; i += blockDim.x)
+            chain_row32(tm, i / 3, i % 3, frames, fr + tm.r_frame_off[i / 3] * 3);
         __syncthreads();
         for (int s = threadIdx.x; s < tm.S; s += blockDim.x) {
-            const float4 X = place32(frames + tm.s_slot[s] * 3, tm.s_local32[s]);
+            const float4 X = place32(fr + tm.s_slot[s] * 3, tm.s_local32[s]);
             out[(long long)k * S_out + s] = make_float4(X.x + tm.origin[0], X.y + tm.origin[1], X.z + tm.origin[2], X.w);
         }
         __syncthreads();
@@ -1412,11 +1428,12 @@ hipError_t launch_finalize(const CallDev& cd, hipStream_t stream)
 }
 
 hipError_t launch_spheres(const CallDev& cd, const int* st_q, const int* st_t, int n_states, float4* out, int S,
-                          int F, hipStream_t stream)
+                          int n_mats, hipStream_t stream)
 {
     if (n_states <= 0) return hipSuccess;
     const unsigned blocks = (unsigned)std::min(n_states, 4096);
-    hipLaunchKernelGGL(k_spheres, dim3(blocks), dim3(64), (size_t)F * 48, stream, cd, st_q, st_t, n_states, out, S);
+    // LDS: the joint transforms and the frames of one timestep, 48 bytes each
+    hipLaunchKernelGGL(k_spheres, dim3(blocks), dim3(64), (size_t)n_mats * 48, stream, cd, st_q, st_t, n_states, out, S);
     return hipGetLastError();
 }
 
