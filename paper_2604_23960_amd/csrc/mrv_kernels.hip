@@ -66,6 +66,20 @@ __device__ __forceinline__ int cload(const int* p) { return *(CInt*)p; }
 __device__ __forceinline__ float cloadf(const float* p) { return *(CFloat*)p; }
 __device__ __forceinline__ unsigned long long cload64(const unsigned long long* p) { return *(CU64*)p; }
 
+// Descriptors read in place through the constant address space (scalar loads).
+// A phase takes its own pointer from at(): the address is opaque to the compiler,
+// so each phase loads the fields it uses where it uses them instead of every
+// field staying in scalar registers for a whole tile.
+typedef const __attribute__((address_space(4))) TeamDev CTeam;
+typedef const __attribute__((address_space(4))) EnvDev CEnv;
+__device__ __forceinline__ unsigned long long opaque_u64(unsigned long long p)
+{
+    asm volatile("" : "+s"(p));
+    return p;
+}
+__device__ __forceinline__ CTeam* team_at(unsigned long long p) { return (CTeam*)opaque_u64(p); }
+__device__ __forceinline__ CEnv* env_at(unsigned long long p) { return (CEnv*)opaque_u64(p); }
+
 // A workgroup flag written by other waves (an LDS load each time).
 __device__ __forceinline__ int flag_read(int* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
 __device__ __forceinline__ unsigned flag_read(unsigned* p)
@@ -596,7 +610,7 @@ __device__ __forceinline__ int classify(float d2, float R, float eps)
 // against column lane % 16 of gb -- in the direct form, masked by mk (the block's
 // four per-register lane masks; null: every pair).  Near pairs below the best
 // known outcome are queued.  Returns whether a pair collides.
-__device__ bool direct_block(const CallDev& cd, const TeamDev& tm, const float* base, int GSp, int ga, int gb, int lane,
+__device__ bool direct_block(const CallDev& cd, CTeam* tm, const float* base, int GSp, int ga, int gb, int lane,
                              const unsigned long long* mk, float eps, int q, int t, int rk, unsigned key, int* s_hit,
                              unsigned* s_key, bool mv)
 {
@@ -617,7 +631,7 @@ __device__ bool direct_block(const CallDev& cd, const TeamDev& tm, const float* 
         } else if (cl == 2) {
             // a near test matters only below the best known outcome
             const bool open = mv ? !flag_read(s_hit) : key < flag_read(s_key);
-            if (open) push_recheck(cd, q, t, rk, tm.slot_sphere[as], tm.slot_sphere[bs], key);
+            if (open) push_recheck(cd, q, t, rk, tm->slot_sphere[as], tm->slot_sphere[bs], key);
         }
     }
     return hit;
@@ -630,11 +644,11 @@ __device__ bool direct_block(const CallDev& cd, const TeamDev& tm, const float* 
 // as three float4 rows [R | p].  The joint value is interpolated in FP64 from the
 // robot's path waypoints of the query (paths from qp0), a revolute angle is
 // reduced to [-pi, pi] in FP64, and the value is rounded once to FP32.
-__device__ __forceinline__ void joint_matrix32(const TeamDev& tm, const CallDev& cd, long long qp0, int jg, int t,
-                                               float4* out)
+template <class TP>
+__device__ __forceinline__ void joint_matrix32(TP tm, const CallDev& cd, long long qp0, int jg, int t, float4* out)
 {
-    const int r = tm.j_robot[jg];
-    const int j = jg - tm.r_joint_off[r];
+    const int r = tm->j_robot[jg];
+    const int j = jg - tm->r_joint_off[r];
     const long long pb = cd.wp_begin[qp0 + r], pe = cd.wp_begin[qp0 + r + 1];
     const long long kseg = find_segment(cd.wp_t, pb, pe, t);
     double qj = cd.wp_q[kseg * cd.dof_stride + j];
@@ -642,12 +656,12 @@ __device__ __forceinline__ void joint_matrix32(const TeamDev& tm, const CallDev&
         const double sfrac = (double)(t - cd.wp_t[kseg]) / (double)(cd.wp_t[kseg + 1] - cd.wp_t[kseg]);
         qj = qj + sfrac * (cd.wp_q[(kseg + 1) * cd.dof_stride + j] - qj);
     }
-    const int jt = tm.j_type[jg];
+    const int jt = tm->j_type[jg];
     // an angle enters only through sin and cos: take it modulo 2 pi while it is
     // exact, so its FP32 rounding error stays below 2^-24 pi
     if (jt == MRV_REV_Z) qj = fma(-6.283185307179586, rint(qj * 0.15915494309189535), qj);
     const float qf = (float)qj;
-    const float4* Fp = reinterpret_cast<const float4*>(tm.j_fixed32 + (long long)jg * 12);
+    const float4* Fp = reinterpret_cast<const float4*>(tm->j_fixed32 + (long long)jg * 12);
     float4 m[3] = { Fp[0], Fp[1], Fp[2] };
     if (jt == MRV_REV_Z) {
         // F Rz(q): columns 0 and 1 of F rotated by q
@@ -674,13 +688,14 @@ __device__ __forceinline__ void joint_matrix32(const TeamDev& tm, const CallDev&
 // one timestep (three float4 rows per global joint).  Row i of Frame_k depends
 // only on row i of Frame_{k-1}, so the three rows of a chain run on three lanes.
 // frames receives (n_joints + 1) frames as three float4 rows each, the base first.
-__device__ __forceinline__ void chain_row32(const TeamDev& tm, int r, int row, const float4* M, float4* frames)
+template <class TP>
+__device__ __forceinline__ void chain_row32(TP tm, int r, int row, const float4* M, float4* frames)
 {
-    const float4 b = *reinterpret_cast<const float4*>(tm.r_base32 + r * 12 + row * 4);
+    const float4 b = *reinterpret_cast<const float4*>(&tm->r_base32[r * 12 + row * 4]);
     float x = b.x, y = b.y, z = b.z, w = b.w;
     frames[row] = b;
-    const int nj = tm.r_nj[r];
-    const float4* Mk = M + tm.r_joint_off[r] * 3;
+    const int nj = tm->r_nj[r];
+    const float4* Mk = M + tm->r_joint_off[r] * 3;
     for (int k = 0; k < nj; ++k, Mk += 3) {
         const float4 m0 = Mk[0], m1 = Mk[1], m2 = Mk[2];
         const float nx = fmaf(z, m2.x, fmaf(y, m1.x, x * m0.x));
@@ -712,12 +727,12 @@ __device__ __forceinline__ float4 place32(const float4* Fp, float4 L)
 // passes one task at a time: with boxes and cylinders selected per task, larger
 // J only adds register pressure.
 template <int J>
-__device__ __forceinline__ void env_tasks(const CallDev& cd, const TeamDev& tm, const EnvDev& env, const float* sp,
+__device__ __forceinline__ void env_tasks(const CallDev& cd, CTeam* tm, CEnv* env, const float* sp,
                                           const int* task, int nch, float ro_max, float eps, bool exhaustive, int q,
                                           unsigned focus, bool fall, const int* s_t, int* s_hit,
                                           unsigned long long& c_env, int lane, float3 off)
 {
-    const int GS = tm.GS, GSp = tm.GSp, TS = tm.TS;
+    const int GS = tm->GS, GSp = tm->GSp, TS = tm->TS;
     int c[J], a[J];
     float x[J], y[J], z[J], rad[J], mb[J], ms[J];
     bool act[J];
@@ -728,7 +743,7 @@ __device__ __forceinline__ void env_tasks(const CallDev& cd, const TeamDev& tm, 
         const float* row = sp + (long long)c[j] * TS + a[j];
         rad[j] = a[j] < GS ? row[3 * GSp] : 0.f;
         act[j] = rad[j] > 0.f;
-        if (act[j] && !fall) act[j] = ((focus >> tm.s_robot[tm.slot_sphere[a[j]]]) & 1u) != 0;
+        if (act[j] && !fall) act[j] = ((focus >> tm->s_robot[tm->slot_sphere[a[j]]]) & 1u) != 0;
         x[j] = 1.0e18f; y[j] = 1.0e18f; z[j] = 1.0e18f;
         if (act[j]) {
             // team-origin coordinates moved to the environment's frame
@@ -743,11 +758,11 @@ __device__ __forceinline__ void env_tasks(const CallDev& cd, const TeamDev& tm, 
     // the box of one of the task's four rows of 16 slots, the spheres widened by
     // 2 eps: every other test lies beyond the near band (the FP32 centres are far
     // closer than eps to the FP64 ones) and so is clear in FP64 as well.
-    const int nbc = env.n_box + env.n_cyl;
+    const int nbc = env->n_box + env->n_cyl;
     unsigned n_tested[J];
 #pragma unroll
     for (int j = 0; j < J; ++j) {
-        n_tested[j] = (unsigned)env.n_sph;
+        n_tested[j] = (unsigned)env->n_sph;
         if (nbc == 0) continue;
         const float w = rad[j] + 2.f * eps;
         const float lx = row_min16(act[j] ? x[j] - w : 3.0e38f), hx = row_max16(act[j] ? x[j] + w : -3.0e38f);
@@ -759,27 +774,27 @@ __device__ __forceinline__ void env_tasks(const CallDev& cd, const TeamDev& tm, 
             const int o = ob + (lane & 15);
             float4 olo = make_float4(3.0e38f, 3.0e38f, 3.0e38f, 0.f), ohi = make_float4(-3.0e38f, -3.0e38f, -3.0e38f, 0.f);
             if (o < nbc) {
-                olo = env.bc_box[2 * o];
-                ohi = env.bc_box[2 * o + 1];
+                olo = env->bc_box[2 * o];
+                ohi = env->bc_box[2 * o + 1];
             }
             const unsigned long long m4 = __ballot((olo.x <= hx) & (ohi.x >= lx) & (olo.y <= hy) & (ohi.y >= ly) &
                                                    (olo.z <= hz) & (ohi.z >= lz));
             const unsigned m = (unsigned)((m4 | (m4 >> 16) | (m4 >> 32) | (m4 >> 48)) & 0xFFFFull);
             n_tested[j] += (unsigned)__popc(m);
-            const int nb = min(max(env.n_box - ob, 0), 16);
+            const int nb = min(max(env->n_box - ob, 0), 16);
             const unsigned low = (1u << nb) - 1u;
             for (unsigned mm = m & low; mm; mm &= mm - 1u) {
                 const int b = ob + __builtin_ctz(mm);
-                mb[j] = fminf(mb[j], box_val(x[j], y[j], z[j], (CFloat*)(env.box32 + b * 16)));
+                mb[j] = fminf(mb[j], box_val(x[j], y[j], z[j], (CFloat*)(env->box32 + b * 16)));
             }
             for (unsigned mm = m & ~low; mm; mm &= mm - 1u) {
-                const int b = ob + __builtin_ctz(mm) - env.n_box;
-                mb[j] = fminf(mb[j], cyl_val(x[j], y[j], z[j], (CFloat*)(env.cyl32 + b * 8)));
+                const int b = ob + __builtin_ctz(mm) - env->n_box;
+                mb[j] = fminf(mb[j], cyl_val(x[j], y[j], z[j], (CFloat*)(env->cyl32 + b * 8)));
             }
         }
     }
-    for (int o = 0; o < env.n_sph; ++o) {
-        const float* ob = &env.sph32[o].x;
+    for (int o = 0; o < env->n_sph; ++o) {
+        const float* ob = &env->sph32[o].x;
         const float ocx = cloadf(ob), ocy = cloadf(ob + 1), ocz = cloadf(ob + 2), orad = cloadf(ob + 3);
 #pragma unroll
         for (int j = 0; j < J; ++j) {
@@ -799,30 +814,30 @@ __device__ __forceinline__ void env_tasks(const CallDev& cd, const TeamDev& tm, 
             hit = (mb[j] < rlo * rlo) || (ms[j] < -2.f * Rb * eps);
             unsure = !hit && ((mb[j] <= rhi * rhi) || (ms[j] <= fmaf(2.f * Rb, eps, eps * eps)));
         }
-        const int sa = act[j] ? tm.slot_sphere[a[j]] : 0;
+        const int sa = act[j] ? tm->slot_sphere[a[j]] : 0;
         const int t = s_t[c[j]];
-        if (env.n_pts > 0 && act[j]) {
-            const float Rp = rad[j] + env.pt_radius;
+        if (env->n_pts > 0 && act[j]) {
+            const float Rp = rad[j] + env->pt_radius;
             const float xs[3] = { x[j], y[j], z[j] };
             int lo3[3], hi3[3];
             const float reach = Rp + eps;
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                const int l = (int)floorf((xs[d] - reach - env.grid_lo[d]) * env.grid_inv);
-                const int h = (int)floorf((xs[d] + reach - env.grid_lo[d]) * env.grid_inv);
+                const int l = (int)floorf((xs[d] - reach - env->grid_lo[d]) * env->grid_inv);
+                const int h = (int)floorf((xs[d] + reach - env->grid_lo[d]) * env->grid_inv);
                 lo3[d] = l < 0 ? 0 : l;
-                hi3[d] = h >= env.grid_dim[d] ? env.grid_dim[d] - 1 : h;
+                hi3[d] = h >= env->grid_dim[d] ? env->grid_dim[d] - 1 : h;
             }
             const float plo = fmaxf(Rp - eps, 0.f), phi = Rp + eps;
             const float plo2 = plo * plo, phi2 = phi * phi;
             if (lo3[0] <= hi3[0])
                 for (int cz = lo3[2]; cz <= hi3[2]; ++cz)
                     for (int cy = lo3[1]; cy <= hi3[1]; ++cy) {
-                        const int crow = (cz * env.grid_dim[1] + cy) * env.grid_dim[0];
-                        const int pb = env.cell_start[crow + lo3[0]];
-                        const int pe = env.cell_start[crow + hi3[0] + 1];
+                        const int crow = (cz * env->grid_dim[1] + cy) * env->grid_dim[0];
+                        const int pb = env->cell_start[crow + lo3[0]];
+                        const int pe = env->cell_start[crow + hi3[0] + 1];
                         for (int p = pb; p < pe; ++p) {
-                            const float4 Pt = env.pts32[p];
+                            const float4 Pt = env->pts32[p];
                             const float dx = x[j] - Pt.x, dy = y[j] - Pt.y, dz = z[j] - Pt.z;
                             const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
                             if (d2 <= phi2) {
@@ -836,20 +851,20 @@ __device__ __forceinline__ void env_tasks(const CallDev& cd, const TeamDev& tm, 
         if (unsure && !(hit && !exhaustive)) {
             // rare: find the near obstacles and queue each for FP64 re-evaluation
             const float xj = x[j], yj = y[j], zj = z[j];
-            for (int o = 0; o < env.n_box; ++o) {
-                const float v = box_val(xj, yj, zj, (CFloat*)(env.box32 + o * 16));
+            for (int o = 0; o < env->n_box; ++o) {
+                const float v = box_val(xj, yj, zj, (CFloat*)(env->box32 + o * 16));
                 if (v < rlo * rlo) hit = true;
                 else if (v <= rhi * rhi && !hit && !flag_read(s_hit))
                     push_recheck(cd, q, t, RK_ENV_BOX, sa, o, 0u);
             }
-            for (int o = 0; o < env.n_cyl; ++o) {
-                const float v = cyl_val(xj, yj, zj, (CFloat*)(env.cyl32 + o * 8));
+            for (int o = 0; o < env->n_cyl; ++o) {
+                const float v = cyl_val(xj, yj, zj, (CFloat*)(env->cyl32 + o * 8));
                 if (v < rlo * rlo) hit = true;
                 else if (v <= rhi * rhi && !hit && !flag_read(s_hit))
                     push_recheck(cd, q, t, RK_ENV_CYL, sa, o, 0u);
             }
-            for (int o = 0; o < env.n_sph; ++o) {
-                const float* ob = &env.sph32[o].x;
+            for (int o = 0; o < env->n_sph; ++o) {
+                const float* ob = &env->sph32[o].x;
                 const float dx = xj - cloadf(ob), dy = yj - cloadf(ob + 1), dz = zj - cloadf(ob + 2);
                 const int cl = classify(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), rad[j] + cloadf(ob + 3), eps);
                 if (cl == 1) hit = true;
@@ -1009,18 +1024,18 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
         const bool do_env = check_env && (!hier || phase == 0);
         const bool do_rr = !hier || phase == 1;
         // this tile's team and environment, and its LDS partition
-        const TeamDev tm = load_descriptor<TeamDev>(uniform_u64(s_tp));
+        const unsigned long long tpu = uniform_u64(s_tp);
         const unsigned long long epu = uniform_u64(s_ep);
-        const EnvDev env = epu ? load_descriptor<EnvDev>(epu) : EnvDev{};
+        CTeam* tm = team_at(tpu);
         const int C = wave_uniform(s_chunk);
         const float eps = __int_as_float(wave_uniform(__float_as_int(s_eps)));   // this query's near band
         // prioritised MV: robots outside the focus set only take part in pairs
         // with a robot in it
         const unsigned focus = kFocus ? (unsigned)wave_uniform((int)s_focus) : 0u;
-        const int S = tm.S;
-        const int F = tm.F;
-        const int G = tm.G;
-        const int n = tm.n_robots;
+        const int S = tm->S;
+        const int F = tm->F;
+        const int G = tm->G;
+        const int n = tm->n_robots;
         const unsigned all_robots = n >= 32 ? 0xFFFFFFFFu : (1u << n) - 1u;
         const bool fall = !kFocus || focus == 0u || (focus & all_robots) == all_robots;
         const long long qp0 = path_of(cd, n, q);
@@ -1029,9 +1044,9 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
         // team's origin, radius (0 marks padding), w = |p|^2 - r^2.  The FK frames of
         // the timestep take its last 12 F floats, past the x, y, z rows, until the
         // radius and w rows are written over them.
-        const int GS = tm.GS;
-        const int GSp = tm.GSp;
-        const int TS = tm.TS;
+        const int GS = tm->GS;
+        const int GSp = tm->GSp;
+        const int TS = tm->TS;
         const int fr_off = TS - 12 * F;
         float* sp = reinterpret_cast<float*>(dyn);                      // [C][TS]
 
@@ -1039,7 +1054,7 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
         // (timestep, joint), into the start of the timestep's slice (the x, y, z rows,
         // written only later); then the chains, one lane per (timestep, robot, frame
         // row), into the frames at the slice's tail.
-        const int J = tm.J;
+        const int J = tm->J;
         for (int idx = tid; idx < nv * J; idx += WG) {
             const int c = idx / J;
             const int jg = idx - c * J;
@@ -1051,7 +1066,7 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
             const int rr = idx - c * 3 * n;
             const int r = rr / 3;
             chain_row32(tm, r, rr - 3 * r, reinterpret_cast<const float4*>(sp + (long long)c * TS),
-                        reinterpret_cast<float4*>(sp + (long long)c * TS + fr_off) + tm.r_frame_off[r] * 3);
+                        reinterpret_cast<float4*>(sp + (long long)c * TS + fr_off) + tm->r_frame_off[r] * 3);
         }
         __syncthreads();
 
@@ -1064,8 +1079,8 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
         for (int idx = tid; idx < span; idx += WG) {
             const int c0 = idx / GS;
             const int s = idx - c0 * GS;
-            const int fs = tm.slot_frame[s];
-            const float4 L = tm.slot_local[s];
+            const int fs = tm->slot_frame[s];
+            const float4 L = tm->slot_local[s];
             for (int c = c0; c < nv; c += cstep) {
                 float x = 0.f, y = 0.f, z = 0.f;
                 if (fs >= 0) {
@@ -1089,7 +1104,7 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
             for (int idx = tid; idx < span; idx += WG) {
                 const int c0 = idx / GS;
                 const int s = idx - c0 * GS;
-                const float r = tm.slot_local[s].w;
+                const float r = tm->slot_local[s].w;
                 for (int c = c0; c < nv; c += cstep) {
                     float* row = sp + (long long)c * TS + s;
                     float w = kFar;
@@ -1115,15 +1130,17 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
             if (exhaustive) __builtin_amdgcn_s_setprio(0);
             // --- robot-obstacle tests (MV with environment checking): one lane per
             // (timestep, slot); obstacle parameters are wave-uniform scalar loads.
-            if (do_env) {
+            if (do_env && epu) {
+                CTeam* tm = team_at(tpu);
+                CEnv* env = env_at(epu);
                 // the team origin in the environment's frame, rounded once from FP64
-                const float3 off = make_float3((float)(tm.origin64[0] - env.origin64[0]),
-                                               (float)(tm.origin64[1] - env.origin64[1]),
-                                               (float)(tm.origin64[2] - env.origin64[2]));
+                const float3 off = make_float3((float)(tm->origin64[0] - env->origin64[0]),
+                                               (float)(tm->origin64[1] - env->origin64[1]),
+                                               (float)(tm->origin64[2] - env->origin64[2]));
                 const int nch = (GS + kWave - 1) / kWave;
                 const int ntask = nv * nch;
                 float ro_max = 0.f;
-                for (int o = 0; o < env.n_sph; ++o) ro_max = fmaxf(ro_max, cloadf(&env.sph32[o].w));
+                for (int o = 0; o < env->n_sph; ++o) ro_max = fmaxf(ro_max, cloadf(&env->sph32[o].w));
                 // tasks wave, wave + kWaves, ... of this wave, one at a time, so that in
                 // early-terminating calls a hit stops the wave before its next task
                 int task = wave;
@@ -1146,10 +1163,11 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
             // pairs outside the self list masked) and its blocks against every group of
             // the higher robots.  Lanes whose minimum lies within the bound's
             // uncertainty revisit their pairs directly.
-            const bool do_self = do_env && tm.n_sblocks > 0;
+            CTeam* tm = team_at(tpu);
+            const bool do_self = do_env && tm->n_sblocks > 0;
             if ((do_rr || do_self) && !(kMV && !exhaustive && flag_read(&s_hit))) {
                 const float rho2 = __uint_as_float(s_rho2);
-                const float rm = tm.r_max;
+                const float rm = tm->r_max;
                 const float u = 5.9604645e-8f;
                 // |D_fp32 - D| <= 24 u (rho^2 + rm^2) for |p| <= rho, r <= rm: 4 u from each
                 // of w_a and w_b, 12 u from the MFMA's four fused steps (partial sums up to
@@ -1162,7 +1180,7 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
                 const int q4 = lane >> 4;
                 for (int k = wave; k < G; k += kWaves) {
                     if (kMV && !exhaustive && flag_read(&s_hit)) break;
-                    const int* tk = tm.gtask + 8 * k;
+                    const int* tk = tm->gtask + 8 * k;
                     const int ga = cload(tk + 0);
                     const int ra = cload(tk + 1);
                     const bool a_in = fall || ((focus >> ra) & 1u);     // ga's robot in focus
@@ -1173,8 +1191,8 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
                     const unsigned long long rr_tests = do_rr && a_in ? (unsigned long long)cload(tk + 5) : 0ull;
                     const unsigned long long self_tests = do_self && a_in ? (unsigned long long)cload(tk + 6) : 0ull;
                     // spheres of group ga, for the test counts of a robot outside the focus set
-                    const int ga_n = a_in ? 0 : cload(reinterpret_cast<const int*>(tm.g_range) + 2 * ga + 1) -
-                                                cload(reinterpret_cast<const int*>(tm.g_range) + 2 * ga);
+                    const int ga_n = a_in ? 0 : cload(reinterpret_cast<const int*>(tm->g_range) + 2 * ga + 1) -
+                                                cload(reinterpret_cast<const int*>(tm->g_range) + 2 * ga);
                     if (sb0 == sb1 && gs >= G) continue;
                     for (int c = 0; c < nv; ++c) {
                         const int t = s_t[c];
@@ -1182,7 +1200,7 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
                             if (!exhaustive && flag_read(&s_hit)) break;
                         } else if (!exhaustive) {
                             const unsigned known = flag_read(&s_key);
-                            if (known != 0xFFFFFFFFu && known < (unsigned)t * (unsigned)tm.P) break;
+                            if (known != 0xFFFFFFFFu && known < (unsigned)t * (unsigned)tm->P) break;
                         }
                         c_rr += rr_tests;
                         c_self += self_tests;
@@ -1195,8 +1213,8 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
                         if (sb0 < sb1) {
                             float best = 3.0e38f;
                             for (int sb = sb0; sb < sb1; ++sb) {
-                                const int gb = cload(tm.sblocks + 8 * sb + 1);
-                                const unsigned long long* mk = tm.sb_mask + 4 * sb;
+                                const int gb = cload(tm->sblocks + 8 * sb + 1);
+                                const unsigned long long* mk = tm->sb_mask + 4 * sb;
                                 const floatx4 acc = { lane_select(cload64(mk + 0), cw.x, kFar), lane_select(cload64(mk + 1), cw.y, kFar),
                                                       lane_select(cload64(mk + 2), cw.z, kFar), lane_select(cload64(mk + 3), cw.w, kFar) };
                                 const float bop = base[q4 * GSp + gb * 16 + i16];
@@ -1208,8 +1226,8 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
                             const bool unsure = !hit && best < e_hi;
                             if (!__ballot(hit) && __ballot(unsure) && unsure) {
                                 for (int sb = sb0; sb < sb1 && !hit; ++sb) {
-                                    const int gb = cload(tm.sblocks + 8 * sb + 1);
-                                    const unsigned long long* mk = tm.sb_mask + 4 * sb;
+                                    const int gb = cload(tm->sblocks + 8 * sb + 1);
+                                    const unsigned long long* mk = tm->sb_mask + 4 * sb;
                                     hit = direct_block(cd, tm, base, GSp, ga, gb, lane, mk, eps, q, t, RK_SELF, 0u, &s_hit, &s_key, true);
                                 }
                             }
@@ -1228,12 +1246,12 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
                             const int rb_end = sweep ? ra + 2 : n;
                             for (int rb = ra + 1; rb < rb_end; ++rb) {
                                 if (!a_in && !((focus >> rb) & 1u)) continue;
-                                const int g0 = sweep ? gs : cload(tm.r_group_off + rb);
-                                const int g1 = sweep ? G : cload(tm.r_group_off + rb + 1);
+                                const int g0 = sweep ? gs : cload(tm->r_group_off + rb);
+                                const int g1 = sweep ? G : cload(tm->r_group_off + rb + 1);
                                 if (!a_in)
                                     c_rr += (unsigned long long)ga_n *
-                                            (unsigned)(cload(tm.r_sphere_off + rb + 1) - cload(tm.r_sphere_off + rb));
-                                const unsigned key = kMV ? 0u : (unsigned)t * (unsigned)tm.P + pair_index(ra, rb, n);
+                                            (unsigned)(cload(tm->r_sphere_off + rb + 1) - cload(tm->r_sphere_off + rb));
+                                const unsigned key = kMV ? 0u : (unsigned)t * (unsigned)tm->P + pair_index(ra, rb, n);
                                 if (!kMV && !exhaustive && key >= flag_read(&s_key)) break;
                                 float best = 3.0e38f;
                                 int g = g0;
@@ -1322,10 +1340,10 @@ __global__ void k_spheres(CallDev cd, const int* st_q, const int* st_t, int n_st
         // the joint transforms first, the frames after them (the same two steps as
         // the validation kernel)
         float4* fr = frames + tm.J * 3;
-        for (int jg = threadIdx.x; jg < tm.J; jg += blockDim.x) joint_matrix32(tm, cd, p0, jg, st_t[k], frames + jg * 3);
+        for (int jg = threadIdx.x; jg < tm.J; jg += blockDim.x) joint_matrix32(&tm, cd, p0, jg, st_t[k], frames + jg * 3);
         __syncthreads();
         for (int i = threadIdx.x; i < tm.n_robots * 3; i += blockDim.x)
-            chain_row32(tm, i / 3, i % 3, frames, fr + tm.r_frame_off[i / 3] * 3);
+            chain_row32(&tm, i / 3, i % 3, frames, fr + tm.r_frame_off[i / 3] * 3);
         __syncthreads();
         for (int s = threadIdx.x; s < tm.S; s += blockDim.x) {
             const float4 X = place32(fr + tm.s_slot[s] * 3, tm.s_local32[s]);
