@@ -79,6 +79,13 @@ __device__ __forceinline__ unsigned long long opaque_u64(unsigned long long p)
 }
 __device__ __forceinline__ CTeam* team_at(unsigned long long p) { return (CTeam*)opaque_u64(p); }
 __device__ __forceinline__ CEnv* env_at(unsigned long long p) { return (CEnv*)opaque_u64(p); }
+// The validation kernel's CallDev argument in place (explicit kernel arguments
+// start the kernarg segment), from a new opaque address for each phase.
+typedef const __attribute__((address_space(4))) CallDev CCall;
+__device__ __forceinline__ CCall& call_at()
+{
+    return *(CCall*)opaque_u64((unsigned long long)__builtin_amdgcn_kernarg_segment_ptr());
+}
 
 // A workgroup flag written by other waves (an LDS load each time).
 __device__ __forceinline__ int flag_read(int* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
@@ -87,9 +94,13 @@ __device__ __forceinline__ unsigned flag_read(unsigned* p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-__device__ __forceinline__ const TeamDev* team_of(const CallDev& cd, int q) { return cd.q_team ? cd.q_team[q] : cd.team0; }
-__device__ __forceinline__ const EnvDev* env_of(const CallDev& cd, int q) { return cd.q_env ? cd.q_env[q] : cd.env0; }
-__device__ __forceinline__ long long path_of(const CallDev& cd, int n_robots, int q)
+// (CD: CallDev, or the kernel's arguments read in place, see call_at)
+template <class CD>
+__device__ __forceinline__ const TeamDev* team_of(const CD& cd, int q) { return cd.q_team ? cd.q_team[q] : cd.team0; }
+template <class CD>
+__device__ __forceinline__ const EnvDev* env_of(const CD& cd, int q) { return cd.q_env ? cd.q_env[q] : cd.env0; }
+template <class CD>
+__device__ __forceinline__ long long path_of(const CD& cd, int n_robots, int q)
 {
     return cd.q_pathoff ? cd.q_pathoff[q] : (long long)q * n_robots;
 }
@@ -510,7 +521,8 @@ __global__ void k_fill_u32(unsigned* p, unsigned v, size_t n)
 // the validation kernel.  key orders the test's possible outcome (MV: 0, FFC:
 // t*P + pair); when the call's queue is full the smallest dropped key is kept
 // per query and k_finalize decides whether the drop leaves the answer open.
-__device__ __forceinline__ void push_recheck(const CallDev& cd, int q, int t, int kind, int a, int b, unsigned key)
+template <class CD>
+__device__ __forceinline__ void push_recheck(const CD& cd, int q, int t, int kind, int a, int b, unsigned key)
 {
     const unsigned g = atomicAdd(reinterpret_cast<unsigned*>(cd.ctrl + 2), 1u);
     if (g < (unsigned)cd.gq_cap) cd.gq[g] = make_int4(q, t | (kind << 24), a, b);
@@ -610,7 +622,8 @@ __device__ __forceinline__ int classify(float d2, float R, float eps)
 // against column lane % 16 of gb -- in the direct form, masked by mk (the block's
 // four per-register lane masks; null: every pair).  Near pairs below the best
 // known outcome are queued.  Returns whether a pair collides.
-__device__ bool direct_block(const CallDev& cd, CTeam* tm, const float* base, int GSp, int ga, int gb, int lane,
+template <class CD>
+__device__ bool direct_block(const CD& cd, CTeam* tm, const float* base, int GSp, int ga, int gb, int lane,
                              const unsigned long long* mk, float eps, int q, int t, int rk, unsigned key, int* s_hit,
                              unsigned* s_key, bool mv)
 {
@@ -644,8 +657,8 @@ __device__ bool direct_block(const CallDev& cd, CTeam* tm, const float* base, in
 // as three float4 rows [R | p].  The joint value is interpolated in FP64 from the
 // robot's path waypoints of the query (paths from qp0), a revolute angle is
 // reduced to [-pi, pi] in FP64, and the value is rounded once to FP32.
-template <class TP>
-__device__ __forceinline__ void joint_matrix32(TP tm, const CallDev& cd, long long qp0, int jg, int t, float4* out)
+template <class TP, class CD>
+__device__ __forceinline__ void joint_matrix32(TP tm, const CD& cd, long long qp0, int jg, int t, float4* out)
 {
     const int r = tm->j_robot[jg];
     const int j = jg - tm->r_joint_off[r];
@@ -726,8 +739,8 @@ __device__ __forceinline__ float4 place32(const float4* Fp, float4 L)
 // tests below the known outcome are queued for FP64 re-evaluation.  The kernel
 // passes one task at a time: with boxes and cylinders selected per task, larger
 // J only adds register pressure.
-template <int J>
-__device__ __forceinline__ void env_tasks(const CallDev& cd, CTeam* tm, CEnv* env, const float* sp,
+template <int J, class CD>
+__device__ __forceinline__ void env_tasks(const CD& cd, CTeam* tm, CEnv* env, const float* sp,
                                           const int* task, int nch, float ro_max, float eps, bool exhaustive, int q,
                                           unsigned focus, bool fall, const int* s_t, int* s_hit,
                                           unsigned long long& c_env, int lane, float3 off)
@@ -878,8 +891,10 @@ __device__ __forceinline__ void env_tasks(const CallDev& cd, CTeam* tm, CEnv* en
 }
 
 template <int KIND>
-__global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kExhWGsPerCU : kWGsPerCU)) void k_validate(CallDev cd)
+__global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kExhWGsPerCU : kWGsPerCU)) void k_validate(CallDev cd_arg)
 {
+    (void)cd_arg;   // read in place through call_at()
+    CCall& cd = call_at();
     // KIND: 0 early-terminating MV, 1 early-terminating FFC, 2 early-terminating MV
     // with a focus set (prioritised MV), 3 exhaustive MV, 4 exhaustive FFC, 5
     // exhaustive MV with a focus set
@@ -934,6 +949,7 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
         // (early-terminating calls keep one level: their obstacle verdicts end queries).
         if (exhaustive) __builtin_amdgcn_s_setprio(2);
         if (tid == 0) {
+            CCall& cd = call_at();
             // the previous tile's outcome (all its waves passed the barrier that
             // ended it) goes to its query's word before the next claim
             if (s_q >= 0 && s_nv > 0) {
@@ -1016,6 +1032,7 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
             s_hit = kMV && known != 0u; s_key = !kMV ? known : 0xFFFFFFFFu; s_rho2 = 0u;
         }
         __syncthreads();
+        CCall& cd = call_at();
         const int q = s_q;
         if (q < 0) break;
         const int nv = s_nv;
@@ -1131,6 +1148,7 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
             // --- robot-obstacle tests (MV with environment checking): one lane per
             // (timestep, slot); obstacle parameters are wave-uniform scalar loads.
             if (do_env && epu) {
+                CCall& cd = call_at();
                 CTeam* tm = team_at(tpu);
                 CEnv* env = env_at(epu);
                 // the team origin in the environment's frame, rounded once from FP64
@@ -1163,6 +1181,7 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
             // pairs outside the self list masked) and its blocks against every group of
             // the higher robots.  Lanes whose minimum lies within the bound's
             // uncertainty revisit their pairs directly.
+            CCall& cd = call_at();
             CTeam* tm = team_at(tpu);
             const bool do_self = do_env && tm->n_sblocks > 0;
             if ((do_rr || do_self) && !(kMV && !exhaustive && flag_read(&s_hit))) {
