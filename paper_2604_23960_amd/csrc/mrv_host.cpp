@@ -239,15 +239,16 @@ int build_team(mrv_ctx ctx, const mrv_robot_desc* robots, int n, TeamHost& out)
         auto& m = blocks.emplace(std::make_pair(sa / 16, sb / 16), std::array<uint64_t, 4>{0, 0, 0, 0}).first->second;
         m[row & 3] |= 1ull << (16 * (row >> 2) + col);
     }
+    // 64-byte records: row group, column group, pairs, robot, 4 unused ints, then the
+    // four lane masks
     std::vector<int> sblocks;
-    std::vector<uint64_t> sb_mask;
     int n_self_unique = 0;
     for (const auto& kv : blocks) {
         int cnt = 0;
         for (uint64_t m : kv.second) cnt += __builtin_popcountll(m);
-        const int rec[8] = { kv.first.first, kv.first.second, cnt, s_robot[g_range[2 * kv.first.first]], 0, 0, 0, 0 };
-        sblocks.insert(sblocks.end(), rec, rec + 8);
-        for (uint64_t m : kv.second) sb_mask.push_back(m);
+        int rec[16] = { kv.first.first, kv.first.second, cnt, s_robot[g_range[2 * kv.first.first]], 0, 0, 0, 0 };
+        std::memcpy(rec + 8, kv.second.data(), 4 * sizeof(uint64_t));
+        sblocks.insert(sblocks.end(), rec, rec + 16);
         n_self_unique += cnt;
     }
     // pair tasks, one per group ga: its self blocks [sb0, sb1) (sorted by ga) and the
@@ -255,12 +256,12 @@ int build_team(mrv_ctx ctx, const mrv_robot_desc* robots, int n, TeamHost& out)
     std::vector<int> gtask;
     {
         size_t sbi = 0;
-        const size_t nsb = sblocks.size() / 8;
+        const size_t nsb = sblocks.size() / 16;
         for (int g = 0; g < G; ++g) {
             const int r = s_robot[g_range[2 * g]];
             const int sb0 = (int)sbi;
             int self_tests = 0;
-            while (sbi < nsb && sblocks[8 * sbi] == g) self_tests += sblocks[8 * sbi++ + 2];
+            while (sbi < nsb && sblocks[16 * sbi] == g) self_tests += sblocks[16 * sbi++ + 2];
             const int rec[8] = { g, r, sb0, (int)sbi, r_group_off[r + 1],
                                  (g_range[2 * g + 1] - g_range[2 * g]) * (S - r_sphere_off[r + 1]), self_tests, 0 };
             gtask.insert(gtask.end(), rec, rec + 8);
@@ -320,7 +321,7 @@ int build_team(mrv_ctx ctx, const mrv_robot_desc* robots, int n, TeamHost& out)
                  o_ss = pk.add(s_slot), o_sl = pk.add(s_lframe), o_l32 = pk.add(s_local32),
                  o_l64 = pk.add(s_local64), o_rt = pk.add(gtask), o_sg = pk.add(s_group),
                  o_gr = pk.add(g_range), o_rg = pk.add(r_group_off), o_ss2 = pk.add(slot_sphere),
-                 o_sb = pk.add(sblocks), o_sm = pk.add(sb_mask), o_rm = pk.add(r_mag),
+                 o_sb = pk.add(sblocks), o_rm = pk.add(r_mag),
                  o_jr = pk.add(j_robot), o_sf = pk.add(slot_frame), o_slc = pk.add(slot_local);
     const TeamDev blank{};
     const size_t o_self = pk.add(&blank, sizeof(TeamDev));
@@ -332,7 +333,7 @@ int build_team(mrv_ctx ctx, const mrv_robot_desc* robots, int n, TeamHost& out)
     t.S = S;
     t.F = F;
     t.n_self = n_self_unique;
-    t.n_sblocks = (int)sblocks.size() / 8;
+    t.n_sblocks = (int)sblocks.size() / 16;
     t.GS = GS;
     t.GSp = GS + 16;
     t.J = (int)j_type.size();
@@ -375,7 +376,6 @@ int build_team(mrv_ctx ctx, const mrv_robot_desc* robots, int n, TeamHost& out)
     t.slot_frame = (const int*)at(o_sf);
     t.slot_local = (const float4*)at(o_slc);
     t.sblocks = (const int*)at(o_sb);
-    t.sb_mask = (const unsigned long long*)at(o_sm);
     out.dmem = d;
     out.d_dev = (TeamDev*)at(o_self);
     out.dof = r_nj;

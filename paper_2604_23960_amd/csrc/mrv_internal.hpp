@@ -102,8 +102,8 @@ struct TeamDev {
     const int* slot_sphere;     // [GS] sphere of each slot, -1 for padding
     const int* slot_frame;      // [GS] frame slot of each slot's sphere, -1 for padding
     const float4* slot_local;   // [GS] local centre and radius of each slot's sphere, zeros for padding
-    const int* sblocks;         // [n_sblocks][8] row group, column group, pairs, robot, 0, 0, 0, 0
-    const unsigned long long* sb_mask;   // [n_sblocks][4] lane masks, one per accumulator register
+    const int* sblocks;         // [n_sblocks][16] row group, column group, pairs, robot, 0, 0, 0, 0, then
+                                // four 64-bit lane masks, one per accumulator register
 };
 
 // Resident environment in the world frame.

@@ -543,6 +543,13 @@ __device__ __forceinline__ float lane_select(unsigned long long m, float on, flo
 // Smallest D in a lane's share of a block: its four rows share the column b, so
 // w_b is added once, after the minimum (rounding to nearest is monotonic, so this
 // equals the minimum of the four sums).
+// The four lane masks of self block sb (one per accumulator register), inline in
+// its 64-byte record after the group indices, so one scalar load brings both.
+__device__ __forceinline__ const unsigned long long* sb_masks(CTeam* tm, int sb)
+{
+    return reinterpret_cast<const unsigned long long*>(tm->sblocks + 16 * sb + 8);
+}
+
 __device__ __forceinline__ float col_min(floatx4 d, float wb)
 {
     return fminf(fminf(fminf(d[0], d[1]), d[2]), d[3]) + wb;
@@ -900,6 +907,10 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
     // exhaustive MV with a focus set
     constexpr bool kMV = KIND != 1 && KIND != 4;
     constexpr bool kFocus = KIND == 2 || KIND == 5;
+    // exhaustive MV runs each group's self blocks over the tile's timesteps in an
+    // inner loop (no early exit to honour between timesteps)
+    constexpr bool kSelfInner = KIND == 3 || KIND == 5;
+    constexpr int kSI = 4;
     constexpr int WG = validate_wg(KIND);
     constexpr int kWaves = WG / kWave;
     extern __shared__ float4 dyn[];
@@ -1213,6 +1224,56 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
                     const int ga_n = a_in ? 0 : cload(reinterpret_cast<const int*>(tm->g_range) + 2 * ga + 1) -
                                                 cload(reinterpret_cast<const int*>(tm->g_range) + 2 * ga);
                     if (sb0 == sb1 && gs >= G) continue;
+                    if constexpr (kSelfInner) {
+                        // exhaustive MV: the self blocks of ga for up to kSI timesteps at a time,
+                        // each block's record loaded once and its MFMAs independent
+                        if (sb0 < sb1) {
+                            for (int c0 = 0; c0 < nv; c0 += kSI) {
+                                float best[kSI];
+#pragma unroll
+                                for (int i = 0; i < kSI; ++i) best[i] = 3.0e38f;
+                                for (int sb = sb0; sb < sb1; ++sb) {
+                                    const int gb = cload(tm->sblocks + 16 * sb + 1);
+                                    const unsigned long long* mk = sb_masks(tm, sb);
+                                    const unsigned long long m0 = cload64(mk), m1 = cload64(mk + 1), m2 = cload64(mk + 2),
+                                                             m3 = cload64(mk + 3);
+#pragma unroll
+                                    for (int i = 0; i < kSI; ++i) {
+                                        if (c0 + i < nv) {
+                                            const float* base = sp + (long long)(c0 + i) * TS;
+                                            const float aop = -2.f * base[q4 * GSp + ga * 16 + i16];
+                                            const float4 cw = *reinterpret_cast<const float4*>(base + 4 * GSp + ga * 16 + 4 * q4);
+                                            const floatx4 acc = { lane_select(m0, cw.x, kFar), lane_select(m1, cw.y, kFar),
+                                                                  lane_select(m2, cw.z, kFar), lane_select(m3, cw.w, kFar) };
+                                            const float bop = base[q4 * GSp + gb * 16 + i16];
+                                            const float wb = base[4 * GSp + gb * 16 + i16];
+                                            const floatx4 d = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, bop, acc, 0, 0, 0);
+                                            best[i] = block_min(d, wb, best[i]);
+                                        }
+                                    }
+                                }
+#pragma unroll
+                                for (int i = 0; i < kSI; ++i) {
+                                    if (c0 + i < nv) {
+                                        c_self += self_tests;
+                                        const int t = s_t[c0 + i];
+                                        const float* base = sp + (long long)(c0 + i) * TS;
+                                        bool hit = best[i] < e_lo;
+                                        const bool unsure = !hit && best[i] < e_hi;
+                                        if (!__ballot(hit) && __ballot(unsure) && unsure) {
+                                            for (int sb = sb0; sb < sb1 && !hit; ++sb) {
+                                                const int gb = cload(tm->sblocks + 16 * sb + 1);
+                                                hit = direct_block(cd, tm, base, GSp, ga, gb, lane, sb_masks(tm, sb), eps, q, t,
+                                                                   RK_SELF, 0u, &s_hit, &s_key, true);
+                                            }
+                                        }
+                                        if (__ballot(hit) && lane == 0) s_hit = 1;
+                                    }
+                                }
+                            }
+                        }
+                        if (gs >= G) continue;
+                    }
                     for (int c = 0; c < nv; ++c) {
                         const int t = s_t[c];
                         if (kMV) {
@@ -1222,18 +1283,18 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
                             if (known != 0xFFFFFFFFu && known < (unsigned)t * (unsigned)tm->P) break;
                         }
                         c_rr += rr_tests;
-                        c_self += self_tests;
+                        if (!kSelfInner) c_self += self_tests;
                         const float* base = sp + (long long)c * TS;
                         const float aop = -2.f * base[q4 * GSp + ga * 16 + i16];
                         const float4 cw = *reinterpret_cast<const float4*>(base + 4 * GSp + ga * 16 + 4 * q4);
                         bool found = false;
 
                         // self blocks of ga
-                        if (sb0 < sb1) {
+                        if (!kSelfInner && sb0 < sb1) {
                             float best = 3.0e38f;
                             for (int sb = sb0; sb < sb1; ++sb) {
-                                const int gb = cload(tm->sblocks + 8 * sb + 1);
-                                const unsigned long long* mk = tm->sb_mask + 4 * sb;
+                                const int gb = cload(tm->sblocks + 16 * sb + 1);
+                                const unsigned long long* mk = sb_masks(tm, sb);
                                 const floatx4 acc = { lane_select(cload64(mk + 0), cw.x, kFar), lane_select(cload64(mk + 1), cw.y, kFar),
                                                       lane_select(cload64(mk + 2), cw.z, kFar), lane_select(cload64(mk + 3), cw.w, kFar) };
                                 const float bop = base[q4 * GSp + gb * 16 + i16];
@@ -1245,8 +1306,8 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
                             const bool unsure = !hit && best < e_hi;
                             if (!__ballot(hit) && __ballot(unsure) && unsure) {
                                 for (int sb = sb0; sb < sb1 && !hit; ++sb) {
-                                    const int gb = cload(tm->sblocks + 8 * sb + 1);
-                                    const unsigned long long* mk = tm->sb_mask + 4 * sb;
+                                    const int gb = cload(tm->sblocks + 16 * sb + 1);
+                                    const unsigned long long* mk = sb_masks(tm, sb);
                                     hit = direct_block(cd, tm, base, GSp, ga, gb, lane, mk, eps, q, t, RK_SELF, 0u, &s_hit, &s_key, true);
                                 }
                             }
