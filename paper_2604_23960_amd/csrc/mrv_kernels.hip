@@ -829,13 +829,16 @@ __device__ __forceinline__ void env_tasks(const CD& cd, CTeam* tm, CEnv* env, co
         if (act[j]) c_env += (unsigned long long)n_tested[j];
         const float rlo = fmaxf(rad[j] - eps, 0.f), rhi = rad[j] + eps;
         const float Rb = rad[j] + ro_max;
+        // common case first: no lane within the near band of a box, cylinder or sphere
         bool hit = false, unsure = false;
-        if (act[j]) {
-            hit = (mb[j] < rlo * rlo) || (ms[j] < -2.f * Rb * eps);
-            unsure = !hit && ((mb[j] <= rhi * rhi) || (ms[j] <= fmaf(2.f * Rb, eps, eps * eps)));
+        const bool near = act[j] && ((mb[j] <= rhi * rhi) || (ms[j] <= fmaf(2.f * Rb, eps, eps * eps)));
+        if (__ballot(near)) {
+            hit = near && ((mb[j] < rlo * rlo) || (ms[j] < -2.f * Rb * eps));
+            unsure = near && !hit;
         }
-        const int sa = act[j] ? tm->slot_sphere[a[j]] : 0;
-        const int t = s_t[c[j]];
+        // the sphere index and timestep of a queued test, read only when one is queued
+        auto sa_of = [&]() { return tm->slot_sphere[a[j]]; };
+        auto t_of = [&]() { return s_t[c[j]]; };
         if (env->n_pts > 0 && act[j]) {
             const float Rp = rad[j] + env->pt_radius;
             const float xs[3] = { x[j], y[j], z[j] };
@@ -863,7 +866,7 @@ __device__ __forceinline__ void env_tasks(const CD& cd, CTeam* tm, CEnv* env, co
                             if (d2 <= phi2) {
                                 if (d2 < plo2) hit = true;
                                 else if (!hit && !flag_read(s_hit))
-                                    push_recheck(cd, q, t, RK_ENV_PT, sa, p, 0u);
+                                    push_recheck(cd, q, t_of(), RK_ENV_PT, sa_of(), p, 0u);
                             }
                         }
                     }
@@ -875,13 +878,13 @@ __device__ __forceinline__ void env_tasks(const CD& cd, CTeam* tm, CEnv* env, co
                 const float v = box_val(xj, yj, zj, (CFloat*)(env->box32 + o * 16));
                 if (v < rlo * rlo) hit = true;
                 else if (v <= rhi * rhi && !hit && !flag_read(s_hit))
-                    push_recheck(cd, q, t, RK_ENV_BOX, sa, o, 0u);
+                    push_recheck(cd, q, t_of(), RK_ENV_BOX, sa_of(), o, 0u);
             }
             for (int o = 0; o < env->n_cyl; ++o) {
                 const float v = cyl_val(xj, yj, zj, (CFloat*)(env->cyl32 + o * 8));
                 if (v < rlo * rlo) hit = true;
                 else if (v <= rhi * rhi && !hit && !flag_read(s_hit))
-                    push_recheck(cd, q, t, RK_ENV_CYL, sa, o, 0u);
+                    push_recheck(cd, q, t_of(), RK_ENV_CYL, sa_of(), o, 0u);
             }
             for (int o = 0; o < env->n_sph; ++o) {
                 const float* ob = &env->sph32[o].x;
@@ -889,7 +892,7 @@ __device__ __forceinline__ void env_tasks(const CD& cd, CTeam* tm, CEnv* env, co
                 const int cl = classify(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), rad[j] + cloadf(ob + 3), eps);
                 if (cl == 1) hit = true;
                 else if (cl == 2 && !hit && !flag_read(s_hit))
-                    push_recheck(cd, q, t, RK_ENV_SPH, sa, o, 0u);
+                    push_recheck(cd, q, t_of(), RK_ENV_SPH, sa_of(), o, 0u);
             }
         }
         any_hit = any_hit || hit;
@@ -1258,9 +1261,10 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
                                         c_self += self_tests;
                                         const int t = s_t[c0 + i];
                                         const float* base = sp + (long long)(c0 + i) * TS;
-                                        bool hit = best[i] < e_lo;
-                                        const bool unsure = !hit && best[i] < e_hi;
-                                        if (!__ballot(hit) && __ballot(unsure) && unsure) {
+                                        bool hit = false;
+                                        const bool unsure = best[i] < e_hi && !(best[i] < e_lo);
+                                        if (__ballot(best[i] < e_hi)) hit = best[i] < e_lo;
+                                        if (__ballot(unsure) && !__ballot(hit) && unsure) {
                                             for (int sb = sb0; sb < sb1 && !hit; ++sb) {
                                                 const int gb = cload(tm->sblocks + 16 * sb + 1);
                                                 hit = direct_block(cd, tm, base, GSp, ga, gb, lane, sb_masks(tm, sb), eps, q, t,
@@ -1354,12 +1358,16 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
                                     const floatx4 d = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, bop, acc, 0, 0, 0);
                                     best = block_min(d, wb, best);
                                 }
-                                bool hit = best < e_lo;
-                                const bool unsure = !hit && best < e_hi;
-                                if (!__ballot(hit) && __ballot(unsure) && unsure) {
-                                    for (int gg = g0; gg < g1 && !hit; ++gg)
-                                        hit = direct_block(cd, tm, base, GSp, ga, gg, lane, nullptr, eps, q, t, RK_RR, key,
-                                                           &s_hit, &s_key, kMV);
+                                // common case first: every pair of the lane clear beyond the band
+                                bool hit = false;
+                                if (__ballot(best < e_hi)) {
+                                    hit = best < e_lo;
+                                    const bool unsure = !hit && best < e_hi;
+                                    if (!__ballot(hit) && __ballot(unsure) && unsure) {
+                                        for (int gg = g0; gg < g1 && !hit; ++gg)
+                                            hit = direct_block(cd, tm, base, GSp, ga, gg, lane, nullptr, eps, q, t, RK_RR, key,
+                                                               &s_hit, &s_key, kMV);
+                                    }
                                 }
                                 if (__ballot(hit)) {
                                     found = true;
