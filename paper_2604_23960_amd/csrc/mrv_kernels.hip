@@ -914,6 +914,13 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
     // inner loop (no early exit to honour between timesteps)
     constexpr bool kSelfInner = KIND == 3 || KIND == 5;
     constexpr int kSI = 4;
+#ifndef MRV_CLAIM_EXH
+#define MRV_CLAIM_EXH 4
+#endif
+    // tiles taken per claim: exhaustive calls run many short tiles, and a single
+    // atomic counter serves at most ~80 M claims/s; early-terminating calls take
+    // one at a time so that every tile sees the latest outcomes when it starts
+    constexpr int kClaim = KIND >= 3 ? MRV_CLAIM_EXH : 1;
     constexpr int WG = validate_wg(KIND);
     constexpr int kWaves = WG / kWave;
     extern __shared__ float4 dyn[];
@@ -926,6 +933,7 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
     __shared__ unsigned s_focus;
     // thread 0's claim state and tile counts, kept in LDS rather than registers
     __shared__ long long s_kcur, s_off0, s_off1;   // current rank and its tile range [off[k], off[k + 1])
+    __shared__ long long s_gnext, s_gend;          // tiles claimed by the last atomic and not yet run
     __shared__ int s_phase_cur;
     __shared__ unsigned long long s_nrun, s_nskip, s_nstates;
 
@@ -946,6 +954,8 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
     unsigned long long c_rr = 0, c_env = 0, c_self = 0;                 // wave-uniform counters
     if (tid == 0) {
         s_kcur = 0;
+        s_gnext = 0;
+        s_gend = 0;
         s_off0 = 0;
         s_off1 = -1;                    // no rank range cached yet
         s_phase_cur = 0;
@@ -973,7 +983,13 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
                     if (s_key != 0xFFFFFFFFu) atomicMin(cd.word + s_q, s_key);
                 }
             }
-            const long long g = (long long)atomicAdd(&w64[1], 1ull);
+            // kClaim consecutive tiles per atomic (one counter serves the whole chip)
+            long long g = s_gnext;
+            if (g >= s_gend) {
+                g = (long long)atomicAdd(&w64[1], (unsigned long long)kClaim);
+                s_gend = g + kClaim;
+            }
+            s_gnext = g + 1;
             int q = -1, nv = 0, phase = 0, C = 1;
             unsigned known = !kMV ? 0xFFFFFFFFu : 0u, focus = 0u;
             if (g < gtotal) {
