@@ -225,8 +225,8 @@ int simd_mv(int n_robots, const int* nj, const int* jtype, const double* jfixed,
 
     long long states = 0;
 #ifdef _OPENMP
-    if (nthreads > 0) omp_set_num_threads(nthreads);
-#pragma omp parallel reduction(+ : states)
+    const int nt = nthreads > 0 ? nthreads : omp_get_max_threads();   /* this call only */
+#pragma omp parallel num_threads(nt) reduction(+ : states)
 #endif
     {
         /* 32-byte aligned: the vectors are moved with aligned AVX loads and stores */

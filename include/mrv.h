@@ -280,6 +280,11 @@ int64_t mrv_motion_steps(const double* dq, int32_t dof, double step, int32_t met
 typedef struct {
     int32_t chunk;           /* timesteps per tile; 0 = automatic */
     int32_t wg_per_cu;       /* persistent workgroups per compute unit; 0 = occupancy limit */
+    int32_t interleave;      /* MV tile order of the calls that ask for MRV_ORDER_BISECT (the default):
+                              * 0 or 1 = golden-ratio bisection, 2 = rake (as MRV_ORDER_RAKE),
+                              * 3 = consecutive timesteps (as MRV_ORDER_LINEAR); FFC ignores it */
+    int32_t claim;           /* tiles a workgroup takes per claim on the launch's tile counter:
+                              * 0 = automatic (4 for exhaustive calls, 1 otherwise), else 1..16 */
 } mrv_tiling;
 /* Set the tiling used for (team, kind), kind 0 = MV, 1 = FFC, by the calls whose
  * MRV_EXHAUSTIVE flag equals that of flags (other flag bits are ignored): calls
@@ -291,16 +296,20 @@ mrv_status mrv_set_tiling(mrv_ctx ctx, int32_t team, int32_t kind, uint32_t flag
 mrv_status mrv_get_tiling(mrv_ctx ctx, int32_t team, int32_t kind, uint32_t flags, mrv_tiling* tiling);
 
 /* Search the tiling for (team, env, kind, flags) by timing the validation kernel on
- * the given host paths (a representative sample of the workload) with every
- * chunk size that fits in LDS and a few workgroup counts per compute unit; the
- * fastest is set for the team (as mrv_set_tiling with the same flags would) and
- * returned in *best.
+ * the given host paths (a representative sample of the workload), one field at a
+ * time from the team's current tiling: every chunk size that fits in LDS, then
+ * workgroups per compute unit, then tiles per claim, then (early-terminating MV)
+ * the interleave, each trial the best of two timed runs after a warm-up.  The
+ * search stops after MRV_TUNE_BUDGET_MS of trial time and keeps the best tiling
+ * found so far; the fastest is set for the team (as mrv_set_tiling with the same
+ * flags would) and returned in *best.
  * Results are cached per context by the team's shape (spheres, frames, groups,
  * robots), the environment's obstacle counts and the flags: a later call with
  * an equal key returns the cached tiling without timing.  The answers of MV/FFC
  * never depend on the tiling.  Trials run on a private copy of the team's
  * descriptor; MRV_E_BUSY while a served request or a captured graph uses the
  * team. */
+#define MRV_TUNE_BUDGET_MS 8000
 mrv_status mrv_autotune(mrv_ctx ctx, int32_t team, int32_t env, int32_t kind, const mrv_paths* sample,
                         uint32_t flags, mrv_tiling* best);
 
@@ -325,10 +334,12 @@ typedef struct {
     uint64_t tiles_run, tiles_skipped;
     uint64_t states_evaluated;   /* robot-states run through FK and tests */
     uint64_t states_covered;     /* sum over queries of n_robots * T */
-    uint64_t rr_tests, env_tests, self_tests;   /* sphere tests executed (obstacle tests skipped by the
-                                                   bounding-box cull are not counted) */
+    uint64_t rr_tests, env_tests, self_tests;   /* sphere tests executed: robot-robot, robot-obstacle
+                                                   (sphere, box and cylinder obstacles; those skipped by
+                                                   the bounding-box cull are not counted), self */
     uint64_t near_rechecks;      /* tests re-evaluated in FP64 */
     double kernel_ms;            /* validation kernel time of the last call (device events) */
+    uint64_t point_tests;        /* sphere-point tests executed (point clouds, grid cells walked) */
 } mrv_stats;
 /* Counters of the last MV/FFC call on this context (synchronises the stream). */
 mrv_status mrv_last_stats(mrv_ctx ctx, mrv_stats* out);

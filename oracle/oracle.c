@@ -504,11 +504,12 @@ static void ffc_one(const orc_team* tm, const orc_paths* P, int64_t qi, double* 
     out[0] = -1; out[1] = -1; out[2] = -1;
 }
 
+/* Threads of one call: nthreads if positive, else the OpenMP default; given to
+ * that call's parallel region only, so the process-wide default is unchanged. */
 static int set_threads(int nthreads)
 {
 #ifdef _OPENMP
-    if (nthreads > 0) omp_set_num_threads(nthreads);
-    return omp_get_max_threads();
+    return nthreads > 0 ? nthreads : omp_get_max_threads();
 #else
     (void)nthreads;
     return 1;
@@ -523,10 +524,10 @@ int orc_mv(const orc_team* tm, const orc_env* E, const orc_paths* P, int64_t q0,
            int32_t check_env, int32_t exhaustive, uint32_t focus, uint8_t* valid_out, int64_t* first_hit_out,
            int32_t nthreads)
 {
-    set_threads(nthreads);
+    const int nt = set_threads(nthreads);
     int S = team_total_spheres(tm);
     int err = 0;
-#pragma omp parallel
+#pragma omp parallel num_threads(nt)
     {
         double* buf = (double*)malloc(sizeof(double) * 4 * (size_t)(S > 0 ? S : 1));
         if (!buf) {
@@ -549,10 +550,10 @@ int orc_mv(const orc_team* tm, const orc_env* E, const orc_paths* P, int64_t q0,
 int orc_ffc(const orc_team* tm, const orc_paths* P, int64_t q0, int64_t q1, int32_t* out,
             int32_t nthreads)
 {
-    set_threads(nthreads);
+    const int nt = set_threads(nthreads);
     int S = team_total_spheres(tm);
     int err = 0;
-#pragma omp parallel
+#pragma omp parallel num_threads(nt)
     {
         double* buf = (double*)malloc(sizeof(double) * 4 * (size_t)(S > 0 ? S : 1));
         if (!buf) {

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <array>
@@ -51,7 +52,7 @@ struct TeamHost {
     void* dmem = nullptr;
     std::vector<int> dof;
     int max_dof = 0;
-    mrv_tiling tiling[2][2] = {{{0, 0}, {0, 0}}, {{0, 0}, {0, 0}}};   // [kind][exhaustive]
+    mrv_tiling tiling[2][2] = {};   // [kind][exhaustive]
     int inflight = 0;
 };
 
@@ -70,6 +71,12 @@ namespace {
 size_t lds_per_t(const TeamHost& tm);
 int default_chunk(const TeamHost& tm, int kind, int exhaustive);
 inline int mode_of(uint32_t flags) { return (flags & MRV_EXHAUSTIVE) ? 1 : 0; }
+// Tiles per claim when the tiling leaves it automatic: exhaustive calls run many
+// short tiles, and one atomic counter serves only about 80 M claims/s (the arm
+// workload's exhaustive MV was held to 31 ms by it at one tile per claim);
+// early-terminating calls take one tile at a time, so that each tile sees the
+// outcomes known when it starts.
+inline int default_claim(uint32_t flags) { return (flags & MRV_EXHAUSTIVE) ? 4 : 1; }
 
 inline double sq(double v) { return v * v; }
 
@@ -752,6 +759,7 @@ void launch_plan(mrv_ctx ctx, const ScratchView& v, const CallPlan& pl, void* ou
     cd.q_focus = pl.q_focus;
     cd.eps32 = (float)ctx->eps;
     cd.chunk_floor = std::max(1, pl.min_chunk);
+    cd.claim = pl.claim > 0 ? pl.claim : default_claim(pl.flags);
     cd.max_nt = (long long)v.bins - 2;
     cd.n_wp = pl.dp.n_wp;
     cd.wp_begin = pl.dp.wp_begin;
@@ -823,6 +831,7 @@ CallPlan single_plan(const TeamHost& tm, const EnvHost* env, int kind, uint32_t 
     pl.min_chunk = tm.dev.chunk[kind][m];
     pl.lds = lds_bytes_for(tm, tm.dev.chunk[kind][m]);
     pl.wg_per_cu = tm.tiling[kind][m].wg_per_cu;
+    pl.claim = tm.tiling[kind][m].claim;
     return pl;
 }
 
@@ -1279,12 +1288,15 @@ mrv_status mrv_set_tiling(mrv_ctx ctx, int32_t team, int32_t kind, uint32_t flag
         if (tiling->chunk > 0 && lds_bytes_for(tm, tiling->chunk) > (size_t)kLdsBudget - 2 * 1024)
             throw Err{MRV_E_INVALID, "chunk does not fit in LDS for this team"};
         if (tiling->wg_per_cu < 0 || tiling->wg_per_cu > 32) throw Err{MRV_E_INVALID, "wg_per_cu out of range"};
+        if (tiling->interleave < 0 || tiling->interleave > 3) throw Err{MRV_E_INVALID, "interleave out of range"};
+        if (tiling->claim < 0 || tiling->claim > 16) throw Err{MRV_E_INVALID, "claim out of range"};
         const int m = mode_of(flags);
         set_device(ctx);
         // calls queued on the context stream read the descriptor: let them finish first
         HIPCHK(hipStreamSynchronize(ctx->stream));
         tm.tiling[kind][m] = *tiling;
         tm.dev.chunk[kind][m] = tiling->chunk > 0 ? tiling->chunk : default_chunk(tm, kind, m);
+        tm.dev.interleave[kind][m] = tiling->interleave;
         HIPCHK(hipMemcpy(tm.d_dev, &tm.dev, sizeof(TeamDev), hipMemcpyHostToDevice));
     });
 }
@@ -1299,6 +1311,8 @@ mrv_status mrv_get_tiling(mrv_ctx ctx, int32_t team, int32_t kind, uint32_t flag
         const int m = mode_of(flags);
         mrv_tiling t = tm.tiling[kind][m];
         t.chunk = tm.dev.chunk[kind][m];
+        t.interleave = kind == 1 ? 3 : std::max(1, t.interleave);
+        if (t.claim == 0) t.claim = default_claim(flags);
         *tiling = t;
     });
 }
@@ -1321,6 +1335,7 @@ mrv_status mrv_last_stats(mrv_ctx ctx, mrv_stats* out)
         r.env_tests = s[ST_ENV_TESTS];
         r.self_tests = s[ST_SELF_TESTS];
         r.near_rechecks = s[ST_RECHECKS];
+        r.point_tests = s[ST_PT_TESTS];
         float ms = 0.f;
         if (ctx->sc.last_kind >= 0 && hipEventElapsedTime(&ms, ctx->sc.ev0, ctx->sc.ev1) == hipSuccess)
             r.kernel_ms = ms;
@@ -1418,7 +1433,7 @@ mrv_status mrv_autotune(mrv_ctx ctx, int32_t team, int32_t env, int32_t kind, co
                                 std::to_string(tm.dev.n_self) + "|" + std::to_string(e.n_sph) + "," +
                                 std::to_string(e.n_box) + "," + std::to_string(e.n_cyl) + "," +
                                 std::to_string(e.n_pts) + "|" + std::to_string(kind) + "|" + std::to_string(f);
-        mrv_tiling choice{0, 0};
+        mrv_tiling choice{};
         auto hit = ctx->tune_cache.find(key);
         if (hit != ctx->tune_cache.end()) {
             choice = hit->second;
@@ -1444,31 +1459,68 @@ mrv_status mrv_autotune(mrv_ctx ctx, int32_t team, int32_t env, int32_t kind, co
             for (int c : {1, 2, 3, 4, 5, 6, 8, 10, 12, 16, 20, 24, 32, 48, 64})
                 if (c <= cmax) chunks.push_back(c);
             if (chunks.empty() || chunks.back() != cmax) chunks.push_back(cmax);
-            float best_ms = 1e30f;
             // trials run on a private copy of the team's descriptor, so calls and served
             // requests that use the team meanwhile keep its tiling
             TeamHost trial = tm;
             ctx->tune_desc.ensure(sizeof(TeamDev));
             trial.d_dev = (TeamDev*)ctx->tune_desc.p;
-            for (int c : chunks) {
-                for (int wg : {0, 1, 2}) {
-                    trial.dev.chunk[kind][mode_of(f)] = c;
-                    trial.tiling[kind][mode_of(f)] = mrv_tiling{c, wg};
-                    HIPCHK(hipMemcpyAsync(trial.d_dev, &trial.dev, sizeof(TeamDev), hipMemcpyHostToDevice, ctx->stream));
-                    float ms_min = 1e30f;
-                    for (int rep = 0; rep < 3; ++rep) {
-                        run_plan(ctx, ctx->sc, single_plan(trial, ev, kind, f, dp, mT), ctx->out_buf.p, ctx->stream);
-                        HIPCHK(hipStreamSynchronize(ctx->stream));
-                        float ms = 0.f;
-                        HIPCHK(hipEventElapsedTime(&ms, ctx->sc.ev0, ctx->sc.ev1));
-                        if (rep > 0) ms_min = std::min(ms_min, ms);
-                    }
-                    if (ms_min < best_ms) {
-                        best_ms = ms_min;
-                        choice = mrv_tiling{c, wg};
-                    }
+            const int m = mode_of(f);
+            const auto t_start = std::chrono::steady_clock::now();
+            auto over_budget = [&] {
+                return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count() >
+                       MRV_TUNE_BUDGET_MS;
+            };
+            // best of two timed runs after a warm-up
+            auto run_trial = [&](const mrv_tiling& t) {
+                trial.dev.chunk[kind][m] = t.chunk;
+                trial.dev.interleave[kind][m] = t.interleave;
+                trial.tiling[kind][m] = t;
+                HIPCHK(hipMemcpyAsync(trial.d_dev, &trial.dev, sizeof(TeamDev), hipMemcpyHostToDevice, ctx->stream));
+                float ms_min = 1e30f;
+                for (int rep = 0; rep < 3; ++rep) {
+                    run_plan(ctx, ctx->sc, single_plan(trial, ev, kind, f, dp, mT), ctx->out_buf.p, ctx->stream);
+                    HIPCHK(hipStreamSynchronize(ctx->stream));
+                    float ms = 0.f;
+                    HIPCHK(hipEventElapsedTime(&ms, ctx->sc.ev0, ctx->sc.ev1));
+                    if (rep > 0) ms_min = std::min(ms_min, ms);
                 }
+                return ms_min;
+            };
+            choice = tm.tiling[kind][m];
+            choice.chunk = tm.dev.chunk[kind][m];
+            float best_ms = run_trial(choice);
+            auto consider = [&](const mrv_tiling& t) {
+                if (over_budget()) return;
+                const float ms = run_trial(t);
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    choice = t;
+                }
+            };
+            // one field at a time, each from the best tiling so far
+            for (int c : chunks) {
+                mrv_tiling t = choice;
+                t.chunk = c;
+                if (c != choice.chunk) consider(t);
             }
+            const int variant = kind == 1 ? (m ? 4 : 1) : (m ? 3 : 0);
+            const int occ = validate_blocks_per_cu(variant, lds_bytes_for(trial, choice.chunk));
+            for (int wg : {1, 2, 3, 4, 6, 8, 0}) {
+                mrv_tiling t = choice;
+                t.wg_per_cu = wg;
+                if ((wg == 0 || wg < occ) && wg != choice.wg_per_cu) consider(t);
+            }
+            for (int cl : {1, 2, 4, 8}) {
+                mrv_tiling t = choice;
+                t.claim = cl;
+                if (cl != (choice.claim ? choice.claim : default_claim(f))) consider(t);
+            }
+            if (kind == 0 && m == 0)
+                for (int il : {1, 2, 3}) {
+                    mrv_tiling t = choice;
+                    t.interleave = il;
+                    if (il != std::max(1, choice.interleave)) consider(t);
+                }
             ctx->tune_cache[key] = choice;
         }
         // apply the choice to the team
@@ -1478,6 +1530,7 @@ mrv_status mrv_autotune(mrv_ctx ctx, int32_t team, int32_t env, int32_t kind, co
         HIPCHK(hipStreamSynchronize(ctx->stream));
         live.tiling[kind][mode_of(f)] = choice;
         live.dev.chunk[kind][mode_of(f)] = choice.chunk;
+        live.dev.interleave[kind][mode_of(f)] = choice.interleave;
         HIPCHK(hipMemcpy(live.d_dev, &live.dev, sizeof(TeamDev), hipMemcpyHostToDevice));
         *best = choice;
     });

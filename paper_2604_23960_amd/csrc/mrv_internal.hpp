@@ -50,7 +50,7 @@ enum RecheckKind : int { RK_RR = 0, RK_SELF = 1, RK_ENV_SPH = 2, RK_ENV_BOX = 3,
 // Per-call counters (uint64 each), see mrv_stats.
 enum StatSlot : int {
     ST_TILES_RUN = 0, ST_TILES_SKIPPED, ST_STATES_EVAL, ST_STATES_COVERED,
-    ST_RR_TESTS, ST_ENV_TESTS, ST_SELF_TESTS, ST_RECHECKS, ST_COUNT
+    ST_RR_TESTS, ST_ENV_TESTS, ST_SELF_TESTS, ST_RECHECKS, ST_PT_TESTS, ST_COUNT
 };
 
 // Resident team.  Spheres of all robots are flattened in robot order; frames of
@@ -70,6 +70,8 @@ struct TeamDev {
     int TS;                // LDS floats per timestep of a tile: five slot rows, or three and the FK frames,
                            // or the joint transforms and the frames, whichever is largest
     int chunk[2][2];       // timesteps per tile: [MV / FFC][early-terminating / exhaustive]
+    int interleave[2][2];  // tuned MV tile order for calls asking for MRV_ORDER_BISECT (0, 1 golden, 2 rake,
+                           // 3 consecutive), as chunk
     int lds_per_t;         // LDS bytes one timestep of a tile needs
     float r_max;           // largest sphere radius of the team
     float origin[4];       // team origin o (centre of the bases' bounding box, an FP32 value): FK, sphere
@@ -150,6 +152,7 @@ struct CallDev {
     const unsigned* q_focus;    // per query, or null: focus0 for every query
     float eps32;                // near band in metres before per-query scaling
     int chunk_floor;            // smallest tile length the call's scratch was sized for
+    int claim;                  // tiles taken per claim on the tile counter (>= 1)
     long long max_nt;           // most tiles a query may have (tile bins - 2)
     long long n_wp;
     const long long* wp_begin;

@@ -369,7 +369,15 @@ __global__ void k_query_info(CallDev cd)
     if (ok) {
         nt = tiles_of(T, chunk);
         if (nt > cd.max_nt) ok = false;     // cannot happen: T <= max_T and chunk >= chunk_floor
-        else g = golden_step((int)nt);
+        else {
+            // tile order: FFC and MRV_ORDER_LINEAR consecutive timesteps (g = 0), MRV_ORDER_RAKE
+            // the paper's rake (g = 1), else the team's tuned interleave, by default the
+            // golden-ratio step that spreads every prefix of a query's tiles over its motion
+            const unsigned of = cd.flags & (MRV_ORDER_RAKE | MRV_ORDER_LINEAR);
+            const int order = cd.kind == 1 || (of & MRV_ORDER_LINEAR) ? 3 : (of & MRV_ORDER_RAKE) ? 2
+                            : tm.interleave[0][(cd.flags & MRV_EXHAUSTIVE) ? 1 : 0];
+            g = order == 3 ? 0 : order == 2 ? 1 : golden_step((int)nt);
+        }
     }
     // Near band.  Every FP32 coordinate the kernels form is relative to the team's
     // origin (frames, spheres) or to the environment's (obstacles, and the spheres
@@ -750,7 +758,7 @@ template <int J, class CD>
 __device__ __forceinline__ void env_tasks(const CD& cd, CTeam* tm, CEnv* env, const float* sp,
                                           const int* task, int nch, float ro_max, float eps, bool exhaustive, int q,
                                           unsigned focus, bool fall, const int* s_t, int* s_hit,
-                                          unsigned long long& c_env, int lane, float3 off)
+                                          unsigned long long& c_env, unsigned long long* s_npt, int lane, float3 off)
 {
     const int GS = tm->GS, GSp = tm->GSp, TS = tm->TS;
     int c[J], a[J];
@@ -853,12 +861,14 @@ __device__ __forceinline__ void env_tasks(const CD& cd, CTeam* tm, CEnv* env, co
             }
             const float plo = fmaxf(Rp - eps, 0.f), phi = Rp + eps;
             const float plo2 = plo * plo, phi2 = phi * phi;
+            unsigned npt = 0;           // points tested by this lane
             if (lo3[0] <= hi3[0])
                 for (int cz = lo3[2]; cz <= hi3[2]; ++cz)
                     for (int cy = lo3[1]; cy <= hi3[1]; ++cy) {
                         const int crow = (cz * env->grid_dim[1] + cy) * env->grid_dim[0];
                         const int pb = env->cell_start[crow + lo3[0]];
                         const int pe = env->cell_start[crow + hi3[0] + 1];
+                        npt += (unsigned)(pe - pb);
                         for (int p = pb; p < pe; ++p) {
                             const float4 Pt = env->pts32[p];
                             const float dx = x[j] - Pt.x, dy = y[j] - Pt.y, dz = z[j] - Pt.z;
@@ -870,6 +880,7 @@ __device__ __forceinline__ void env_tasks(const CD& cd, CTeam* tm, CEnv* env, co
                             }
                         }
                     }
+            if (npt) atomicAdd(s_npt, (unsigned long long)npt);
         }
         if (unsure && !(hit && !exhaustive)) {
             // rare: find the near obstacles and queue each for FP64 re-evaluation
@@ -914,13 +925,7 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
     // inner loop (no early exit to honour between timesteps)
     constexpr bool kSelfInner = KIND == 3 || KIND == 5;
     constexpr int kSI = 4;
-#ifndef MRV_CLAIM_EXH
-#define MRV_CLAIM_EXH 4
-#endif
-    // tiles taken per claim: exhaustive calls run many short tiles, and a single
-    // atomic counter serves at most ~80 M claims/s; early-terminating calls take
-    // one at a time so that every tile sees the latest outcomes when it starts
-    constexpr int kClaim = KIND >= 3 ? MRV_CLAIM_EXH : 1;
+
     constexpr int WG = validate_wg(KIND);
     constexpr int kWaves = WG / kWave;
     extern __shared__ float4 dyn[];
@@ -935,7 +940,7 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
     __shared__ long long s_kcur, s_off0, s_off1;   // current rank and its tile range [off[k], off[k + 1])
     __shared__ long long s_gnext, s_gend;          // tiles claimed by the last atomic and not yet run
     __shared__ int s_phase_cur;
-    __shared__ unsigned long long s_nrun, s_nskip, s_nstates;
+    __shared__ unsigned long long s_nrun, s_nskip, s_nstates, s_npt;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -962,6 +967,7 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
         s_nrun = 0;
         s_nskip = 0;
         s_nstates = 0;
+        s_npt = 0;
         s_q = -1;                       // no tile yet whose outcome is to publish
         s_nv = 0;
     }
@@ -983,11 +989,12 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
                     if (s_key != 0xFFFFFFFFu) atomicMin(cd.word + s_q, s_key);
                 }
             }
-            // kClaim consecutive tiles per atomic (one counter serves the whole chip)
+            // cd.claim consecutive tiles per atomic (one counter serves the whole chip)
             long long g = s_gnext;
             if (g >= s_gend) {
-                g = (long long)atomicAdd(&w64[1], (unsigned long long)kClaim);
-                s_gend = g + kClaim;
+                const int kc = cd.claim;
+                g = (long long)atomicAdd(&w64[1], (unsigned long long)kc);
+                s_gend = g + kc;
             }
             s_gnext = g + 1;
             int q = -1, nv = 0, phase = 0, C = 1;
@@ -1036,11 +1043,14 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
                 s_eps = cd.q_eps[q];
                 const int T = cd.T[q];
                 const int nt = cd.nt[q];
+                // tile k of the query: consecutive timesteps (g = 0), or every nt-th from
+                // the interleaved base (k g) mod nt
+                const int gq = cd.gstep[q];
                 int base, stride;
-                if (!kMV || (flags & MRV_ORDER_LINEAR)) {
+                if (!kMV || gq == 0) {
                     base = k * C; stride = 1;
                 } else {
-                    base = (flags & MRV_ORDER_RAKE) ? k : (int)(((long long)k * cd.gstep[q]) % nt);
+                    base = (int)(((long long)k * gq) % nt);
                     stride = nt;
                 }
                 for (int c = 0; c < C; ++c) {
@@ -1195,7 +1205,7 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
                 for (; task < ntask && !(!exhaustive && flag_read(&s_hit)); task += kWaves) {
                     const int tk[1] = { task };
                     env_tasks<1>(cd, tm, env, sp, tk, nch, ro_max, eps, exhaustive, q, focus, fall, s_t, &s_hit, c_env,
-                                 lane, off);
+                                 &s_npt, lane, off);
                 }
             }
 
@@ -1427,6 +1437,7 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
         atomicAdd(&cd.stats[ST_TILES_RUN], s_nrun);
         atomicAdd(&cd.stats[ST_TILES_SKIPPED], s_nskip);
         atomicAdd(&cd.stats[ST_STATES_EVAL], s_nstates);
+        if (s_npt) atomicAdd(&cd.stats[ST_PT_TESTS], s_npt);
     }
 }
 

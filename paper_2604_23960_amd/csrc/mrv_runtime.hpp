@@ -159,6 +159,7 @@ struct CallPlan {
     int min_chunk;                     // smallest timesteps-per-tile among the queries' teams
     size_t lds;                        // dynamic LDS: max over the queries' teams
     int wg_per_cu;                     // 0 = occupancy limit
+    int claim;                         // tiles per claim, 0 = automatic
 };
 
 // Device-side descriptors a served request needs, resolved at submit time.

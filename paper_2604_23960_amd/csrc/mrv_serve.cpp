@@ -448,6 +448,7 @@ struct ServeLoop::Impl {
         pl.min_chunk = min_chunk;
         pl.lds = lds;
         pl.wg_per_cu = 0;
+        pl.claim = 0;
         s.plan = pl;
         s.nout = nout;
         s.attempts = 0;

@@ -34,10 +34,20 @@ def _sleep_until(t_abs: float):
 
 
 def summarize(lat: np.ndarray, t_first: float, t_last: float, states: float) -> dict:
+    """Throughput and latency of one run.  ``sustained``: the queue did not grow over
+    the run, i.e. the mean latency of the last quarter of the requests (in arrival
+    order) is within twice that of the first quarter plus a millisecond."""
     span = max(t_last - t_first, 1e-9)
+    q = max(len(lat) // 4, 1)
+    head, tail = float(lat[:q].mean()), float(lat[-q:].mean())
     return dict(queries=int(len(lat)), seconds=span, qps=len(lat) / span, states_per_s=states / span,
                 p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
-                mean_ms=float(lat.mean() * 1e3))
+                mean_ms=float(lat.mean() * 1e3), first_quarter_ms=head * 1e3, last_quarter_ms=tail * 1e3,
+                sustained=bool(tail <= 2.0 * head + 1e-3))
+
+
+def _states(reqs) -> float:
+    return float(sum(r.horizon * len(r.paths.wp_begin[:-1]) // max(r.paths.n_queries, 1) for r in reqs))
 
 
 def prepare(reqs):
@@ -98,9 +108,8 @@ def run_served(ctx: mrv.Context, handles, env: int, reqs, hps, rate: float, seed
     if errors:
         raise errors[0]
     lat = done - arrive
-    states = float(sum(r.horizon * len(r.paths.wp_begin[:-1]) // max(r.paths.n_queries, 1) for r in reqs))
     results = [o[0] if r.kind == 0 else o for o, r in zip(outs, reqs)]
-    return summarize(lat, arrive.min(), done.max(), states), [np.atleast_1d(x) for x in results]
+    return summarize(lat, arrive.min(), done.max(), _states(reqs)), [np.atleast_1d(x) for x in results]
 
 
 def run_plain(ctx: mrv.Context, handles, env: int, reqs, hps, rate: float, seed: int = 0,
@@ -120,5 +129,58 @@ def run_plain(ctx: mrv.Context, handles, env: int, reqs, hps, rate: float, seed:
             results[i] = ctx.ffc(handles[r.client], hps[i], flags_ffc)
         done[i] = time.perf_counter()
     lat = done - arrive
-    states = float(sum(r.horizon * len(r.paths.wp_begin[:-1]) // max(r.paths.n_queries, 1) for r in reqs))
-    return summarize(lat, arrive.min(), done.max(), states), results
+    return summarize(lat, arrive.min(), done.max(), _states(reqs)), results
+
+
+def run_plain_streams(ctxs, handles_per_ctx, envs, reqs, hps, rate: float, seed: int = 0,
+                      flags_mv: int = mrv.CHECK_ENV, flags_ffc: int = 0):
+    """The plain form on several streams: one host thread per context (each with
+    its own stream and resident copies of the teams), request i taken by thread
+    i mod len(ctxs) at its arrival time, one synchronous call per query."""
+    n, k = len(reqs), len(ctxs)
+    arr = arrival_times(n, rate, seed)
+    arrive = np.zeros(n)
+    done = np.zeros(n)
+    results = [None] * n
+    t0 = time.perf_counter() + 0.01
+    errors = []
+
+    def worker(w):
+        try:
+            ctx, handles, env = ctxs[w], handles_per_ctx[w], envs[w]
+            for i in range(w, n, k):
+                _sleep_until(t0 + arr[i])
+                arrive[i] = max(t0 + arr[i], arrive[i])
+                r = reqs[i]
+                if r.kind == 0:
+                    results[i] = ctx.mv(handles[r.client], env, hps[i], flags_mv)
+                else:
+                    results[i] = ctx.ffc(handles[r.client], hps[i], flags_ffc)
+                done[i] = time.perf_counter()
+        except Exception as e:
+            errors.append(e)
+
+    ths = [threading.Thread(target=worker, args=(w,)) for w in range(k)]
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    if errors:
+        raise errors[0]
+    arrive[:] = t0 + arr
+    lat = done - arrive
+    return summarize(lat, arrive.min(), done.max(), _states(reqs)), results
+
+
+def binding_overhead_us(ctx: mrv.Context, handle: int, dof_stride: int, reps: int = 2000) -> float:
+    """Host time of one plain-form call through the Python binding (output array,
+    argument marshalling, the C call) on an empty query list, which the library
+    answers before any device work: what the plain loop adds per query on top of
+    the library itself."""
+    from .workloads import paths_from_lists
+    hp = mrv.HostPaths(paths_from_lists([], dof_stride))
+    ctx.mv(handle, -1, hp, 0)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.mv(handle, -1, hp, 0)
+    return (time.perf_counter() - t0) / reps * 1e6

@@ -68,14 +68,17 @@ class Conflict(C.Structure):
 
 
 class Tiling(C.Structure):
-    _fields_ = [("chunk", C.c_int32), ("wg_per_cu", C.c_int32)]
+    _fields_ = [("chunk", C.c_int32), ("wg_per_cu", C.c_int32), ("interleave", C.c_int32), ("claim", C.c_int32)]
+
+    def as_tuple(self):
+        return self.chunk, self.wg_per_cu, self.interleave, self.claim
 
 
 class Stats(C.Structure):
     _fields_ = [("tiles_run", C.c_uint64), ("tiles_skipped", C.c_uint64),
                 ("states_evaluated", C.c_uint64), ("states_covered", C.c_uint64),
                 ("rr_tests", C.c_uint64), ("env_tests", C.c_uint64), ("self_tests", C.c_uint64),
-                ("near_rechecks", C.c_uint64), ("kernel_ms", C.c_double)]
+                ("near_rechecks", C.c_uint64), ("kernel_ms", C.c_double), ("point_tests", C.c_uint64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -310,16 +313,18 @@ class Context:
         return out[:len(sq)]
 
     # -- tuning / stats
-    def set_tiling(self, team: int, kind: int, chunk: int = 0, wg_per_cu: int = 0, flags: int | None = None):
-        """flags=None sets both modes (early-terminating and exhaustive calls)."""
-        t = Tiling(chunk, wg_per_cu)
+    def set_tiling(self, team: int, kind: int, chunk: int = 0, wg_per_cu: int = 0, flags: int | None = None,
+                   interleave: int = 0, claim: int = 0):
+        """flags None: both modes (early-terminating and exhaustive)."""
+        t = Tiling(chunk, wg_per_cu, interleave, claim)
         for f in ((0, EXHAUSTIVE) if flags is None else (flags,)):
             check(lib().mrv_set_tiling(self.h, team, kind, f, C.byref(t)))
 
     def get_tiling(self, team: int, kind: int, flags: int = 0):
+        """(chunk, wg_per_cu, interleave, claim) in effect."""
         t = Tiling()
         check(lib().mrv_get_tiling(self.h, team, kind, flags, C.byref(t)))
-        return t.chunk, t.wg_per_cu
+        return t.as_tuple()
 
     def last_stats(self) -> dict:
         s = Stats()
@@ -330,7 +335,7 @@ class Context:
         hp = sample_paths if isinstance(sample_paths, HostPaths) else HostPaths(sample_paths)
         t = Tiling()
         check(lib().mrv_autotune(self.h, team, env, kind, C.byref(hp.desc), flags, C.byref(t)))
-        return t.chunk, t.wg_per_cu
+        return t.as_tuple()
 
     # -- captured graphs
     def graph_create(self, team: int, env: int, kind: int, dpaths: DevicePaths, flags: int, out_ptr: int):

@@ -369,6 +369,39 @@ def sample_configs(rng: np.random.Generator, team: list[Robot], n: int, dof_stri
     return out
 
 
+def valid_configs(rng: np.random.Generator, team: list[Robot], n: int, dof_stride: int, decide,
+                  batch: int = 8192, max_rounds: int = 256) -> tuple[np.ndarray, dict]:
+    """n team configurations valid as single states, by the valid-endpoint protocol
+    of the paper's experiments (§IV-A): per-robot configurations uniform in the
+    joint limits are kept when valid for that robot alone (its self and obstacle
+    tests), then composed at random and kept when the whole team's state is
+    valid.  ``decide(robots, configs)`` returns, for configs [m, len(robots),
+    dof_stride], whether each state is valid; it is the caller's validity test
+    (the library or the oracle), so this module holds no collision arithmetic.
+    Returns [n, len(team), dof_stride] and the acceptance rates."""
+    alone, acc_alone = [], []
+    for rob in team:
+        good, tried = [], 0
+        while sum(len(g) for g in good) < min(n, batch) and tried < max_rounds * batch:
+            cand = sample_configs(rng, [rob], batch, dof_stride)
+            good.append(cand[np.asarray(decide([rob], cand), bool)])
+            tried += batch
+        pool = np.concatenate(good)[:, 0, :]
+        if len(pool) == 0:
+            raise RuntimeError(f"no configuration of {rob.name} is valid alone")
+        alone.append(pool)
+        acc_alone.append(len(pool) / tried)
+    kept, tried = [], 0
+    while sum(len(k) for k in kept) < n and tried < max_rounds * batch:
+        cand = np.stack([a[rng.integers(0, len(a), batch)] for a in alone], axis=1)
+        kept.append(cand[np.asarray(decide(team, cand), bool)])
+        tried += batch
+    out = np.concatenate(kept)
+    if len(out) < n:
+        raise RuntimeError(f"only {len(out)} of {n} valid team configurations found")
+    return out[:n], dict(alone=acc_alone, team=len(out) / tried)
+
+
 def random_timed_paths(rng: np.random.Generator, team: list[Robot], n_queries: int,
                        len_lo: int, len_hi: int, k_lo: int, k_hi: int, dof_stride: int,
                        lengths: np.ndarray | None = None) -> Paths:
@@ -410,26 +443,39 @@ class Workload:
     notes: str = ""
 
 
-def disks_workload(n_queries: int = 4096, seed: int = 0) -> Workload:
-    """Two disks (r=0.05) in the unit square among 16 circles; straight lines at 0.005 L2 per step."""
+def _endpoints(rng, team, n, dof_stride, decide):
+    """Start and goal configurations: uniform in the joint limits, or (decide given)
+    valid team states drawn by valid_configs, starts first."""
+    if decide is None:
+        return sample_configs(rng, team, n, dof_stride), sample_configs(rng, team, n, dof_stride), None
+    both, acc = valid_configs(rng, team, 2 * n, dof_stride, decide)
+    return both[:n], both[n:], acc
+
+
+def disks_workload(n_queries: int = 4096, seed: int = 0, decide=None) -> Workload:
+    """Two disks (r=0.05) in the unit square among 16 circles; straight lines at 0.005
+    L2 per step.  With ``decide`` (see valid_configs) the endpoints are valid states,
+    uniform in collision-free space."""
     team = [disk_robot(0.05, "disk0"), disk_robot(0.05, "disk1")]
     env = circles_env(seed)
     rng = _rng(seed, STREAM_WORK)
-    s = sample_configs(rng, team, n_queries, 2)
-    g = sample_configs(rng, team, n_queries, 2)
+    s, g, acc = _endpoints(rng, team, n_queries, 2, decide and (lambda rs, c: decide(rs, env, c)))
     paths = straight_line_paths(s, g, [2, 2], 0.005, "l2", 2)
-    return Workload("disks-2r-16circles", team, env, paths, "mv+ffc")
+    return Workload("disks-2r-16circles", team, env, paths, "mv+ffc",
+                    notes="" if acc is None else f"valid endpoints, acceptance {acc}")
 
 
-def arms_workload(n_queries: int = 65536, seed: int = 1) -> Workload:
-    """Four 7-R arms facing inward on a 1 m square; straight lines at 1/32 rad max-joint step."""
+def arms_workload(n_queries: int = 65536, seed: int = 1, decide=None) -> Workload:
+    """Four 7-R arms facing inward on a 1 m square; straight lines at 1/32 rad
+    max-joint step.  With ``decide`` (see valid_configs) the endpoints are valid
+    states (alone, then as a team)."""
     team = arm_team(seed)
     env = cube_env(seed)
     rng = _rng(seed, STREAM_WORK)
-    s = sample_configs(rng, team, n_queries, 7)
-    g = sample_configs(rng, team, n_queries, 7)
+    s, g, acc = _endpoints(rng, team, n_queries, 7, decide and (lambda rs, c: decide(rs, env, c)))
     paths = straight_line_paths(s, g, [7] * 4, 1.0 / 32.0, "linf", 7)
-    return Workload("arms-4x7R-60sph-20box-8cyl", team, env, paths, "mv")
+    return Workload("arms-4x7R-60sph-20box-8cyl", team, env, paths, "mv",
+                    notes="" if acc is None else f"valid endpoints, acceptance {acc}")
 
 
 def hetero_team(seed_arms: int = 1, n_arms: int = 4, n_rects: int = 4, rect_z: float = 0.5,

@@ -21,15 +21,45 @@ def test_autotune_keeps_answers():
     ctx = mrv.Context(0)
     try:
         team, env = ctx.load_team(w.team), ctx.load_env(w.env)
-        chunk, wg = ctx.autotune(team, env, 0, w.paths.subset(np.arange(128)), mrv.CHECK_ENV | mrv.EXHAUSTIVE)
-        assert 1 <= chunk <= 64 and 0 <= wg <= 2
-        assert ctx.get_tiling(team, 0, mrv.EXHAUSTIVE)[0] == chunk
+        tuned = ctx.autotune(team, env, 0, w.paths.subset(np.arange(128)), mrv.CHECK_ENV | mrv.EXHAUSTIVE)
+        chunk, wg, il, claim = tuned
+        assert 1 <= chunk <= 64 and 0 <= wg <= 8 and 0 <= il <= 3 and 0 <= claim <= 16
+        got = ctx.get_tiling(team, 0, mrv.EXHAUSTIVE)
+        assert got[0] == chunk and got[1] == wg and got[3] == (claim or 4)
         ref = oracle.mv(oracle.Team(w.team), oracle.Env(w.env), oracle.Paths(w.paths))
         assert np.array_equal(ctx.mv(team, env, w.paths, mrv.CHECK_ENV | mrv.EXHAUSTIVE), ref)
         # cached: same answer, no retiming needed
-        assert ctx.autotune(team, env, 0, w.paths.subset(np.arange(16)), mrv.CHECK_ENV | mrv.EXHAUSTIVE) == (chunk, wg)
-        c2, _ = ctx.autotune(team, -1, 1, w.paths.subset(np.arange(64)), 0)
+        assert ctx.autotune(team, env, 0, w.paths.subset(np.arange(16)), mrv.CHECK_ENV | mrv.EXHAUSTIVE) == tuned
+        # early-terminating MV also searches the interleave
+        ctx.autotune(team, env, 0, w.paths.subset(np.arange(128)), mrv.CHECK_ENV)
+        assert np.array_equal(ctx.mv(team, env, w.paths, mrv.CHECK_ENV), ref)
+        ctx.autotune(team, -1, 1, w.paths.subset(np.arange(64)), 0)
         assert np.array_equal(ctx.ffc(team, w.paths), oracle.ffc(oracle.Team(w.team), oracle.Paths(w.paths)))
+    finally:
+        ctx.close()
+
+
+def test_interleaves_and_claim_sizes_keep_answers():
+    say("interleaves and claim sizes")
+    w = W.arms_workload(384)
+    ctx = mrv.Context(0)
+    try:
+        team, env = ctx.load_team(w.team), ctx.load_env(w.env)
+        ot, oe, op = oracle.Team(w.team), oracle.Env(w.env), oracle.Paths(w.paths)
+        ref_env, ref_rr = oracle.mv(ot, oe, op), oracle.mv(ot, oe, op, check_env=False)
+        ref_ffc = oracle.ffc(ot, op)
+        for il in (1, 2, 3):
+            for claim in (1, 3, 16):
+                for flags in (0, mrv.EXHAUSTIVE):
+                    ctx.set_tiling(team, 0, 5, 0, flags, interleave=il, claim=claim)
+                    ctx.set_tiling(team, 1, 7, 0, flags, interleave=il, claim=claim)
+                    assert ctx.get_tiling(team, 0, flags)[2:] == (il, claim)
+                    assert np.array_equal(ctx.mv(team, env, w.paths, mrv.CHECK_ENV | flags), ref_env), (il, claim)
+                    assert np.array_equal(ctx.mv(team, env, w.paths, flags), ref_rr), (il, claim)
+                    assert np.array_equal(ctx.ffc(team, w.paths, flags), ref_ffc), (il, claim)
+        for bad in (dict(interleave=4), dict(claim=17), dict(claim=-1)):
+            with pytest.raises(mrv.MrvError):
+                ctx.set_tiling(team, 0, 0, 0, 0, **bad)
     finally:
         ctx.close()
 
