@@ -142,6 +142,10 @@ def ordering_study(log, n_motions=4096, step=1.0 / 128, max_rounds=64):
     Endpoint validity is decided by this library (MV of single-state motions).
     For every order: kernel time per call, effort (robot-states evaluated per
     robot-state covered) and the valid fraction; exhaustive MV for reference.
+    The orders: combined or hierarchical (all obstacle tiles before robot-robot
+    tiles, Alg. 1) with the golden-ratio bisection, rake or linear tile order;
+    robot-robot tests before obstacle tests within a tile; and the
+    pair-prioritised order (adjacent bases first within a tile, §III-A).
     Endpoints are composed from per-robot configurations that are valid alone
     (self and obstacle tests of a one-robot team), then kept if the whole team's
     state is valid."""
@@ -150,7 +154,11 @@ def ordering_study(log, n_motions=4096, step=1.0 / 128, max_rounds=64):
     from paper_2604_23960_amd import workloads as W
     orders = [("combined-bisect", 0), ("combined-rake", mrv.ORDER_RAKE), ("combined-linear", mrv.ORDER_LINEAR),
               ("hierarchical-bisect", mrv.HIERARCHICAL), ("hierarchical-rake", mrv.HIERARCHICAL | mrv.ORDER_RAKE),
-              ("hierarchical-linear", mrv.HIERARCHICAL | mrv.ORDER_LINEAR)]
+              ("hierarchical-linear", mrv.HIERARCHICAL | mrv.ORDER_LINEAR),
+              ("pairs-first-bisect", mrv.PAIRS_FIRST),
+              ("combined-bisect-pair-priority", mrv.PAIR_PRIORITY),
+              ("pairs-first-bisect-pair-priority", mrv.PAIRS_FIRST | mrv.PAIR_PRIORITY),
+              ("combined-linear-pair-priority", mrv.ORDER_LINEAR | mrv.PAIR_PRIORITY)]
     ctx = mrv.Context(0)
     rows = []
     for n_arms in (4, 8, 16):

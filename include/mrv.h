@@ -186,11 +186,16 @@ enum {
     MRV_ORDER_LINEAR = 16,   /* MV tile order: consecutive timesteps (FFC always uses this) */
     MRV_PAIRS_FIRST = 32,    /* early-terminating MV: within a tile, robot-robot (and self) tests
                                 before robot-obstacle tests */
-    MRV_OBSTACLES_FIRST = 64 /* early-terminating MV: robot-obstacle tests first.  With neither
+    MRV_OBSTACLES_FIRST = 64, /* early-terminating MV: robot-obstacle tests first.  With neither
                                 flag, pairs go first when the environment has a point cloud (its
                                 tests cost most) and obstacles first otherwise.  The order
                                 changes only how soon a collision ends a query, never the answer;
                                 exhaustive calls always test obstacles first. */
+    MRV_PAIR_PRIORITY = 128  /* early-terminating MV without a focus set: within a tile, first the
+                                self tests and the robot pairs likeliest to collide -- bases
+                                adjacent, within 1.25 times the team's smallest base distance
+                                (paper §III-A) -- then, only if none collides, the other pairs.
+                                Other calls ignore it; it never changes an answer. */
 };
 
 /* Near contact.  A test whose FP32 clearance lies within near_eps of zero is

@@ -321,6 +321,24 @@ int build_team(mrv_ctx ctx, const mrv_robot_desc* robots, int n, TeamHost& out)
         }
     }
 
+    // prioritised robot pairs (MRV_PAIR_PRIORITY): bases adjacent, i.e. within 1.25 times
+    // the smallest distance between two bases; none when every base coincides (the
+    // pair order is then the plain one)
+    std::vector<unsigned> r_pri(n, 0u);
+    {
+        double dmin = 1e300;
+        auto bd = [&](int i, int j) {
+            return std::sqrt(sq(base64[i * 12 + 3] - base64[j * 12 + 3]) + sq(base64[i * 12 + 7] - base64[j * 12 + 7]) +
+                             sq(base64[i * 12 + 11] - base64[j * 12 + 11]));
+        };
+        for (int i = 0; i < n; ++i)
+            for (int j = i + 1; j < n; ++j) dmin = std::min(dmin, bd(i, j));
+        if (dmin > 0.0 && dmin < 1e300)
+            for (int i = 0; i < n; ++i)
+                for (int j = i + 1; j < n; ++j)
+                    if (bd(i, j) <= 1.25 * dmin) r_pri[i] |= 1u << j;
+    }
+
     Packer pk;
     const size_t o_nj = pk.add(r_nj), o_jo = pk.add(r_joint_off), o_so = pk.add(r_sphere_off),
                  o_fo = pk.add(r_frame_off), o_b32 = pk.add(base32), o_b64 = pk.add(base64),
@@ -329,7 +347,8 @@ int build_team(mrv_ctx ctx, const mrv_robot_desc* robots, int n, TeamHost& out)
                  o_l64 = pk.add(s_local64), o_rt = pk.add(gtask), o_sg = pk.add(s_group),
                  o_gr = pk.add(g_range), o_rg = pk.add(r_group_off), o_ss2 = pk.add(slot_sphere),
                  o_sb = pk.add(sblocks), o_rm = pk.add(r_mag),
-                 o_jr = pk.add(j_robot), o_sf = pk.add(slot_frame), o_slc = pk.add(slot_local);
+                 o_jr = pk.add(j_robot), o_sf = pk.add(slot_frame), o_slc = pk.add(slot_local),
+                 o_pri = pk.add(r_pri);
     const TeamDev blank{};
     const size_t o_self = pk.add(&blank, sizeof(TeamDev));
     void* d = nullptr;
@@ -381,6 +400,7 @@ int build_team(mrv_ctx ctx, const mrv_robot_desc* robots, int n, TeamHost& out)
     t.gtask = (const int*)at(o_rt);
     t.slot_sphere = (const int*)at(o_ss2);
     t.slot_frame = (const int*)at(o_sf);
+    t.r_pri = (const unsigned*)at(o_pri);
     t.slot_local = (const float4*)at(o_slc);
     t.sblocks = (const int*)at(o_sb);
     out.dmem = d;
@@ -982,7 +1002,7 @@ void noalloc_call(mrv_ctx ctx, int team, int env, const mrv_paths* p, uint32_t f
 uint32_t check_flags(int kind, uint32_t flags)
 {
     const uint32_t known = MRV_CHECK_ENV | MRV_EXHAUSTIVE | MRV_HIERARCHICAL | MRV_ORDER_RAKE | MRV_ORDER_LINEAR |
-                           MRV_PAIRS_FIRST | MRV_OBSTACLES_FIRST;
+                           MRV_PAIRS_FIRST | MRV_OBSTACLES_FIRST | MRV_PAIR_PRIORITY;
     if (flags & ~known) throw Err{MRV_E_INVALID, "unknown flag bits"};
     if ((flags & MRV_ORDER_RAKE) && (flags & MRV_ORDER_LINEAR)) throw Err{MRV_E_INVALID, "two tile orders requested"};
     if ((flags & MRV_PAIRS_FIRST) && (flags & MRV_OBSTACLES_FIRST))

@@ -103,6 +103,7 @@ struct TeamDev {
                                 // first group of the higher robots, robot-robot tests, self tests, 0
     const int* slot_sphere;     // [GS] sphere of each slot, -1 for padding
     const int* slot_frame;      // [GS] frame slot of each slot's sphere, -1 for padding
+    const unsigned* r_pri;      // [n] bit j of entry i (j > i): the pair (i, j) is prioritised (adjacent bases)
     const float4* slot_local;   // [GS] local centre and radius of each slot's sphere, zeros for padding
     const int* sblocks;         // [n_sblocks][16] row group, column group, pairs, robot, 0, 0, 0, 0, then
                                 // four 64-bit lane masks, one per accumulator register

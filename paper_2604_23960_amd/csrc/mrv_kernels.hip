@@ -924,6 +924,7 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
     // exhaustive MV runs each group's self blocks over the tile's timesteps in an
     // inner loop (no early exit to honour between timesteps)
     constexpr bool kSelfInner = KIND == 3 || KIND == 5;
+    constexpr bool kPrio = KIND == 0;   // pair-prioritised order: early-terminating plain MV
     constexpr int kSI = 4;
 
     constexpr int WG = validate_wg(KIND);
@@ -1223,7 +1224,17 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
             // uncertainty revisit their pairs directly.
             CCall& cd = call_at();
             CTeam* tm = team_at(tpu);
-            const bool do_self = do_env && tm->n_sblocks > 0;
+            // pair-prioritised order (early-terminating MV, MRV_PAIR_PRIORITY): a first pass
+            // over the self blocks and the robot pairs whose bases are adjacent, the likeliest
+            // to collide (paper §III-A), then, after a barrier and only if no collision is
+            // known, a second pass over the other pairs
+            const bool prio = kPrio && do_rr && (flags & MRV_PAIR_PRIORITY) != 0;
+            for (int pass = 0; pass < (prio ? 2 : 1); ++pass) {
+            if (pass > 0) {
+                __syncthreads();                 // every wave reads the flag after the first pass
+                if (flag_read(&s_hit)) break;
+            }
+            const bool do_self = do_env && tm->n_sblocks > 0 && pass == 0;
             if ((do_rr || do_self) && !(kMV && !exhaustive && flag_read(&s_hit))) {
                 const float rho2 = __uint_as_float(s_rho2);
                 const float rm = tm->r_max;
@@ -1247,11 +1258,11 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
                     const int sb1 = do_self && a_in ? cload(tk + 3) : 0;
                     const bool higher_in = ra + 1 < 32 && (focus >> (ra + 1)) != 0u;   // a higher robot in focus
                     const int gs = do_rr && (a_in || higher_in) ? cload(tk + 4) : G;
-                    const unsigned long long rr_tests = do_rr && a_in ? (unsigned long long)cload(tk + 5) : 0ull;
+                    const unsigned long long rr_tests = do_rr && a_in && !prio ? (unsigned long long)cload(tk + 5) : 0ull;
                     const unsigned long long self_tests = do_self && a_in ? (unsigned long long)cload(tk + 6) : 0ull;
                     // spheres of group ga, for the test counts of a robot outside the focus set
-                    const int ga_n = a_in ? 0 : cload(reinterpret_cast<const int*>(tm->g_range) + 2 * ga + 1) -
-                                                cload(reinterpret_cast<const int*>(tm->g_range) + 2 * ga);
+                    const int ga_n = a_in && !prio ? 0 : cload(reinterpret_cast<const int*>(tm->g_range) + 2 * ga + 1) -
+                                                         cload(reinterpret_cast<const int*>(tm->g_range) + 2 * ga);
                     if (sb0 == sb1 && gs >= G) continue;
                     if constexpr (kSelfInner) {
                         // exhaustive MV: the self blocks of ga for up to kSI timesteps at a time,
@@ -1352,13 +1363,15 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
                             const floatx4 acc = { cw.x, cw.y, cw.z, cw.w };
                             // MV: all higher robots in one sweep, unless ga's robot is outside the
                             // focus set; then robot by robot, over those in it
-                            const bool sweep = kMV && a_in;
+                            const bool sweep = kMV && a_in && !prio;
                             const int rb_end = sweep ? ra + 2 : n;
+                            const unsigned pri = prio ? (unsigned)cload(reinterpret_cast<const int*>(tm->r_pri) + ra) : 0u;
                             for (int rb = ra + 1; rb < rb_end; ++rb) {
                                 if (!a_in && !((focus >> rb) & 1u)) continue;
+                                if (prio && (((pri >> rb) & 1u) != 0u) != (pass == 0)) continue;
                                 const int g0 = sweep ? gs : cload(tm->r_group_off + rb);
                                 const int g1 = sweep ? G : cload(tm->r_group_off + rb + 1);
-                                if (!a_in)
+                                if (!a_in || prio)
                                     c_rr += (unsigned long long)ga_n *
                                             (unsigned)(cload(tm->r_sphere_off + rb + 1) - cload(tm->r_sphere_off + rb));
                                 const unsigned key = kMV ? 0u : (unsigned)t * (unsigned)tm->P + pair_index(ra, rb, n);
@@ -1411,6 +1424,7 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
                         if (!kMV && found && !exhaustive) break;
                     }
                 }
+            }
             }
 
         };

@@ -21,7 +21,7 @@ MRV_E_INVALID, MRV_E_NOMEM, MRV_E_DEVICE, MRV_E_BUSY = -1, -2, -3, -4
 MRV_E_HANDLE, MRV_E_CANCELLED, MRV_E_TIMEOUT = -5, -6, -7
 CHECK_ENV, EXHAUSTIVE, HIERARCHICAL = 1, 2, 4
 ORDER_BISECT, ORDER_RAKE, ORDER_LINEAR = 0, 8, 16
-PAIRS_FIRST, OBSTACLES_FIRST = 32, 64
+PAIRS_FIRST, OBSTACLES_FIRST, PAIR_PRIORITY = 32, 64, 128
 MAX_T = 1 << 20
 NOALLOC_MAX_QUERIES = 1 << 18
 

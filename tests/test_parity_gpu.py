@@ -24,6 +24,9 @@ FLAG_SETS = [
     mrv.CHECK_ENV | mrv.ORDER_LINEAR | mrv.EXHAUSTIVE,
     0,
     mrv.EXHAUSTIVE,
+    mrv.CHECK_ENV | mrv.PAIR_PRIORITY,
+    mrv.CHECK_ENV | mrv.PAIRS_FIRST | mrv.PAIR_PRIORITY | mrv.ORDER_RAKE,
+    mrv.PAIR_PRIORITY,
 ]
 
 
@@ -333,3 +336,24 @@ def test_out_of_range_values_rejected(ctx, value):
     with pytest.raises(mrv.MrvError) as e:
         ctx.load_team(robots)
     assert e.value.status == mrv.MRV_E_INVALID
+
+
+@pytest.mark.parametrize("n_arms", [8, 16])
+def test_ring_teams_pair_priority(ctx, n_arms):
+    """Ring teams of 8 and 16 arms (adjacent bases about 1 m apart): the
+    pair-prioritised order, with and without obstacles, against the oracle."""
+    say("ring team", n_arms, "pair priority")
+    team_def = W.ring_team(n_arms)
+    rng = np.random.default_rng([n_arms, 9])
+    s = W.sample_configs(rng, team_def, 96, 7)
+    g = np.clip(s + rng.uniform(-0.4, 0.4, s.shape), -2.9, 2.9)
+    paths = W.straight_line_paths(s, g, [7] * n_arms, 1.0 / 32.0, "linf", 7)
+    env = W.cube_env(1)
+    team, eh = ctx.load_team(team_def), ctx.load_env(env)
+    ot, oe, op = oracle.Team(team_def), oracle.Env(env), oracle.Paths(paths)
+    ref_env, ref_rr = oracle.mv(ot, oe, op), oracle.mv(ot, oe, op, check_env=False)
+    for flags in (mrv.PAIR_PRIORITY, mrv.PAIR_PRIORITY | mrv.PAIRS_FIRST, mrv.PAIR_PRIORITY | mrv.ORDER_LINEAR):
+        assert np.array_equal(ctx.mv(team, eh, paths, mrv.CHECK_ENV | flags), ref_env), flags
+        assert np.array_equal(ctx.mv(team, -1, paths, flags), ref_rr), flags
+    ctx.unload(team)
+    ctx.unload(eh)
