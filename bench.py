@@ -353,17 +353,17 @@ def cloud_bench(log, n_queries=262_144, tune_sample=1024, exhaustive_queries=819
         out = {}
         w1, k1, s1 = run_device(ctx, th, eh, dmv, 0, mrv.CHECK_ENV, o_mv, 3, 1)
         out["mv_early_exit"] = dict(ms_per_call=w1 / 3 * 1e3, covered_states_per_s=s1["states_covered"] * 3 / w1,
-                                    roofline=roofline_of(team, env, s1, float(np.mean(k1)), "k_validate<0>"))
+                                    roofline=roofline_of(team, env, s1, float(np.mean(k1)), "k_validate<0, true> (early-terminating MV, point cloud)"))
         w2, k2, s2 = run_device(ctx, th, -1, dffc, 1, 0, o_ffc, 3, 1)
         out["ffc"] = dict(ms_per_call=w2 / 3 * 1e3, covered_states_per_s=s2["states_covered"] * 3 / w2,
                           evaluated_states_per_s=s2["states_evaluated"] * 3 / w2,
-                          roofline=roofline_of(team, None, s2, float(np.mean(k2)), "k_validate<1>"))
+                          roofline=roofline_of(team, None, s2, float(np.mean(k2)), "k_validate<1, false> (early-terminating FFC)"))
         w3, k3, s3 = run_device(ctx, th, eh, dsub, 0, mrv.CHECK_ENV | mrv.EXHAUSTIVE, o_sub, 2, 1)
         out["mv_exhaustive_slice"] = dict(queries=sub.n_queries, ms_per_call=w3 / 2 * 1e3,
                                           kernel_ms=float(np.mean(k3)),
                                           states_per_s=s3["states_evaluated"] * 2 / w3,
                                           point_tests=s3["point_tests"], rr_tests=s3["rr_tests"],
-                                          roofline=roofline_of(team, env, s3, float(np.mean(k3)), "k_validate<3>"))
+                                          roofline=roofline_of(team, env, s3, float(np.mean(k3)), "k_validate<3, true> (exhaustive MV, point cloud)"))
         out["tiling"] = dict(mv_early=ctx.get_tiling(th, 0), mv_exhaustive=ctx.get_tiling(th, 0, mrv.EXHAUSTIVE),
                              ffc=ctx.get_tiling(th, 1))
         log(f"cloud {tag}: {out['mv_exhaustive_slice']['states_per_s']:.3g} states/s exhaustive")
@@ -573,7 +573,7 @@ def main():
     value = states * args.steps / wall
     ms_per_step = wall / args.steps * 1e3
     kernel_ms = float(np.mean(kms))
-    roofline = roofline_of(w.team, w.env, st, kernel_ms, "k_validate<3> (exhaustive MV)")
+    roofline = roofline_of(w.team, w.env, st, kernel_ms, "k_validate<3, false> (exhaustive MV)")
     roofline["traffic"] = profiled_traffic()
     extra = dict(states_covered=st["states_covered"], rr_tests=st["rr_tests"], env_tests=st["env_tests"],
                  self_tests=st["self_tests"], near_rechecks=st["near_rechecks"],
@@ -586,7 +586,7 @@ def main():
                                       evaluated_states_per_s=st2["states_evaluated"] * 5 / wall2,
                                       ms_per_call=wall2 / 5 * 1e3, effort=st2["states_evaluated"] / st2["states_covered"],
                                       roofline=roofline_of(w.team, w.env, st2, float(np.mean(kms2)),
-                                                           "k_validate<0> (early-terminating MV)"))
+                                                           "k_validate<0, false> (early-terminating MV)"))
         log("timing prioritised MV (focus on arm 0)")
         wall4, kms4, st4 = run_device(ctx, team, env, dp, 0, mrv.CHECK_ENV | mrv.EXHAUSTIVE, out, 3, 1, focus=1)
         wall5, _, st5 = run_device(ctx, team, env, dp, 0, mrv.CHECK_ENV, out, 5, 1, focus=1)
@@ -607,12 +607,12 @@ def main():
                                    evaluated_states_per_s=st3["states_evaluated"] * 5 / wall3,
                                    null_fraction=float((cf[:, 0] < 0).float().mean().item()),
                                    roofline=roofline_of(wf.team, None, st3, float(np.mean(kms3)),
-                                                        "k_validate<1> (early-terminating FFC)"))
+                                                        "k_validate<1, false> (early-terminating FFC)"))
         wall4, kms4, st4 = run_device(ctx, tf, -1, dpf, 1, mrv.EXHAUSTIVE, cf, 3, 1)
         extra["ffc_hetero_exhaustive"] = dict(ms_per_call=wall4 / 3 * 1e3,
                                               states_per_s=st4["states_evaluated"] * 3 / wall4,
                                               roofline=roofline_of(wf.team, None, st4, float(np.mean(kms4)),
-                                                                   "k_validate<4> (exhaustive FFC)"))
+                                                                   "k_validate<4, false> (exhaustive FFC)"))
         log("serving loop vs plain launches")
         extra["serving"] = serving_bench(log)
         log("16-robot point-cloud workload")

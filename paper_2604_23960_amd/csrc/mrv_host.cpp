@@ -804,7 +804,8 @@ void launch_plan(mrv_ctx ctx, const ScratchView& v, const CallPlan& pl, void* ou
     cd.valid_out = kind == 0 ? (unsigned char*)out_dev : nullptr;
     cd.conflict_out = kind == 1 ? (int*)out_dev : nullptr;
 
-    const int per_cu = std::max(1, validate_blocks_per_cu(validate_variant(cd), pl.lds));
+    cd.points = pl.points && kind == 0 && (pl.flags & MRV_CHECK_ENV) ? 1 : 0;
+    const int per_cu = std::max(1, validate_blocks_per_cu(validate_variant(cd), cd.points != 0, pl.lds));
     const int want = pl.wg_per_cu > 0 ? std::min(pl.wg_per_cu, per_cu) : per_cu;
     const int grid = std::max(1, ctx->n_cu * want);
 
@@ -852,6 +853,7 @@ CallPlan single_plan(const TeamHost& tm, const EnvHost* env, int kind, uint32_t 
     pl.lds = lds_bytes_for(tm, tm.dev.chunk[kind][m]);
     pl.wg_per_cu = tm.tiling[kind][m].wg_per_cu;
     pl.claim = tm.tiling[kind][m].claim;
+    pl.points = env && env->dev.n_pts > 0;
     return pl;
 }
 
@@ -1524,7 +1526,8 @@ mrv_status mrv_autotune(mrv_ctx ctx, int32_t team, int32_t env, int32_t kind, co
                 if (c != choice.chunk) consider(t);
             }
             const int variant = kind == 1 ? (m ? 4 : 1) : (m ? 3 : 0);
-            const int occ = validate_blocks_per_cu(variant, lds_bytes_for(trial, choice.chunk));
+            const int occ = validate_blocks_per_cu(variant, ev && ev->dev.n_pts > 0 && kind == 0,
+                                                   lds_bytes_for(trial, choice.chunk));
             for (int wg : {1, 2, 3, 4, 6, 8, 0}) {
                 mrv_tiling t = choice;
                 t.wg_per_cu = wg;
@@ -1675,6 +1678,7 @@ mrv_status mrv_submit(mrv_ctx ctx, const mrv_request* req, uint64_t* ticket)
             check_paths_host(tm, &req->paths);
             refs.team = tm.d_dev;
             refs.env = ev ? ev->d_dev : nullptr;
+            refs.points = ev && ev->dev.n_pts > 0;
             refs.n_robots = tm.dev.n_robots;
             const int m = mode_of(req->flags);
             refs.chunk = tm.dev.chunk[req->kind][m];

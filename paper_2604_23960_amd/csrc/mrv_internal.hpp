@@ -154,6 +154,7 @@ struct CallDev {
     float eps32;                // near band in metres before per-query scaling
     int chunk_floor;            // smallest tile length the call's scratch was sized for
     int claim;                  // tiles taken per claim on the tile counter (>= 1)
+    int points;                 // 1: some query's environment holds a point cloud (MV with obstacles)
     long long max_nt;           // most tiles a query may have (tile bins - 2)
     long long n_wp;
     const long long* wp_begin;
@@ -205,7 +206,8 @@ inline int validate_variant(const CallDev& cd)
     if (has_focus(cd)) return exh ? 5 : 2;
     return exh ? 3 : 0;
 }
-int validate_blocks_per_cu(int variant, size_t lds_bytes);
+// points: the build for environments with point clouds (CallDev::points).
+int validate_blocks_per_cu(int variant, bool points, size_t lds_bytes);
 // Device address of the fixed scratch on `device`.  noalloc_scratch_setup looks it
 // up once per device (that device current) and keeps it; noalloc_scratch returns
 // the kept address, null before set-up.

@@ -754,7 +754,7 @@ __device__ __forceinline__ float4 place32(const float4* Fp, float4 L)
 // tests below the known outcome are queued for FP64 re-evaluation.  The kernel
 // passes one task at a time: with boxes and cylinders selected per task, larger
 // J only adds register pressure.
-template <int J, class CD>
+template <int J, bool PTS, class CD>
 __device__ __forceinline__ void env_tasks(const CD& cd, CTeam* tm, CEnv* env, const float* sp,
                                           const int* task, int nch, float ro_max, float eps, bool exhaustive, int q,
                                           unsigned focus, bool fall, const int* s_t, int* s_hit,
@@ -847,7 +847,7 @@ __device__ __forceinline__ void env_tasks(const CD& cd, CTeam* tm, CEnv* env, co
         // the sphere index and timestep of a queued test, read only when one is queued
         auto sa_of = [&]() { return tm->slot_sphere[a[j]]; };
         auto t_of = [&]() { return s_t[c[j]]; };
-        if (env->n_pts > 0 && act[j]) {
+        if (PTS && env->n_pts > 0 && act[j]) {
             const float Rp = rad[j] + env->pt_radius;
             const float xs[3] = { x[j], y[j], z[j] };
             int lo3[3], hi3[3];
@@ -862,15 +862,32 @@ __device__ __forceinline__ void env_tasks(const CD& cd, CTeam* tm, CEnv* env, co
             const float plo = fmaxf(Rp - eps, 0.f), phi = Rp + eps;
             const float plo2 = plo * plo, phi2 = phi * phi;
             unsigned npt = 0;           // points tested by this lane
+            // Cell rows (fixed y and z cells, consecutive x cells) within reach of the
+            // centre only, each cut to the sphere's chord at the row's nearest y and z:
+            // a point within reach lies at least as close in y and z as its row does.
+            // Rounding of the cell bounds (~1e-7 m) is far inside the band eps, so no
+            // point closer than r + r_p + eps - 1e-7 is skipped, and every farther one
+            // is clear in FP64 as well.
+            const float reach2 = reach * reach, cell = env->grid_cell;
             if (lo3[0] <= hi3[0])
-                for (int cz = lo3[2]; cz <= hi3[2]; ++cz)
+                for (int cz = lo3[2]; cz <= hi3[2]; ++cz) {
+                    const float z0 = fmaf((float)cz, cell, env->grid_lo[2]);
+                    const float dz = fmaxf(fmaxf(z0 - xs[2], xs[2] - (z0 + cell)), 0.f);
                     for (int cy = lo3[1]; cy <= hi3[1]; ++cy) {
+                        const float y0 = fmaf((float)cy, cell, env->grid_lo[1]);
+                        const float dy = fmaxf(fmaxf(y0 - xs[1], xs[1] - (y0 + cell)), 0.f);
+                        const float rem = reach2 - fmaf(dy, dy, dz * dz);
+                        if (rem < 0.f) continue;
+                        const float hw = __builtin_amdgcn_sqrtf(rem);
+                        const int l0 = max((int)floorf((xs[0] - hw - env->grid_lo[0]) * env->grid_inv), lo3[0]);
+                        const int h0 = min((int)floorf((xs[0] + hw - env->grid_lo[0]) * env->grid_inv), hi3[0]);
+                        if (l0 > h0) continue;
                         const int crow = (cz * env->grid_dim[1] + cy) * env->grid_dim[0];
-                        const int pb = env->cell_start[crow + lo3[0]];
-                        const int pe = env->cell_start[crow + hi3[0] + 1];
+                        const int pb = env->cell_start[crow + l0];
+                        const int pe = env->cell_start[crow + h0 + 1];
                         npt += (unsigned)(pe - pb);
-                        for (int p = pb; p < pe; ++p) {
-                            const float4 Pt = env->pts32[p];
+                        // four independent point loads in flight per step
+                        auto test_pt = [&](const float4 Pt, int p) {
                             const float dx = x[j] - Pt.x, dy = y[j] - Pt.y, dz = z[j] - Pt.z;
                             const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
                             if (d2 <= phi2) {
@@ -878,8 +895,19 @@ __device__ __forceinline__ void env_tasks(const CD& cd, CTeam* tm, CEnv* env, co
                                 else if (!hit && !flag_read(s_hit))
                                     push_recheck(cd, q, t_of(), RK_ENV_PT, sa_of(), p, 0u);
                             }
+                        };
+                        int p = pb;
+                        for (; p + 4 <= pe; p += 4) {
+                            const float4 P0 = env->pts32[p], P1 = env->pts32[p + 1], P2 = env->pts32[p + 2],
+                                         P3 = env->pts32[p + 3];
+                            test_pt(P0, p);
+                            test_pt(P1, p + 1);
+                            test_pt(P2, p + 2);
+                            test_pt(P3, p + 3);
                         }
+                        for (; p < pe; ++p) test_pt(env->pts32[p], p);
                     }
+                }
             if (npt) atomicAdd(s_npt, (unsigned long long)npt);
         }
         if (unsure && !(hit && !exhaustive)) {
@@ -911,7 +939,10 @@ __device__ __forceinline__ void env_tasks(const CD& cd, CTeam* tm, CEnv* env, co
     if (__ballot(any_hit) && lane == 0) *s_hit = 1;
 }
 
-template <int KIND>
+// PTS: the build for calls whose environments hold point clouds (the grid walk of
+// the obstacle phase); without it the walk compiles out, which keeps its registers
+// out of every other call.
+template <int KIND, bool PTS>
 __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kExhWGsPerCU : kWGsPerCU)) void k_validate(CallDev cd_arg)
 {
     (void)cd_arg;   // read in place through call_at()
@@ -1205,7 +1236,7 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
                 int task = wave;
                 for (; task < ntask && !(!exhaustive && flag_read(&s_hit)); task += kWaves) {
                     const int tk[1] = { task };
-                    env_tasks<1>(cd, tm, env, sp, tk, nch, ro_max, eps, exhaustive, q, focus, fall, s_t, &s_hit, c_env,
+                    env_tasks<1, PTS>(cd, tm, env, sp, tk, nch, ro_max, eps, exhaustive, q, focus, fall, s_t, &s_hit, c_env,
                                  &s_npt, lane, off);
                 }
             }
@@ -1529,40 +1560,40 @@ hipError_t launch_prepare(const CallDev& cd, hipStream_t stream)
     return hipGetLastError();
 }
 
+namespace {
+template <int KIND, bool PTS>
+hipError_t launch_one(const CallDev& cd, int grid, hipStream_t stream)
+{
+    // allow dynamic LDS beyond 64 KiB (once per instantiation and process)
+    static const hipError_t lds_opt = hipFuncSetAttribute((const void*)k_validate<KIND, PTS>,
+                                                          hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget - 1024);
+    if (lds_opt != hipSuccess && cd.lds_bytes > 64 * 1024) return lds_opt;
+    hipLaunchKernelGGL((k_validate<KIND, PTS>), dim3(grid), dim3(validate_wg(KIND)), (size_t)cd.lds_bytes, stream, cd);
+    return hipGetLastError();
+}
+
+template <int KIND, bool PTS>
+int occupancy_one(size_t lds_bytes)
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_validate<KIND, PTS>, validate_wg(KIND), lds_bytes) != hipSuccess)
+        return 0;
+    return nb;
+}
+}  // namespace
+
 hipError_t launch_validate(const CallDev& cd, int grid, hipStream_t stream)
 {
     if (cd.n_queries == 0) return hipSuccess;
-    // allow dynamic LDS beyond 64 KiB (once per process)
-    static const hipError_t lds_opt = [] {
-        hipError_t e = hipFuncSetAttribute((const void*)k_validate<0>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           kLdsBudget - 1024);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void*)k_validate<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    kLdsBudget - 1024);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void*)k_validate<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    kLdsBudget - 1024);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void*)k_validate<3>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    kLdsBudget - 1024);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void*)k_validate<4>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    kLdsBudget - 1024);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void*)k_validate<5>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    kLdsBudget - 1024);
-        return e;
-    }();
-    if (lds_opt != hipSuccess && cd.lds_bytes > 64 * 1024) return lds_opt;
+    const bool pts = cd.points != 0;
     switch (validate_variant(cd)) {
-    case 1: hipLaunchKernelGGL(k_validate<1>, dim3(grid), dim3(validate_wg(1)), (size_t)cd.lds_bytes, stream, cd); break;
-    case 2: hipLaunchKernelGGL(k_validate<2>, dim3(grid), dim3(validate_wg(2)), (size_t)cd.lds_bytes, stream, cd); break;
-    case 3: hipLaunchKernelGGL(k_validate<3>, dim3(grid), dim3(validate_wg(3)), (size_t)cd.lds_bytes, stream, cd); break;
-    case 4: hipLaunchKernelGGL(k_validate<4>, dim3(grid), dim3(validate_wg(4)), (size_t)cd.lds_bytes, stream, cd); break;
-    case 5: hipLaunchKernelGGL(k_validate<5>, dim3(grid), dim3(validate_wg(5)), (size_t)cd.lds_bytes, stream, cd); break;
-    default: hipLaunchKernelGGL(k_validate<0>, dim3(grid), dim3(validate_wg(0)), (size_t)cd.lds_bytes, stream, cd); break;
+    case 1: return launch_one<1, false>(cd, grid, stream);
+    case 2: return pts ? launch_one<2, true>(cd, grid, stream) : launch_one<2, false>(cd, grid, stream);
+    case 3: return pts ? launch_one<3, true>(cd, grid, stream) : launch_one<3, false>(cd, grid, stream);
+    case 4: return launch_one<4, false>(cd, grid, stream);
+    case 5: return pts ? launch_one<5, true>(cd, grid, stream) : launch_one<5, false>(cd, grid, stream);
+    default: return pts ? launch_one<0, true>(cd, grid, stream) : launch_one<0, false>(cd, grid, stream);
     }
-    return hipGetLastError();
 }
 
 hipError_t launch_finalize(const CallDev& cd, hipStream_t stream)
@@ -1624,17 +1655,18 @@ void* noalloc_scratch(int device)
     return g_scratch_ptr[device];
 }
 
-int validate_blocks_per_cu(int kind, size_t lds_bytes)
+int validate_blocks_per_cu(int kind, bool points, size_t lds_bytes)
 {
     int nb = 0;
-    hipError_t e = kind == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_validate<1>, validate_wg(1), lds_bytes)
-                 : kind == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_validate<2>, validate_wg(2), lds_bytes)
-                 : kind == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_validate<3>, validate_wg(3), lds_bytes)
-                 : kind == 4 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_validate<4>, validate_wg(4), lds_bytes)
-                 : kind == 5 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_validate<5>, validate_wg(5), lds_bytes)
-                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_validate<0>, validate_wg(0), lds_bytes);
-    if (e != hipSuccess || nb < 1) nb = 1;
-    return nb;
+    switch (kind) {
+    case 1: nb = occupancy_one<1, false>(lds_bytes); break;
+    case 2: nb = points ? occupancy_one<2, true>(lds_bytes) : occupancy_one<2, false>(lds_bytes); break;
+    case 3: nb = points ? occupancy_one<3, true>(lds_bytes) : occupancy_one<3, false>(lds_bytes); break;
+    case 4: nb = occupancy_one<4, false>(lds_bytes); break;
+    case 5: nb = points ? occupancy_one<5, true>(lds_bytes) : occupancy_one<5, false>(lds_bytes); break;
+    default: nb = points ? occupancy_one<0, true>(lds_bytes) : occupancy_one<0, false>(lds_bytes); break;
+    }
+    return nb < 1 ? 1 : nb;
 }
 
 }  // namespace mrv

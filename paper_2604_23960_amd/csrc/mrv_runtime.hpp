@@ -160,12 +160,14 @@ struct CallPlan {
     size_t lds;                        // dynamic LDS: max over the queries' teams
     int wg_per_cu;                     // 0 = occupancy limit
     int claim;                         // tiles per claim, 0 = automatic
+    bool points;                       // some query's environment holds a point cloud
 };
 
 // Device-side descriptors a served request needs, resolved at submit time.
 struct ServeRefs {
     const TeamDev* team;
     const EnvDev* env;
+    bool points;                       // the environment holds a point cloud
     int n_robots;
     int chunk;
     size_t lds;

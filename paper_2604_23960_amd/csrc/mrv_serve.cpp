@@ -382,6 +382,7 @@ struct ServeLoop::Impl {
         long long n_wp = 0, max_T = 1;
         int nq = 0, min_chunk = 1 << 30;
         size_t lds = 0;
+        bool points = false;
         s.q_off.clear();
         for (auto& r : s.batch) {
             s.q_off.push_back(nq);
@@ -390,6 +391,7 @@ struct ServeLoop::Impl {
             max_T = std::max(max_T, r->max_T);
             min_chunk = std::min(min_chunk, r->refs.chunk);
             lds = std::max(lds, r->refs.lds);
+            points = points || r->refs.points;
         }
         // one pinned block: wp_begin | wp_t | wp_q | q_team | q_env | q_pathoff | q_focus
         BatchShape sh;
@@ -449,6 +451,7 @@ struct ServeLoop::Impl {
         pl.lds = lds;
         pl.wg_per_cu = 0;
         pl.claim = 0;
+        pl.points = points;
         s.plan = pl;
         s.nout = nout;
         s.attempts = 0;
