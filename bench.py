@@ -428,6 +428,41 @@ def simd_baseline(w, value, n_sample=16384):
                 gpu_over_simd_exhaustive=value / rate)
 
 
+def calibration_copy(mib, log):
+    """A plain device copy of mib MiB (read and written once): the reference the HBM
+    counters of a profile are scaled by."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"copy calibration: {mib} MiB read + written")
+
+
+def cloud_exhaustive(n_motions, steps, warmup, log):
+    """Exhaustive MV with obstacles of the 16-robot point-cloud team over its first
+    n_motions MV motions (the profiled configuration of the point-cloud kernel)."""
+    import torch
+    from paper_2604_23960_amd import mrv
+    from paper_2604_23960_amd import workloads as W
+    team, env, mvp, _ = W.big_hetero_workload(max(2 * n_motions, 1024))
+    sub = mvp.subset(np.arange(n_motions))
+    ctx = mrv.Context(0)
+    th, eh = ctx.load_team(team), ctx.load_env(env)
+    dp = mrv.DevicePaths(sub)
+    out = torch.zeros(n_motions, dtype=torch.uint8, device="cuda")
+    log(f"timing exhaustive MV of the cloud team over {n_motions} motions")
+    wall, kms, st = run_device(ctx, th, eh, dp, 0, mrv.CHECK_ENV | mrv.EXHAUSTIVE, out, steps, warmup)
+    kms_mean = float(np.mean(kms))
+    res = dict(workload="cloud-16r-576sph-200kpts MV exhaustive", motions=n_motions, steps=steps,
+               ms_per_step=wall / steps * 1e3, states_per_s=st["states_evaluated"] * steps / wall,
+               point_tests=st["point_tests"], rr_tests=st["rr_tests"], self_tests=st["self_tests"],
+               roofline=roofline_of(team, env, st, kms_mean, "k_validate<3, true> (exhaustive MV, point cloud)"))
+    ctx.close()
+    return res
+
+
 def cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -528,6 +563,8 @@ def main():
                     help="only run the early-termination ordering study with this many motions per team")
     ap.add_argument("--ordering-out", default="",
                     help="also write the ordering study's JSON record to this file")
+    ap.add_argument("--cloud-exhaustive", type=int, default=0, metavar="MOTIONS",
+                    help="only time exhaustive MV of the 16-robot point-cloud team over this many motions")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
@@ -550,14 +587,14 @@ def main():
         print(json.dumps(rec), flush=True)
         return
 
+    if args.cloud_exhaustive > 0:
+        if args.copy_calib_mib > 0:
+            calibration_copy(args.copy_calib_mib, log)
+        print(json.dumps(cloud_exhaustive(args.cloud_exhaustive, args.steps, args.warmup, log)), flush=True)
+        return
+
     if args.copy_calib_mib > 0:
-        n = args.copy_calib_mib * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"copy calibration: {args.copy_calib_mib} MiB read + written")
-        del src, dst
+        calibration_copy(args.copy_calib_mib, log)
     ctx = mrv.Context(0)
     decide, release = library_decider(ctx)
     log("generating the four-arm workload (endpoints valid, decided by this library)")
