@@ -758,7 +758,7 @@ template <int J, bool PTS, class CD>
 __device__ __forceinline__ void env_tasks(const CD& cd, CTeam* tm, CEnv* env, const float* sp,
                                           const int* task, int nch, float ro_max, float eps, bool exhaustive, int q,
                                           unsigned focus, bool fall, const int* s_t, int* s_hit,
-                                          unsigned long long& c_env, unsigned long long* s_npt, int lane, float3 off)
+                                          unsigned& c_env, unsigned long long* s_npt, int lane, float3 off)
 {
     const int GS = tm->GS, GSp = tm->GSp, TS = tm->TS;
     int c[J], a[J];
@@ -834,7 +834,7 @@ __device__ __forceinline__ void env_tasks(const CD& cd, CTeam* tm, CEnv* env, co
     bool any_hit = false;
 #pragma unroll
     for (int j = 0; j < J; ++j) {
-        if (act[j]) c_env += (unsigned long long)n_tested[j];
+        if (act[j]) c_env += n_tested[j];
         const float rlo = fmaxf(rad[j] - eps, 0.f), rhi = rad[j] + eps;
         const float Rb = rad[j] + ro_max;
         // common case first: no lane within the near band of a box, cylinder or sphere
@@ -982,14 +982,18 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
     const bool check_env = kMV && (flags & MRV_CHECK_ENV) != 0;
     const bool hier = check_env && (flags & MRV_HIERARCHICAL) != 0;
 
-    unsigned long long* w64 = reinterpret_cast<unsigned long long*>(cd.ctrl + 4);
-    const long long total = (long long)__hip_atomic_load(&w64[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const long long gtotal = hier ? 2 * total : total;
-    const long long* off = reinterpret_cast<const long long*>(cd.off);
-    const int M = cd.ctrl[0];
+    // the tile space, read once into LDS (thread 0's claims read it from there)
+    __shared__ long long s_total, s_gtotal;
+    __shared__ int s_M;
 
-    unsigned long long c_rr = 0, c_env = 0, c_self = 0;                 // wave-uniform counters
+    unsigned long long c_rr = 0, c_self = 0;    // wave-uniform counters
+    unsigned c_env = 0;                         // per lane: obstacle tests of this workgroup's tiles
     if (tid == 0) {
+        const long long total = (long long)__hip_atomic_load(reinterpret_cast<unsigned long long*>(cd.ctrl + 4),
+                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_total = total;
+        s_gtotal = hier ? 2 * total : total;
+        s_M = cd.ctrl[0];
         s_kcur = 0;
         s_gnext = 0;
         s_gend = 0;
@@ -1012,6 +1016,10 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
         if (exhaustive) __builtin_amdgcn_s_setprio(2);
         if (tid == 0) {
             CCall& cd = call_at();
+            unsigned long long* w64 = reinterpret_cast<unsigned long long*>(cd.ctrl + 4);
+            const long long* off = reinterpret_cast<const long long*>(cd.off);
+            const long long total = s_total, gtotal = s_gtotal;
+            const int M = s_M;
             // the previous tile's outcome (all its waves passed the barrier that
             // ended it) goes to its query's word before the next claim
             if (s_q >= 0 && s_nv > 0) {
@@ -1477,7 +1485,7 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kEx
         if (c_rr) atomicAdd(&cd.stats[ST_RR_TESTS], c_rr);
         if (c_self) atomicAdd(&cd.stats[ST_SELF_TESTS], c_self);
     }
-    if (c_env) atomicAdd(&cd.stats[ST_ENV_TESTS], c_env);
+    if (c_env) atomicAdd(&cd.stats[ST_ENV_TESTS], (unsigned long long)c_env);
     if (tid == 0) {
         atomicAdd(&cd.stats[ST_TILES_RUN], s_nrun);
         atomicAdd(&cd.stats[ST_TILES_SKIPPED], s_nskip);
