@@ -57,12 +57,13 @@ def profiled_traffic():
 
 def executed_flop(team, env, stats):
     """FLOP of one MV/FFC launch from its executed-test counters, split by the pipe
-    that runs it.  Matrix cores: 10 per robot-robot and self sphere test (the Gram
-    form's 16 x 16 x 4 products plus the vector unit's column minimum and w_b).
-    Vector unit: FK and sphere placement of every evaluated robot-state, 10 per
-    sphere-obstacle and sphere-point test, 26 per box or cylinder test actually run
-    (the kernel skips those whose world box misses a row of 16 spheres by more than
-    the near band; that skip is comparisons only and counts no FLOP)."""
+    that runs it.  Matrix cores: 10 per robot-robot, self and sphere-point test (the
+    Gram form's 16 x 16 x 4 products plus the vector unit's minimum; sphere-point
+    tests are the pairs of a group's spheres and the points of the cell rows its box
+    meets).  Vector unit: FK and sphere placement of every evaluated robot-state, 10
+    per sphere-obstacle test, 26 per box or cylinder test actually run (the kernel
+    skips those whose world box misses a row of 16 spheres by more than the near
+    band; that skip is comparisons only and counts no FLOP)."""
     from paper_2604_23960_amd import workloads as W
     assert FLOP_SPHERE_BOX == FLOP_SPHERE_CYL        # one counter covers both
     ts = stats["states_evaluated"] / len(team)
@@ -72,9 +73,8 @@ def executed_flop(team, env, stats):
         fk += r.n_spheres * FLOP_SPHERE_PLACE
     n_sph = len(env.spheres) if env is not None else 0
     sph_tests = ts * sum(r.n_spheres for r in team) * n_sph if stats["env_tests"] else 0.0
-    mfma = (stats["rr_tests"] + stats["self_tests"]) * FLOP_SPHERE_SPHERE
-    valu = (ts * fk + (sph_tests + stats.get("point_tests", 0)) * FLOP_SPHERE_SPHERE +
-            (stats["env_tests"] - sph_tests) * FLOP_SPHERE_BOX)
+    mfma = (stats["rr_tests"] + stats["self_tests"] + stats.get("point_tests", 0)) * FLOP_SPHERE_SPHERE
+    valu = ts * fk + sph_tests * FLOP_SPHERE_SPHERE + (stats["env_tests"] - sph_tests) * FLOP_SPHERE_BOX
     return dict(total=mfma + valu, mfma=mfma, valu=valu)
 
 

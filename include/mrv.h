@@ -344,7 +344,8 @@ typedef struct {
                                                    the bounding-box cull are not counted), self */
     uint64_t near_rechecks;      /* tests re-evaluated in FP64 */
     double kernel_ms;            /* validation kernel time of the last call (device events) */
-    uint64_t point_tests;        /* sphere-point tests executed (point clouds, grid cells walked) */
+    uint64_t point_tests;        /* sphere-point pairs tested (point clouds: each 16-sphere group against the
+                                    points of the grid cell rows its bounding box meets) */
 } mrv_stats;
 /* Counters of the last MV/FFC call on this context (synchronises the stream). */
 mrv_status mrv_last_stats(mrv_ctx ctx, mrv_stats* out);

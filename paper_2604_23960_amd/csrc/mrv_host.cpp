@@ -575,15 +575,24 @@ void build_env(mrv_ctx ctx, const mrv_env_desc* e, EnvHost& out)
         cell_start.assign(total + 1, 0);
         for (long long c = 0; c < total; ++c) cell_start[c + 1] = cell_start[c] + count[c + 1];
         std::vector<int> cursor(cell_start.begin(), cell_start.end() - 1);
-        pts32.assign((size_t)e->n_points * 4, 0.f);
+        // FP32 points carry |p|^2 (of the FP32 coordinates, rounded once) for the
+        // sphere-point blocks, and kPtsPad copies of the last point past the end, which
+        // the blocks may read
+        pts32.assign(((size_t)e->n_points + kPtsPad) * 4, 0.f);
         pts64.assign((size_t)e->n_points * 3, 0.0);
         for (long long i = 0; i < e->n_points; ++i) {
             int p = cursor[cell_of[i]]++;
+            double n2 = 0.0;
             for (int d = 0; d < 3; ++d) {
-                pts32[(size_t)p * 4 + d] = (float)(e->points[i * 3 + d] - o[d]);
+                const float v = (float)(e->points[i * 3 + d] - o[d]);
+                pts32[(size_t)p * 4 + d] = v;
+                n2 += (double)v * (double)v;
                 pts64[(size_t)p * 3 + d] = e->points[i * 3 + d];
             }
+            pts32[(size_t)p * 4 + 3] = (float)n2;
         }
+        for (size_t k = 0; k < (size_t)kPtsPad * 4; ++k)
+            pts32[(size_t)e->n_points * 4 + k] = pts32[((size_t)e->n_points - 1) * 4 + k % 4];
     }
     std::vector<double> sph64(e->spheres, e->spheres + (size_t)e->n_spheres * 4);
     std::vector<double> box64(e->boxes, e->boxes + (size_t)e->n_boxes * 15);

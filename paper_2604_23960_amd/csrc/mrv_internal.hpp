@@ -25,6 +25,7 @@ constexpr int kMaxChunk = 64;       // timesteps per tile
 constexpr int kLdsBudget = 160 * 1024;   // LDS one workgroup may use on gfx950
 constexpr int kWGsPerCU = 5;        // validation workgroups per CU the register budget allows
 constexpr int kExhWGsPerCU = 7;     // the same for the exhaustive MV kernel (72 VGPRs)
+constexpr int kExhPtsWGsPerCU = 6;  // and for its build for point clouds (80 VGPRs)
 // The near band of a query widens in proportion to the largest coordinate magnitude
 // its FP32 arithmetic sees beyond this scale (metres); see k_query_info.
 constexpr double kEpsRefScale = 4.0;
@@ -109,6 +110,10 @@ struct TeamDev {
                                 // four 64-bit lane masks, one per accumulator register
 };
 
+// Points stored past the end of a cloud (copies of its last point), read by the
+// sphere-point blocks, which take 32 consecutive points at a time.
+constexpr int kPtsPad = 64;
+
 // Resident environment in the world frame.
 struct EnvDev {
     int n_sph, n_box, n_cyl;
@@ -124,7 +129,7 @@ struct EnvDev {
     double origin64[3];         // the environment origin (centre of its obstacles' bounding box, an FP32 value)
     float mag;                  // bound on |FP32 coordinate| of any obstacle part relative to the origin
     // uniform grid over the point cloud (CSR by cell)
-    const float4* pts32;        // [n_pts] points sorted by cell (x, y, z, 0)
+    const float4* pts32;        // [n_pts + kPtsPad] points sorted by cell (x, y, z, |p|^2), then copies of the last
     const double* pts64;        // [n_pts][3] in the same order
     const int* cell_start;      // [n_cells + 1]
     float grid_lo[3];

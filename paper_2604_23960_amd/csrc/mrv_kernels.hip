@@ -30,6 +30,7 @@
 #include "../../include/mrv.h"
 #include "mrv_internal.hpp"
 
+
 namespace mrv {
 
 namespace {
@@ -747,6 +748,204 @@ __device__ __forceinline__ float4 place32(const float4* Fp, float4 L)
                        fmaf(r2.x, L.x, fmaf(r2.y, L.y, fmaf(r2.z, L.z, r2.w))), L.w);
 }
 
+// Value of v in lane src (every lane active).
+__device__ __forceinline__ float lane_get(float v, int src)
+{
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
+}
+
+__device__ __forceinline__ float readlane_f32(float v, int lane)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+// Grid cell of coordinate offset v (metres past the grid's low corner) along an axis
+// of dim cells at 1 / cell = inv, as an int in [-1, dim] (clamped before conversion).
+__device__ __forceinline__ int cell_of(float v, float inv, int dim)
+{
+    return (int)floorf(fminf(fmaxf(v * inv, -1.f), (float)dim));
+}
+
+// Sphere-point tests of one wave's 64 slots (four groups of 16) against the point
+// cloud, as 16 x 16 blocks on the matrix cores.  For a sphere (centre c, radius
+// r_s) and a point p of the cloud (radius r_p), with R = r_s + r_p,
+//   D = |c|^2 - R^2 - 2 c.p + |p|^2 = |p - c|^2 - R^2,
+// one MFMA per block: K = 4 rows (-2c, 1) of 16 spheres, columns (p, |p|^2) of 16
+// consecutive points of the sorted cloud (|p|^2 is stored with each point), the
+// accumulator preset to |c|^2 - R^2.  Group by group, the points are those of the
+// grid's cell rows that meet the group's bounding box widened by R + eps; each
+// row is a contiguous run of the cloud, taken 32 points at a time, so a step may
+// run past its row's end into the next points of the cloud, which are real points
+// as well (the cloud is padded past its end with copies of its last point): a hit
+// among them is a real collision and a clear one changes nothing.  A lane whose
+// smallest D lies within the rounding bound of the band revisits its pairs in the
+// direct form |p - c|^2 against (R -+ eps)^2, the FP32 test of every other
+// sphere-obstacle pair, and queues those within the band for FP64.  a0: slot of
+// lane 0; x, y, z: the lane's centre in the environment's frame.  Returns whether
+// one of the lane's tests is a sure collision; adds the pairs tested to *s_npt.
+template <class CD>
+__device__ bool point_blocks(const CD& cd, CTeam* tm, CEnv* env, int a0, float x, float y, float z, float rad,
+                             bool act, float eps, bool exhaustive, int q, int t, int* s_hit,
+                             unsigned long long* s_npt, int lane)
+{
+    const float rp = env->pt_radius;
+    const float R = rad + rp;
+    const float reach = R + eps;
+    const float w_own = act ? fmaf(-R, R, fmaf(x, x, fmaf(y, y, z * z))) : kFar;
+    const float lx = row_min16(act ? x - reach : 3.0e38f), hx = row_max16(act ? x + reach : -3.0e38f);
+    const float ly = row_min16(act ? y - reach : 3.0e38f), hy = row_max16(act ? y + reach : -3.0e38f);
+    const float lz = row_min16(act ? z - reach : 3.0e38f), hz = row_max16(act ? z + reach : -3.0e38f);
+    const float cell = env->grid_cell;
+    constexpr int kPtSteps = 2;
+    // |D_fp32 - D| for |c|, |p| <= rho and R <= Rm: the accumulator's |c|^2 - R^2 within
+    // 3 u (rho^2 + Rm^2), the stored |p|^2 within u rho^2, and the MFMA's products and
+    // four additions, whose partial sums stay below (|c| + |p|)^2 + R^2 <= 4 rho^2 + Rm^2,
+    // within 2 u rho^2 + 4 u (4 rho^2 + Rm^2): 22 u rho^2 + 7 u Rm^2 in all; 40 u leaves a margin
+    const float c2 = wave_max_f32(act ? fmaf(x, x, fmaf(y, y, z * z)) : 0.f);
+    const float rho2 = fmaxf(c2, env->mag * env->mag);
+    const float Rm = tm->r_max + rp;
+    const float e_err = 40.f * 5.9604645e-8f * (rho2 + Rm * Rm) + 1.0e-30f;
+    const float e_hi = e_err + fmaf(2.f * Rm, eps, eps * eps);
+    const float e_lo = -(e_err + 2.f * Rm * eps);
+    const unsigned long long am = __ballot(act);
+    const int i16 = lane & 15, q4 = lane >> 4;
+    const float* ptsf = reinterpret_cast<const float*>(env->pts32);
+    const float ginv = env->grid_inv;
+    const int d0 = env->grid_dim[0], d1 = env->grid_dim[1], d2 = env->grid_dim[2];
+    bool hit = false;
+    unsigned long long tests = 0;
+    for (int g = 0; g < 4; ++g) {
+        const unsigned gm = (unsigned)(am >> (16 * g)) & 0xFFFFu;
+        if (gm == 0u) continue;
+        if (!exhaustive && flag_read(s_hit)) break;
+        // cells of the group's box (wave-uniform)
+        const int cx0 = max(cell_of(readlane_f32(lx, 16 * g) - env->grid_lo[0], ginv, d0), 0);
+        const int cx1 = min(cell_of(readlane_f32(hx, 16 * g) - env->grid_lo[0], ginv, d0), d0 - 1);
+        const int cy0 = max(cell_of(readlane_f32(ly, 16 * g) - env->grid_lo[1], ginv, d1), 0);
+        const int cy1 = min(cell_of(readlane_f32(hy, 16 * g) - env->grid_lo[1], ginv, d1), d1 - 1);
+        const int cz0 = max(cell_of(readlane_f32(lz, 16 * g) - env->grid_lo[2], ginv, d2), 0);
+        const int cz1 = min(cell_of(readlane_f32(hz, 16 * g) - env->grid_lo[2], ginv, d2), d2 - 1);
+        if (cx0 > cx1 || cy0 > cy1 || cz0 > cz1) continue;
+        const int ny = cy1 - cy0 + 1;
+        const int n_rows = ny * (cz1 - cz0 + 1);
+        // operands: A row i = sphere i of the group, component q4; accumulator rows 4 q4 + r
+        const int src = 16 * g + i16;
+        const float ax = lane_get(x, src), ay = lane_get(y, src), az = lane_get(z, src);
+        const float aop = q4 == 0 ? -2.f * ax : (q4 == 1 ? -2.f * ay : (q4 == 2 ? -2.f * az : 1.f));
+        const int s0 = 16 * g + 4 * q4;
+        const floatx4 acc = { lane_get(w_own, s0), lane_get(w_own, s0 + 1), lane_get(w_own, s0 + 2),
+                              lane_get(w_own, s0 + 3) };
+        const unsigned nact = (unsigned)__popc(gm);
+        float best = 3.0e38f;
+        // rows 64 at a time, one per lane, each cut to the x extent the group can reach
+        // on it; then the non-empty rows by the whole wave
+        auto rows = [&](auto&& batch) {
+            for (int r0 = 0; r0 < n_rows; r0 += kWave) {
+                const int rr = r0 + lane;
+                int pb = 0, pe = 0;
+                if (rr < n_rows) {
+                    const int cz = cz0 + rr / ny;
+                    const int cy = cy0 + (rr - (cz - cz0) * ny);
+                    const float yc = fmaf((float)cy, cell, env->grid_lo[1]), zc = fmaf((float)cz, cell, env->grid_lo[2]);
+                    float xa = 3.0e38f, xb = -3.0e38f;
+                    for (unsigned gs = gm; gs; gs &= gs - 1u) {
+                        const int sl = 16 * g + __builtin_ctz(gs);
+                        const float sx = readlane_f32(x, sl), sy = readlane_f32(y, sl), sz = readlane_f32(z, sl);
+                        const float sr = readlane_f32(reach, sl);
+                        const float dz = fmaxf(fmaxf(zc - sz, sz - (zc + cell)), 0.f);
+                        const float dy = fmaxf(fmaxf(yc - sy, sy - (yc + cell)), 0.f);
+                        const float rem = fmaf(sr, sr, -fmaf(dy, dy, dz * dz));
+                        const float hw = __builtin_amdgcn_sqrtf(fmaxf(rem, 0.f));
+                        xa = rem >= 0.f ? fminf(xa, sx - hw) : xa;
+                        xb = rem >= 0.f ? fmaxf(xb, sx + hw) : xb;
+                    }
+                    const int ax = max(cell_of(xa - env->grid_lo[0], ginv, d0), cx0);
+                    const int bx = min(cell_of(xb - env->grid_lo[0], ginv, d0), cx1);
+                    if (ax <= bx) {
+                        const int crow = (cz * d1 + cy) * d0;
+                        pb = env->cell_start[crow + ax];
+                        pe = env->cell_start[crow + bx + 1];
+                    }
+                }
+                batch(pb, pe);
+            }
+        };
+        // the rows' points in steps of 32, the loads of kPtSteps steps in flight at a time
+        rows([&](int pb, int pe) {
+            unsigned long long m = __ballot(pe > pb);
+            int b = 0, se = 0;
+            for (;;) {
+                int sb[kPtSteps];
+                float v0[kPtSteps], v1[kPtSteps];
+                int n = 0;
+#pragma unroll
+                for (int k = 0; k < kPtSteps; ++k) {
+                    if (b >= se) {
+                        if (!m) break;
+                        const int L = __builtin_ctzll(m);
+                        m &= m - 1;
+                        b = __builtin_amdgcn_readlane(pb, L);
+                        se = __builtin_amdgcn_readlane(pe, L);
+                        tests += (unsigned long long)nact * (unsigned)((se - b + 31) & ~31);
+                    }
+                    sb[k] = b;
+                    b += 32;
+                    v0[k] = ptsf[(long long)(sb[k] + i16) * 4 + q4];
+                    v1[k] = ptsf[(long long)(sb[k] + 16 + i16) * 4 + q4];
+                    n = k + 1;
+                }
+                if (n == 0) break;
+#pragma unroll
+                for (int k = 0; k < kPtSteps; ++k) {
+                    if (k < n) {
+                        const floatx4 e0 = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, v0[k], acc, 0, 0, 0);
+                        const floatx4 e1 = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, v1[k], acc, 0, 0, 0);
+                        best = fminf(fminf(best, fminf(fminf(e0[0], e0[1]), fminf(e0[2], e0[3]))),
+                                     fminf(fminf(e1[0], e1[1]), fminf(e1[2], e1[3])));
+                    }
+                }
+                if (n < kPtSteps) break;
+            }
+        });
+        const bool sure = best < e_lo;
+        const bool unsure = !sure && best < e_hi;
+        hit = hit || sure;
+        // rare: pairs within the band and no collision known
+        if (__ballot(unsure) && !__ballot(hit) && !flag_read(s_hit)) {
+            const long long last = env->n_pts - 1;
+            // sphere by sphere of the lane's four rows, to keep few values live
+#pragma unroll 1
+            for (int r = 0; r < 4; ++r) {
+                const float sx = lane_get(x, s0 + r), sy = lane_get(y, s0 + r), sz = lane_get(z, s0 + r);
+                const float sr = lane_get(act ? rad : -1.f, s0 + r);
+                if (!__ballot(unsure && sr >= 0.f)) continue;
+                const float Rp = sr + rp;
+                const float plo = fmaxf(Rp - eps, 0.f), phi = Rp + eps;
+                const int sphere = tm->slot_sphere[a0 + s0 + r];
+                rows([&](int pb, int pe) {
+                    for (unsigned long long m = __ballot(pe > pb); m; m &= m - 1) {
+                    const int L = __builtin_ctzll(m);
+                    const int sb = __builtin_amdgcn_readlane(pb, L), se = __builtin_amdgcn_readlane(pe, L);
+                    for (int b = sb; b < se; b += 16) {
+                        const int p = b + i16;
+                        const float4 P = env->pts32[p];
+                        const float dx = sx - P.x, dy = sy - P.y, dz = sz - P.z;
+                        const float dd = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                        if (unsure && sr >= 0.f && dd <= phi * phi) {
+                            if (dd < plo * plo) hit = true;
+                            else if (!hit && !flag_read(s_hit))
+                                push_recheck(cd, q, t, RK_ENV_PT, sphere, (int)min((long long)p, last), 0u);
+                        }
+                    }
+                    }
+                });
+            }
+        }
+    }
+    if (lane == 0 && tests) atomicAdd(s_npt, tests);
+    return hit;
+}
+
 // Robot-obstacle tests of J (timestep, 64-slot chunk) tasks of one wave, one lane
 // per slot, in the environment's frame (`off` = team origin minus environment
 // origin), obstacle parameters in wave-uniform scalar loads (each sphere
@@ -847,68 +1046,10 @@ __device__ __forceinline__ void env_tasks(const CD& cd, CTeam* tm, CEnv* env, co
         // the sphere index and timestep of a queued test, read only when one is queued
         auto sa_of = [&]() { return tm->slot_sphere[a[j]]; };
         auto t_of = [&]() { return s_t[c[j]]; };
-        if (PTS && env->n_pts > 0 && act[j]) {
-            const float Rp = rad[j] + env->pt_radius;
-            const float xs[3] = { x[j], y[j], z[j] };
-            int lo3[3], hi3[3];
-            const float reach = Rp + eps;
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const int l = (int)floorf((xs[d] - reach - env->grid_lo[d]) * env->grid_inv);
-                const int h = (int)floorf((xs[d] + reach - env->grid_lo[d]) * env->grid_inv);
-                lo3[d] = l < 0 ? 0 : l;
-                hi3[d] = h >= env->grid_dim[d] ? env->grid_dim[d] - 1 : h;
-            }
-            const float plo = fmaxf(Rp - eps, 0.f), phi = Rp + eps;
-            const float plo2 = plo * plo, phi2 = phi * phi;
-            unsigned npt = 0;           // points tested by this lane
-            // Cell rows (fixed y and z cells, consecutive x cells) within reach of the
-            // centre only, each cut to the sphere's chord at the row's nearest y and z:
-            // a point within reach lies at least as close in y and z as its row does.
-            // Rounding of the cell bounds (~1e-7 m) is far inside the band eps, so no
-            // point closer than r + r_p + eps - 1e-7 is skipped, and every farther one
-            // is clear in FP64 as well.
-            const float reach2 = reach * reach, cell = env->grid_cell;
-            if (lo3[0] <= hi3[0])
-                for (int cz = lo3[2]; cz <= hi3[2]; ++cz) {
-                    const float z0 = fmaf((float)cz, cell, env->grid_lo[2]);
-                    const float dz = fmaxf(fmaxf(z0 - xs[2], xs[2] - (z0 + cell)), 0.f);
-                    for (int cy = lo3[1]; cy <= hi3[1]; ++cy) {
-                        const float y0 = fmaf((float)cy, cell, env->grid_lo[1]);
-                        const float dy = fmaxf(fmaxf(y0 - xs[1], xs[1] - (y0 + cell)), 0.f);
-                        const float rem = reach2 - fmaf(dy, dy, dz * dz);
-                        if (rem < 0.f) continue;
-                        const float hw = __builtin_amdgcn_sqrtf(rem);
-                        const int l0 = max((int)floorf((xs[0] - hw - env->grid_lo[0]) * env->grid_inv), lo3[0]);
-                        const int h0 = min((int)floorf((xs[0] + hw - env->grid_lo[0]) * env->grid_inv), hi3[0]);
-                        if (l0 > h0) continue;
-                        const int crow = (cz * env->grid_dim[1] + cy) * env->grid_dim[0];
-                        const int pb = env->cell_start[crow + l0];
-                        const int pe = env->cell_start[crow + h0 + 1];
-                        npt += (unsigned)(pe - pb);
-                        // four independent point loads in flight per step
-                        auto test_pt = [&](const float4 Pt, int p) {
-                            const float dx = x[j] - Pt.x, dy = y[j] - Pt.y, dz = z[j] - Pt.z;
-                            const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                            if (d2 <= phi2) {
-                                if (d2 < plo2) hit = true;
-                                else if (!hit && !flag_read(s_hit))
-                                    push_recheck(cd, q, t_of(), RK_ENV_PT, sa_of(), p, 0u);
-                            }
-                        };
-                        int p = pb;
-                        for (; p + 4 <= pe; p += 4) {
-                            const float4 P0 = env->pts32[p], P1 = env->pts32[p + 1], P2 = env->pts32[p + 2],
-                                         P3 = env->pts32[p + 3];
-                            test_pt(P0, p);
-                            test_pt(P1, p + 1);
-                            test_pt(P2, p + 2);
-                            test_pt(P3, p + 3);
-                        }
-                        for (; p < pe; ++p) test_pt(env->pts32[p], p);
-                    }
-                }
-            if (npt) atomicAdd(s_npt, (unsigned long long)npt);
+        if constexpr (PTS) {
+            if (env->n_pts > 0 && point_blocks(cd, tm, env, a[j] - lane, x[j], y[j], z[j], rad[j], act[j], eps,
+                                               exhaustive, q, t_of(), s_hit, s_npt, lane))
+                hit = true;
         }
         if (unsure && !(hit && !exhaustive)) {
             // rare: find the near obstacles and queue each for FP64 re-evaluation
@@ -943,7 +1084,7 @@ __device__ __forceinline__ void env_tasks(const CD& cd, CTeam* tm, CEnv* env, co
 // the obstacle phase); without it the walk compiles out, which keeps its registers
 // out of every other call.
 template <int KIND, bool PTS>
-__global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? kExhWGsPerCU : kWGsPerCU)) void k_validate(CallDev cd_arg)
+__global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? (PTS ? kExhPtsWGsPerCU : kExhWGsPerCU) : kWGsPerCU)) void k_validate(CallDev cd_arg)
 {
     (void)cd_arg;   // read in place through call_at()
     CCall& cd = call_at();

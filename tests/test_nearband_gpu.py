@@ -9,6 +9,12 @@
   of the 16-robot team) and self pairs (two spheres of one robot, one on its base
   frame) are placed so that collision iff the clearance is negative holds by
   construction; the test asserts that on the oracle too.
+* Sphere-point tests also run on the matrix cores in a Gram form, D = |c|^2 -
+  R^2 - 2 c.p + |p|^2, whose bound grows with |p|^2 relative to the cloud's
+  origin.  A probe sphere is placed 1.6-3.0 m from it at clearances -3 eps to
+  +6 eps from one point of a cloud (the point amid a cluster of points that stay
+  clear), so the kernel decides some of them from the bound and revisits the rest
+  in the direct form, re-evaluating the near ones in FP64.
 * Teams and environments far from the world origin (hundreds of metres): the
   kernels work relative to the team's and the environment's origins, so answers
   equal the oracle's there too; where a query's relative coordinates are large
@@ -208,6 +214,52 @@ def test_gram_near_band_self(ctx, ia, ib):
             got = ctx.mv(th, -1, paths, flags)
             assert np.array_equal(got, ref), (ia, ib, dist, flags, got, ref)
         ctx.unload(th)
+
+
+def point_case(dist, seed):
+    """A probe robot (one sphere of radius R_PROBE on three prismatic joints) and a
+    cloud (radius RP_PROBE) whose bounding box is centred at the world origin: the
+    probe point p0 lies `dist` m from it along a random unit w, the sphere's centre
+    at zero joint values at p0 - (R_PROBE + RP_PROBE) w, so joint vector -delta w
+    sets the clearance to delta.  The other points are the box's corners and a
+    cluster of 200 around p0, all clear of the sphere by at least 2 mm.
+    Returns (robot, env, configurations over DELTAS)."""
+    rng = np.random.default_rng(seed)
+    w = rng.normal(size=3)
+    w /= np.linalg.norm(w)
+    p0 = dist * w
+    c0 = p0 - (R_PROBE + RP_PROBE) * w
+    corners = np.array([[sx, sy, sz] for sx in (-3.1, 3.1) for sy in (-3.1, 3.1) for sz in (-3.1, 3.1)])
+    # cluster: directions mostly towards p0, at R + r_p + 2..30 mm from c0
+    u = rng.normal(size=(200, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    u = np.where((u @ w)[:, None] < 0.2, u + 1.2 * w, u)
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    cl = c0 + (R_PROBE + RP_PROBE + rng.uniform(0.002, 0.03, (200, 1))) * u
+    pts = np.concatenate([corners, cl, p0[None, :]])
+    robot = probe_robot([(0.0, 0.0, 0.0)], base_xyz=c0)
+    cfgs = (-DELTAS[:, None] * w[None, :])[:, None, :]
+    return robot, W.Env(points=pts, point_radius=RP_PROBE), cfgs
+
+
+RP_PROBE = 0.005
+
+
+@pytest.mark.parametrize("dist", [1.6, 2.3, 3.0])
+def test_gram_near_band_points(ctx, dist):
+    robot, env, cfgs = point_case(dist, int(dist * 10))
+    paths = single_state_paths(cfgs, dof_stride=3, T=4)
+    ot, oe, op = oracle.Team([robot]), oracle.Env(env), oracle.Paths(paths)
+    ref = oracle.mv(ot, oe, op, check_env=True)
+    assert np.array_equal(ref, (DELTAS >= 0).astype(np.uint8))      # by construction
+    th, eh = ctx.load_team([robot]), ctx.load_env(env)
+    for flags in (mrv.CHECK_ENV, mrv.CHECK_ENV | mrv.EXHAUSTIVE, mrv.CHECK_ENV | mrv.PAIRS_FIRST,
+                  mrv.CHECK_ENV | mrv.HIERARCHICAL):
+        say("sphere-point probe", f"|p|={dist}", "flags", flags)
+        got = ctx.mv(th, eh, paths, flags)
+        assert np.array_equal(got, ref), (dist, flags, got, ref)
+    ctx.unload(th)
+    ctx.unload(eh)
 
 
 def shifted(w, shift):
