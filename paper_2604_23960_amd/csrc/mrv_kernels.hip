@@ -810,6 +810,7 @@ __device__ bool point_blocks(const CD& cd, CTeam* tm, CEnv* env, int a0, float x
     const unsigned long long am = __ballot(act);
     const int i16 = lane & 15, q4 = lane >> 4;
     const float* ptsf = reinterpret_cast<const float*>(env->pts32);
+    const unsigned lane_off = (unsigned)(i16 * 4 + q4);
     const float ginv = env->grid_inv;
     const int d0 = env->grid_dim[0], d1 = env->grid_dim[1], d2 = env->grid_dim[2];
     bool hit = false;
@@ -836,7 +837,10 @@ __device__ bool point_blocks(const CD& cd, CTeam* tm, CEnv* env, int a0, float x
         const floatx4 acc = { lane_get(w_own, s0), lane_get(w_own, s0 + 1), lane_get(w_own, s0 + 2),
                               lane_get(w_own, s0 + 3) };
         const unsigned nact = (unsigned)__popc(gm);
+        const float half = 0.5f * cell;
+        const float ymid0 = env->grid_lo[1] + half, zmid0 = env->grid_lo[2] + half;
         float best = 3.0e38f;
+        unsigned long long gpts = 0;   // points taken by the steps (wave-uniform)
         // rows 64 at a time, one per lane, each cut to the x extent the group can reach
         // on it; then the non-empty rows by the whole wave
         auto rows = [&](auto&& batch) {
@@ -846,18 +850,21 @@ __device__ bool point_blocks(const CD& cd, CTeam* tm, CEnv* env, int a0, float x
                 if (rr < n_rows) {
                     const int cz = cz0 + rr / ny;
                     const int cy = cy0 + (rr - (cz - cz0) * ny);
-                    const float yc = fmaf((float)cy, cell, env->grid_lo[1]), zc = fmaf((float)cz, cell, env->grid_lo[2]);
+                    // the row's y and z cell centres; a sphere's distance to the row's slab is
+                    // |centre - mid| - cell / 2 per axis (0 inside)
+                    const float ym = fmaf((float)cy, cell, ymid0), zm = fmaf((float)cz, cell, zmid0);
                     float xa = 3.0e38f, xb = -3.0e38f;
                     for (unsigned gs = gm; gs; gs &= gs - 1u) {
                         const int sl = 16 * g + __builtin_ctz(gs);
                         const float sx = readlane_f32(x, sl), sy = readlane_f32(y, sl), sz = readlane_f32(z, sl);
                         const float sr = readlane_f32(reach, sl);
-                        const float dz = fmaxf(fmaxf(zc - sz, sz - (zc + cell)), 0.f);
-                        const float dy = fmaxf(fmaxf(yc - sy, sy - (yc + cell)), 0.f);
+                        const float dz = fmaxf(fabsf(sz - zm) - half, 0.f);
+                        const float dy = fmaxf(fabsf(sy - ym) - half, 0.f);
                         const float rem = fmaf(sr, sr, -fmaf(dy, dy, dz * dz));
-                        const float hw = __builtin_amdgcn_sqrtf(fmaxf(rem, 0.f));
-                        xa = rem >= 0.f ? fminf(xa, sx - hw) : xa;
-                        xb = rem >= 0.f ? fmaxf(xb, sx + hw) : xb;
+                        // no chord: a half-width of -3e38 leaves both ends unchanged
+                        const float hw = rem >= 0.f ? __builtin_amdgcn_sqrtf(rem) : -3.0e38f;
+                        xa = fminf(xa, sx - hw);
+                        xb = fmaxf(xb, sx + hw);
                     }
                     const int ax = max(cell_of(xa - env->grid_lo[0], ginv, d0), cx0);
                     const int bx = min(cell_of(xb - env->grid_lo[0], ginv, d0), cx1);
@@ -886,12 +893,14 @@ __device__ bool point_blocks(const CD& cd, CTeam* tm, CEnv* env, int a0, float x
                         m &= m - 1;
                         b = __builtin_amdgcn_readlane(pb, L);
                         se = __builtin_amdgcn_readlane(pe, L);
-                        tests += (unsigned long long)nact * (unsigned)((se - b + 31) & ~31);
+                        gpts += (unsigned)((se - b + 31) & ~31);
                     }
                     sb[k] = b;
                     b += 32;
-                    v0[k] = ptsf[(long long)(sb[k] + i16) * 4 + q4];
-                    v1[k] = ptsf[(long long)(sb[k] + 16 + i16) * 4 + q4];
+                    // a wave-uniform base and a fixed lane offset: component q4 of point b + i16
+                    const float* step = ptsf + (size_t)(unsigned)sb[k] * 4;
+                    v0[k] = step[lane_off];
+                    v1[k] = step[lane_off + 64];
                     n = k + 1;
                 }
                 if (n == 0) break;
@@ -907,6 +916,7 @@ __device__ bool point_blocks(const CD& cd, CTeam* tm, CEnv* env, int a0, float x
                 if (n < kPtSteps) break;
             }
         });
+        tests += (unsigned long long)nact * gpts;
         const bool sure = best < e_lo;
         const bool unsure = !sure && best < e_hi;
         hit = hit || sure;
