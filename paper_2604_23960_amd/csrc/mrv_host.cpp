@@ -694,11 +694,12 @@ int default_chunk(const TeamHost& tm, int kind, int exhaustive)
     // queries end in their first tiles, whose fixed cost then dominates; one 8-wave
     // workgroup per CU runs them (FFC on the arm+rectangle team: 24 timesteps,
     // 20.1 ms against 26.5 ms at 16).  Exhaustive calls: up to 8, the largest that
-    // keeps as many workgroups per CU as registers allow (six for MV, five for FFC)
+    // keeps as many workgroups per CU as registers allow (seven for MV and FFC)
     // within the CU's 160 KiB of LDS if that is at least 2, else one workgroup
-    // fewer, ...
+    // fewer, ... (exhaustive FFC on the arm+rectangle team: 3 timesteps at seven
+    // per CU 214 ms, 4 at five 244 ms)
     if (!exhaustive) return std::max(1, std::min(cmax, 32));
-    for (int wgs = kind == 0 ? kExhWGsPerCU : kWGsPerCU; wgs >= 1; --wgs) {
+    for (int wgs = kExhWGsPerCU; wgs >= 1; --wgs) {
         const int c = (int)((160 * 1024 / wgs - 1024) / per_t);
         if (c >= 2 || wgs == 1) return std::max(1, std::min(cmax, std::min(8, c)));
     }

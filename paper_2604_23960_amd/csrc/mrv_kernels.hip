@@ -1094,7 +1094,7 @@ __device__ __forceinline__ void env_tasks(const CD& cd, CTeam* tm, CEnv* env, co
 // the obstacle phase); without it the walk compiles out, which keeps its registers
 // out of every other call.
 template <int KIND, bool PTS>
-__global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? (PTS ? kExhPtsWGsPerCU : kExhWGsPerCU) : kWGsPerCU)) void k_validate(CallDev cd_arg)
+__global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? (PTS ? kExhPtsWGsPerCU : kExhWGsPerCU) : (KIND == 4 ? kExhWGsPerCU : kWGsPerCU))) void k_validate(CallDev cd_arg)
 {
     (void)cd_arg;   // read in place through call_at()
     CCall& cd = call_at();
