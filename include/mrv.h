@@ -289,7 +289,9 @@ typedef struct {
                               * 0 or 1 = golden-ratio bisection, 2 = rake (as MRV_ORDER_RAKE),
                               * 3 = consecutive timesteps (as MRV_ORDER_LINEAR); FFC ignores it */
     int32_t claim;           /* tiles a workgroup takes per claim on the launch's tile counter:
-                              * 0 = automatic (4 for exhaustive calls, 1 otherwise), else 1..16 */
+                              * 0 = automatic (at most 4 for exhaustive calls and 8 otherwise, fewer
+                              * when a call has under 8 claims' worth of tiles per workgroup),
+                              * else 1..16 */
 } mrv_tiling;
 /* Set the tiling used for (team, kind), kind 0 = MV, 1 = FFC, by the calls whose
  * MRV_EXHAUSTIVE flag equals that of flags (other flag bits are ignored): calls

@@ -159,6 +159,8 @@ struct CallDev {
     float eps32;                // near band in metres before per-query scaling
     int chunk_floor;            // smallest tile length the call's scratch was sized for
     int claim;                  // tiles taken per claim on the tile counter (>= 1)
+    int claim_auto;             // 1: claim is only the most taken; small calls take fewer, keeping
+                                // at least 8 claims per workgroup
     int points;                 // 1: some query's environment holds a point cloud (MV with obstacles)
     long long max_nt;           // most tiles a query may have (tile bins - 2)
     long long n_wp;

@@ -1135,7 +1135,7 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? (PT
 
     // the tile space, read once into LDS (thread 0's claims read it from there)
     __shared__ long long s_total, s_gtotal;
-    __shared__ int s_M;
+    __shared__ int s_M, s_kc;
 
     unsigned long long c_rr = 0, c_self = 0;    // wave-uniform counters
     unsigned c_env = 0;                         // per lane: obstacle tests of this workgroup's tiles
@@ -1145,6 +1145,10 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? (PT
         s_total = total;
         s_gtotal = hier ? 2 * total : total;
         s_M = cd.ctrl[0];
+        // tiles per claim: the call's value, or (automatic) at most that, keeping at
+        // least 8 claims per workgroup
+        const long long per = (hier ? 2 * total : total) / (8ll * (long long)gridDim.x);
+        s_kc = cd.claim_auto ? (int)(per < 1 ? 1 : (per < cd.claim ? per : cd.claim)) : cd.claim;
         s_kcur = 0;
         s_gnext = 0;
         s_gend = 0;
@@ -1180,10 +1184,10 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? (PT
                     if (s_key != 0xFFFFFFFFu) atomicMin(cd.word + s_q, s_key);
                 }
             }
-            // cd.claim consecutive tiles per atomic (one counter serves the whole chip)
+            // s_kc consecutive tiles per atomic (one counter serves the whole chip)
             long long g = s_gnext;
             if (g >= s_gend) {
-                const int kc = cd.claim;
+                const int kc = s_kc;
                 g = (long long)atomicAdd(&w64[1], (unsigned long long)kc);
                 s_gend = g + kc;
             }
