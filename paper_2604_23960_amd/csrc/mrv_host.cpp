@@ -696,15 +696,21 @@ int default_chunk(const TeamHost& tm, int kind, int exhaustive)
     int cmax = (int)((kLdsBudget - 2 * 1024) / per_t);
     cmax = std::min(cmax, kMaxChunk);
     if (cmax < 1) cmax = 1;
-    // early-terminating calls: as many timesteps as fit, up to 32, since most
-    // queries end in their first tiles, whose fixed cost then dominates; one 8-wave
-    // workgroup per CU runs them (FFC on the arm+rectangle team: 24 timesteps,
-    // 20.1 ms against 26.5 ms at 16).  Exhaustive calls: up to 8, the largest that
+    // early-terminating calls: the longest tiles (up to 32 timesteps) with which two
+    // 8-wave workgroups fit in the CU's LDS, if that is at least 2, else as many
+    // timesteps as fit for one (arm workload MV: 14 timesteps, 4.0 ms against
+    // 6.2 ms at 29 with one workgroup per CU; arm+rectangle FFC: 11, 10.2 ms against
+    // 13.7 ms at 24; the cloud team: 6, MV 39.1 ms and FFC 51.2 ms against 47.3 ms
+    // and 87.9 ms at 12; shorter tiles are slower, 5.1 ms at 8 on the arms, 11.6 ms
+    // at 8 for FFC).  Exhaustive calls: up to 8, the largest that
     // keeps as many workgroups per CU as registers allow (seven for MV and FFC)
     // within the CU's 160 KiB of LDS if that is at least 2, else one workgroup
     // fewer, ... (exhaustive FFC on the arm+rectangle team: 3 timesteps at seven
     // per CU 214 ms, 4 at five 244 ms)
-    if (!exhaustive) return std::max(1, std::min(cmax, 32));
+    if (!exhaustive) {
+        const int c2 = (int)((kLdsBudget / 2 - 1024) / per_t);
+        return c2 >= 2 ? std::min(c2, 32) : std::max(1, std::min(cmax, 32));
+    }
     for (int wgs = kExhWGsPerCU; wgs >= 1; --wgs) {
         const int c = (int)((160 * 1024 / wgs - 1024) / per_t);
         if (c >= 2 || wgs == 1) return std::max(1, std::min(cmax, std::min(8, c)));
