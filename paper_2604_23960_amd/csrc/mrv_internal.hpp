@@ -23,7 +23,7 @@ constexpr int kMaxRobots = 32;
 constexpr int kMaxJoints = 8;
 constexpr int kMaxChunk = 64;       // timesteps per tile
 constexpr int kLdsBudget = 160 * 1024;   // LDS one workgroup may use on gfx950
-constexpr int kWGsPerCU = 5;        // validation workgroups per CU the register budget allows (exhaustive MV with a focus set)
+constexpr int kWGsPerCU = 6;        // validation workgroups per CU the register budget allows (exhaustive MV with a focus set, 80 VGPRs)
 constexpr int kExhWGsPerCU = 7;     // the same for the exhaustive MV and FFC kernels (72 VGPRs)
 constexpr int kExhPtsWGsPerCU = 6;  // and for its build for point clouds (80 VGPRs)
 // The near band of a query widens in proportion to the largest coordinate magnitude
