@@ -329,7 +329,7 @@ def disks_bench(ctx, n_queries=4096, reps=20):
     return res
 
 
-def cloud_bench(log, n_queries=262_144, tune_sample=1024, exhaustive_queries=8192, tune_budget_s=15.0):
+def cloud_bench(log, n_queries=262_144, tune_sample=8192, exhaustive_queries=8192, tune_budget_s=15.0):
     """16-robot team in a 200k-point cloud: early-exit MV and FFC over the whole
     batch, exhaustive MV on a slice (each with its roofline), default vs autotuned
     tiling (the tuner held to a time budget), and one-launch graph replay vs the

@@ -773,8 +773,10 @@ __device__ __forceinline__ int cell_of(float v, float inv, int dim)
 // one MFMA per block: K = 4 rows (-2c, 1) of 16 spheres, columns (p, |p|^2) of 16
 // consecutive points of the sorted cloud (|p|^2 is stored with each point), the
 // accumulator preset to |c|^2 - R^2.  Group by group, the points are those of the
-// grid's cell rows that meet the group's bounding box widened by R + eps; each
-// row is a contiguous run of the cloud, taken 32 points at a time, so a step may
+// grid's cell rows that meet the group's bounding box widened by R + eps, each row
+// cut to the union of the group's chords on it (a point within R + eps of a sphere
+// lies in that union: the cut rounds by about 1e-7 m, far inside eps); each row is
+// a contiguous run of the cloud, taken 32 points at a time, so a step may
 // run past its row's end into the next points of the cloud, which are real points
 // as well (the cloud is padded past its end with copies of its last point): a hit
 // among them is a real collision and a clear one changes nothing.  A lane whose
