@@ -329,7 +329,8 @@ def disks_bench(ctx, n_queries=4096, reps=20):
     return res
 
 
-def cloud_bench(log, n_queries=262_144, tune_sample=8192, exhaustive_queries=8192, tune_budget_s=15.0):
+def cloud_bench(log, n_queries=262_144, tune_sample=8192, exhaustive_tune_sample=1024, exhaustive_queries=8192,
+                tune_budget_s=15.0):
     """16-robot team in a 200k-point cloud: early-exit MV and FFC over the whole
     batch, exhaustive MV on a slice (each with its roofline), default vs autotuned
     tiling (the tuner held to a time budget), and one-launch graph replay vs the
@@ -371,7 +372,12 @@ def cloud_bench(log, n_queries=262_144, tune_sample=8192, exhaustive_queries=819
 
     res["default_tiling"] = measure("default")
     t0 = time.perf_counter()
-    ctx.autotune(th, eh, 0, sub.subset(np.arange(tune_sample)), mrv.CHECK_ENV | mrv.EXHAUSTIVE)
+    # exhaustive work per query does not depend on the batch, so a small sample
+    # serves; early-terminating FFC prunes by what other queries' tiles found, which
+    # a sample much smaller than the batch misrepresents (tuned on 1,024 path sets,
+    # the chosen tiling took 80.7 ms on the 131,072 against 51.1 ms for the default;
+    # on 8,192 the tuner keeps the default)
+    ctx.autotune(th, eh, 0, sub.subset(np.arange(exhaustive_tune_sample)), mrv.CHECK_ENV | mrv.EXHAUSTIVE)
     ctx.autotune(th, -1, 1, ffcp.subset(np.arange(tune_sample)), 0)
     res["autotune_seconds"] = time.perf_counter() - t0
     res["autotuned"] = measure("autotuned")

@@ -309,7 +309,10 @@ mrv_status mrv_get_tiling(mrv_ctx ctx, int32_t team, int32_t kind, uint32_t flag
  * the interleave, each trial the best of two timed runs after a warm-up.  The
  * search stops after MRV_TUNE_BUDGET_MS of trial time and keeps the best tiling
  * found so far; the fastest is set for the team (as mrv_set_tiling with the same
- * flags would) and returned in *best.
+ * flags would) and returned in *best.  Early-terminating calls skip tiles on
+ * outcomes other queries' tiles found, so their sample should come near the batch
+ * size the tiling is for (FFC of the 16-robot cloud team: tuned on 1,024 path sets
+ * the choice lost on 131,072; on 8,192 the default was kept).
  * Results are cached per context by the team's shape (spheres, frames, groups,
  * robots), the environment's obstacle counts and the flags: a later call with
  * an equal key returns the cached tiling without timing.  The answers of MV/FFC
