@@ -776,7 +776,7 @@ __device__ __forceinline__ int cell_of(float v, float inv, int dim)
 // grid's cell rows that meet the group's bounding box widened by R + eps, each row
 // cut to the union of the group's chords on it (a point within R + eps of a sphere
 // lies in that union: the cut rounds by about 1e-7 m, far inside eps); each row is
-// a contiguous run of the cloud, taken 32 points at a time, so a step may
+// a contiguous run of the cloud, taken 32 points at a time (16 at its end), so a step may
 // run past its row's end into the next points of the cloud, which are real points
 // as well (the cloud is padded past its end with copies of its last point): a hit
 // among them is a real collision and a clear one changes nothing.  A lane whose
@@ -879,13 +879,14 @@ __device__ bool point_blocks(const CD& cd, CTeam* tm, CEnv* env, int a0, float x
                 batch(pb, pe);
             }
         };
-        // the rows' points in steps of 32, the loads of kPtSteps steps in flight at a time
+        // the rows' points in steps of 32 (16 where a row has no more), the loads of
+        // kPtSteps steps in flight at a time
         rows([&](int pb, int pe) {
             unsigned long long m = __ballot(pe > pb);
             int b = 0, se = 0;
             for (;;) {
-                int sb[kPtSteps];
                 float v0[kPtSteps], v1[kPtSteps];
+                bool two[kPtSteps];     // the step's second 16 points hold some of the row's
                 int n = 0;
 #pragma unroll
                 for (int k = 0; k < kPtSteps; ++k) {
@@ -895,14 +896,14 @@ __device__ bool point_blocks(const CD& cd, CTeam* tm, CEnv* env, int a0, float x
                         m &= m - 1;
                         b = __builtin_amdgcn_readlane(pb, L);
                         se = __builtin_amdgcn_readlane(pe, L);
-                        gpts += (unsigned)((se - b + 31) & ~31);
+                        gpts += (unsigned)((se - b + 15) & ~15);
                     }
-                    sb[k] = b;
-                    b += 32;
+                    two[k] = se - b > 16;
                     // a wave-uniform base and a fixed lane offset: component q4 of point b + i16
-                    const float* step = ptsf + (size_t)(unsigned)sb[k] * 4;
+                    const float* step = ptsf + (size_t)(unsigned)b * 4;
                     v0[k] = step[lane_off];
-                    v1[k] = step[lane_off + 64];
+                    v1[k] = two[k] ? step[lane_off + 64] : 0.f;
+                    b += 32;
                     n = k + 1;
                 }
                 if (n == 0) break;
@@ -910,9 +911,11 @@ __device__ bool point_blocks(const CD& cd, CTeam* tm, CEnv* env, int a0, float x
                 for (int k = 0; k < kPtSteps; ++k) {
                     if (k < n) {
                         const floatx4 e0 = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, v0[k], acc, 0, 0, 0);
-                        const floatx4 e1 = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, v1[k], acc, 0, 0, 0);
-                        best = fminf(fminf(best, fminf(fminf(e0[0], e0[1]), fminf(e0[2], e0[3]))),
-                                     fminf(fminf(e1[0], e1[1]), fminf(e1[2], e1[3])));
+                        best = fminf(best, fminf(fminf(e0[0], e0[1]), fminf(e0[2], e0[3])));
+                        if (two[k]) {
+                            const floatx4 e1 = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, v1[k], acc, 0, 0, 0);
+                            best = fminf(best, fminf(fminf(e1[0], e1[1]), fminf(e1[2], e1[3])));
+                        }
                     }
                 }
                 if (n < kPtSteps) break;
