@@ -59,8 +59,8 @@ def executed_flop(team, env, stats):
     """FLOP of one MV/FFC launch from its executed-test counters, split by the pipe
     that runs it.  Matrix cores: 10 per robot-robot, self and sphere-point test (the
     Gram form's 16 x 16 x 4 products plus the vector unit's minimum; sphere-point
-    tests are the pairs of a group's spheres and the points of the cell rows its box
-    meets).  Vector unit: FK and sphere placement of every evaluated robot-state, 10
+    tests are the pairs of a 16-sphere group's active spheres and the points its
+    blocks take, 16 at a time from the cell rows its spheres reach).  Vector unit: FK and sphere placement of every evaluated robot-state, 10
     per sphere-obstacle test, 26 per box or cylinder test actually run (the kernel
     skips those whose world box misses a row of 16 spheres by more than the near
     band; that skip is comparisons only and counts no FLOP)."""

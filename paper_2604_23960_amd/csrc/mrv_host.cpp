@@ -71,17 +71,14 @@ namespace {
 size_t lds_per_t(const TeamHost& tm);
 int default_chunk(const TeamHost& tm, int kind, int exhaustive);
 inline int mode_of(uint32_t flags) { return (flags & MRV_EXHAUSTIVE) ? 1 : 0; }
-// Tiles per claim when the tiling leaves it automatic: exhaustive calls run many
-// short tiles, and one atomic counter serves only about 80 M claims/s (the arm
-// workload's exhaustive MV was held to 31 ms by it at one tile per claim);
-// early-terminating calls take one tile at a time, so that each tile sees the
-// outcomes known when it starts.
-// Tiles per claim when the tiling leaves it automatic: at most 4 for exhaustive
-// calls and 8 for early-terminating ones, whose tiles often end at once (a known
-// outcome); the kernel takes fewer when the call has fewer than 8 claims' worth
-// of tiles per workgroup (early-terminating MV on the arm workload 6.4 ms at 8
-// against 7.4 ms at 1, the cloud team's 47.6 ms against 78.5 ms; exhaustive
-// calls gain nothing past 4)
+// Tiles per claim when the tiling leaves it automatic: one atomic counter serves
+// only about 80 M claims/s (the arm workload's exhaustive MV was held to 31 ms by
+// it at one tile per claim), so exhaustive calls take up to 4 and early-terminating
+// ones, whose tiles often end at once on a known outcome, up to 8; the kernel takes
+// fewer when the call has fewer than 8 claims' worth of tiles per workgroup.  Each
+// tile still reads its query's outcome when it starts.  (Early-terminating MV on
+// the arm workload 6.4 ms at 8 against 7.4 ms at 1, the cloud team's 47.6 ms
+// against 78.5 ms; exhaustive calls gain nothing past 4.)
 inline int default_claim(uint32_t flags) { return (flags & MRV_EXHAUSTIVE) ? 4 : 8; }
 
 inline double sq(double v) { return v * v; }
@@ -699,7 +696,7 @@ int default_chunk(const TeamHost& tm, int kind, int exhaustive)
     // early-terminating calls: the longest tiles (up to 32 timesteps) with which two
     // 8-wave workgroups fit in the CU's LDS, if that is at least 2, else as many
     // timesteps as fit for one (arm workload MV: 14 timesteps, 4.0 ms against
-    // 6.2 ms at 29 with one workgroup per CU; arm+rectangle FFC: 11, 10.2 ms against
+    // 6.2 ms at 29 with one workgroup per CU; arm+rectangle FFC: 12, 9.8 ms against
     // 13.7 ms at 24; the cloud team: 6, MV 39.1 ms and FFC 51.2 ms against 47.3 ms
     // and 87.9 ms at 12; shorter tiles are slower, 5.1 ms at 8 on the arms, 11.6 ms
     // at 8 for FFC).  Exhaustive calls: up to 8, the largest that
