@@ -349,8 +349,9 @@ typedef struct {
                                                    the bounding-box cull are not counted), self */
     uint64_t near_rechecks;      /* tests re-evaluated in FP64 */
     double kernel_ms;            /* validation kernel time of the last call (device events) */
-    uint64_t point_tests;        /* sphere-point pairs tested (point clouds: each 16-sphere group against the
-                                    points of the grid cell rows its bounding box meets) */
+    uint64_t point_tests;        /* sphere-point pairs tested (point clouds: each 16-sphere group's spheres
+                                    against the points its blocks take, 16 at a time, from the grid cell
+                                    rows its spheres reach) */
 } mrv_stats;
 /* Counters of the last MV/FFC call on this context (synchronises the stream). */
 mrv_status mrv_last_stats(mrv_ctx ctx, mrv_stats* out);
