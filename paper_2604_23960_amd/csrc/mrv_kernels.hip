@@ -936,7 +936,8 @@ __device__ bool point_blocks(const CD& cd, CTeam* tm, CEnv* env, int a0, float x
                 if (!__ballot(unsure && sr >= 0.f)) continue;
                 const float Rp = sr + rp;
                 const float plo = fmaxf(Rp - eps, 0.f), phi = Rp + eps;
-                const int sphere = tm->slot_sphere[a0 + s0 + r];
+                // (read only for a real sphere: the wave's last chunk may end past the slots)
+                const int sphere = sr >= 0.f ? tm->slot_sphere[a0 + s0 + r] : -1;
                 rows([&](int pb, int pe) {
                     for (unsigned long long m = __ballot(pe > pb); m; m &= m - 1) {
                     const int L = __builtin_ctzll(m);
