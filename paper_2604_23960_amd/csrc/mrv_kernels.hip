@@ -1469,9 +1469,17 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? (PT
                         // each block's record loaded once and its MFMAs independent
                         if (sb0 < sb1) {
                             for (int c0 = 0; c0 < nv; c0 += kSI) {
-                                float best[kSI];
+                                float best[kSI], aop[kSI];
+                                int row[kSI];
 #pragma unroll
-                                for (int i = 0; i < kSI; ++i) best[i] = 3.0e38f;
+                                for (int i = 0; i < kSI; ++i) {
+                                    best[i] = 3.0e38f;
+                                    // past the tile's last timestep a slot repeats that timestep
+                                    // (its result is dropped below), so the blocks carry no branch
+                                    // and their MFMAs issue back to back
+                                    row[i] = min(c0 + i, nv - 1) * TS;
+                                    aop[i] = -2.f * sp[row[i] + q4 * GSp + ga * 16 + i16];
+                                }
                                 for (int sb = sb0; sb < sb1; ++sb) {
                                     const int gb = cload(tm->sblocks + 16 * sb + 1);
                                     const unsigned long long* mk = sb_masks(tm, sb);
@@ -1479,17 +1487,14 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? (PT
                                                              m3 = cload64(mk + 3);
 #pragma unroll
                                     for (int i = 0; i < kSI; ++i) {
-                                        if (c0 + i < nv) {
-                                            const float* base = sp + (long long)(c0 + i) * TS;
-                                            const float aop = -2.f * base[q4 * GSp + ga * 16 + i16];
-                                            const float4 cw = *reinterpret_cast<const float4*>(base + 4 * GSp + ga * 16 + 4 * q4);
-                                            const floatx4 acc = { lane_select(m0, cw.x, kFar), lane_select(m1, cw.y, kFar),
-                                                                  lane_select(m2, cw.z, kFar), lane_select(m3, cw.w, kFar) };
-                                            const float bop = base[q4 * GSp + gb * 16 + i16];
-                                            const float wb = base[4 * GSp + gb * 16 + i16];
-                                            const floatx4 d = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, bop, acc, 0, 0, 0);
-                                            best[i] = block_min(d, wb, best[i]);
-                                        }
+                                        const float* base = sp + row[i];
+                                        const float4 cw = *reinterpret_cast<const float4*>(base + 4 * GSp + ga * 16 + 4 * q4);
+                                        const floatx4 acc = { lane_select(m0, cw.x, kFar), lane_select(m1, cw.y, kFar),
+                                                              lane_select(m2, cw.z, kFar), lane_select(m3, cw.w, kFar) };
+                                        const float bop = base[q4 * GSp + gb * 16 + i16];
+                                        const float wb = base[4 * GSp + gb * 16 + i16];
+                                        const floatx4 d = __builtin_amdgcn_mfma_f32_16x16x4f32(aop[i], bop, acc, 0, 0, 0);
+                                        best[i] = block_min(d, wb, best[i]);
                                     }
                                 }
 #pragma unroll
