@@ -569,13 +569,6 @@ __device__ __forceinline__ float block_min(floatx4 d, float wb, float best)
     return fminf(best, col_min(d, wb));
 }
 
-__device__ __forceinline__ float wave_max_f32(float v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
 // Minimum and maximum over each row of 16 lanes, in every lane of the row: lanes
 // exchanged within quads, then rows rotated by 4 and 8 (DPP; all lanes active).
 template <int CTRL>
@@ -757,6 +750,14 @@ __device__ __forceinline__ float lane_get(float v, int src)
 __device__ __forceinline__ float readlane_f32(float v, int lane)
 {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+// Maximum over the wave, in every lane (every lane active): the row maxima, then
+// the four rows' values read from their first lanes.
+__device__ __forceinline__ float wave_max_f32(float v)
+{
+    v = row_max16(v);
+    return fmaxf(fmaxf(readlane_f32(v, 0), readlane_f32(v, 16)), fmaxf(readlane_f32(v, 32), readlane_f32(v, 48)));
 }
 
 // Grid cell of coordinate offset v (metres past the grid's low corner) along an axis
@@ -1330,56 +1331,106 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? (PT
 
         // --- sphere records, slot-major: lane idx keeps slot idx mod GS over the
         // tile's timesteps c0, c0 + cstep, ... (c0 = idx / GS), so a slot's frame
-        // index and local centre are loaded once per tile.  First the centres
-        // relative to the team origin (padding slots at the origin) ...
+        // index and local centre are loaded once per tile.
         const int cstep = GS < WG ? WG / GS : 1;
         const int span = cstep * GS;
-        for (int idx = tid; idx < span; idx += WG) {
-            const int c0 = idx / GS;
-            const int s = idx - c0 * GS;
-            const int fs = tm->slot_frame[s];
-            const float4 L = tm->slot_local[s];
-            for (int c = c0; c < nv; c += cstep) {
-                float x = 0.f, y = 0.f, z = 0.f;
-                if (fs >= 0) {
-                    const float4 X = place32(reinterpret_cast<const float4*>(sp + (long long)c * TS + fr_off) + fs * 3, L);
-                    x = X.x;
-                    y = X.y;
-                    z = X.z;
-                }
-                float* row = sp + (long long)c * TS + s;
-                row[0] = x;
-                row[GSp] = y;
-                row[2 * GSp] = z;
-            }
-        }
-        __syncthreads();
-
-        // ... then, over the frames, the radius and w = |p|^2 - r^2 rows (radius 0 and
-        // w far away for padding)
-        {
+        constexpr int kRec = 4;
+        if (GS <= WG && nv <= kRec * cstep) {
+            // one pass when every lane holds at most kRec records: the centres go out
+            // at once, w = |p|^2 - r^2 waits in registers until no lane reads the frames
+            // that the radius and w rows overwrite
+            const bool in = tid < span;
+            const int c0 = in ? tid / GS : 0;
+            const int s = tid - c0 * GS;
+            const int fs = in ? tm->slot_frame[s] : -1;
+            const float4 L = in ? tm->slot_local[s] : make_float4(0.f, 0.f, 0.f, 0.f);
+            float wv[kRec];
             float r2max = 0.f;
-            for (int idx = tid; idx < span; idx += WG) {
-                const int c0 = idx / GS;
-                const int s = idx - c0 * GS;
-                const float r = tm->slot_local[s].w;
-                for (int c = c0; c < nv; c += cstep) {
-                    float* row = sp + (long long)c * TS + s;
-                    float w = kFar;
-                    if (r > 0.f) {
-                        const float x = row[0], y = row[GSp], z = row[2 * GSp];
+#pragma unroll
+            for (int m = 0; m < kRec; ++m) {
+                const int c = c0 + m * cstep;
+                wv[m] = kFar;
+                if (in && c < nv) {
+                    float x = 0.f, y = 0.f, z = 0.f;
+                    if (fs >= 0) {
+                        const float4 X = place32(reinterpret_cast<const float4*>(sp + c * TS + fr_off) + fs * 3, L);
+                        x = X.x;
+                        y = X.y;
+                        z = X.z;
+                    }
+                    float* row = sp + c * TS + s;
+                    row[0] = x;
+                    row[GSp] = y;
+                    row[2 * GSp] = z;
+                    if (L.w > 0.f) {
                         const float d2 = fmaf(x, x, fmaf(y, y, z * z));
-                        w = fmaf(-r, r, d2);
+                        wv[m] = fmaf(-L.w, L.w, d2);
                         r2max = fmaxf(r2max, d2);
                     }
-                    row[3 * GSp] = r;
-                    row[4 * GSp] = w;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < kRec; ++m) {
+                const int c = c0 + m * cstep;
+                if (in && c < nv) {
+                    float* row = sp + c * TS + s;
+                    row[3 * GSp] = L.w;
+                    row[4 * GSp] = wv[m];
                 }
             }
             r2max = wave_max_f32(r2max);
             if (lane == 0) atomicMax(&s_rho2, __float_as_uint(r2max));
+            __syncthreads();
+        } else {
+            // First the centres relative to the team origin (padding slots at the origin) ...
+            for (int idx = tid; idx < span; idx += WG) {
+                const int c0 = idx / GS;
+                const int s = idx - c0 * GS;
+                const int fs = tm->slot_frame[s];
+                const float4 L = tm->slot_local[s];
+                for (int c = c0; c < nv; c += cstep) {
+                    float x = 0.f, y = 0.f, z = 0.f;
+                    if (fs >= 0) {
+                        const float4 X = place32(reinterpret_cast<const float4*>(sp + (long long)c * TS + fr_off) + fs * 3, L);
+                        x = X.x;
+                        y = X.y;
+                        z = X.z;
+                    }
+                    float* row = sp + (long long)c * TS + s;
+                    row[0] = x;
+                    row[GSp] = y;
+                    row[2 * GSp] = z;
+                }
+            }
+            __syncthreads();
+
+            // ... then, over the frames, the radius and w = |p|^2 - r^2 rows (radius 0 and
+            // w far away for padding)
+            {
+                float r2max = 0.f;
+                for (int idx = tid; idx < span; idx += WG) {
+                    const int c0 = idx / GS;
+                    const int s = idx - c0 * GS;
+                    const float r = tm->slot_local[s].w;
+                    for (int c = c0; c < nv; c += cstep) {
+                        float* row = sp + (long long)c * TS + s;
+                        float w = kFar;
+                        if (r > 0.f) {
+                            const float x = row[0], y = row[GSp], z = row[2 * GSp];
+                            const float d2 = fmaf(x, x, fmaf(y, y, z * z));
+                            w = fmaf(-r, r, d2);
+                            r2max = fmaxf(r2max, d2);
+                        }
+                        row[3 * GSp] = r;
+                        row[4 * GSp] = w;
+                    }
+                }
+                r2max = wave_max_f32(r2max);
+                if (lane == 0) atomicMax(&s_rho2, __float_as_uint(r2max));
+            }
+            __syncthreads();
         }
-        __syncthreads();
 
         // The obstacle phase and the pair phase, in the call's order: early-terminating
         // MV may run the pairs first (MRV_PAIRS_FIRST), so that their hits end a tile
