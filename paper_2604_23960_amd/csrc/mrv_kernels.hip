@@ -1617,32 +1617,19 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? (PT
                         // robot-robot blocks against the higher robots
                         if (gs < G && !(found && !exhaustive)) {
                             const floatx4 acc = { cw.x, cw.y, cw.z, cw.w };
-                            // MV: all higher robots in one sweep, unless ga's robot is outside the
-                            // focus set; then robot by robot, over those in it
-                            const bool sweep = kMV && a_in && !prio;
-                            const int rb_end = sweep ? ra + 2 : n;
-                            const unsigned pri = prio ? (unsigned)cload(reinterpret_cast<const int*>(tm->r_pri) + ra) : 0u;
-                            for (int rb = ra + 1; rb < rb_end; ++rb) {
-                                if (!a_in && !((focus >> rb) & 1u)) continue;
-                                if (prio && (((pri >> rb) & 1u) != 0u) != (pass == 0)) continue;
-                                const int g0 = sweep ? gs : cload(tm->r_group_off + rb);
-                                const int g1 = sweep ? G : cload(tm->r_group_off + rb + 1);
-                                if (!a_in || prio)
-                                    c_rr += (unsigned long long)ga_n *
-                                            (unsigned)(cload(tm->r_sphere_off + rb + 1) - cload(tm->r_sphere_off + rb));
-                                const unsigned key = kMV ? 0u : (unsigned)t * (unsigned)tm->P + pair_index(ra, rb, n);
-                                if (!kMV && !exhaustive && key >= flag_read(&s_key)) break;
+                            // the lane's minimum of D over column groups [g0, g1)
+                            auto blocks_min = [&](int g0, int g1) {
                                 float best = 3.0e38f;
                                 int g = g0;
                                 for (; g + 4 <= g1; g += 4) {
                                     float bop[4], wb[4];
                                     floatx4 d[4];
-    #pragma unroll
+#pragma unroll
                                     for (int v = 0; v < 4; ++v) {
                                         bop[v] = base[q4 * GSp + (g + v) * 16 + i16];
                                         wb[v] = base[4 * GSp + (g + v) * 16 + i16];
                                     }
-    #pragma unroll
+#pragma unroll
                                     for (int v = 0; v < 4; ++v) d[v] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, bop[v], acc, 0, 0, 0);
                                     best = fminf(best, fminf(fminf(col_min(d[0], wb[0]), col_min(d[1], wb[1])),
                                                              fminf(col_min(d[2], wb[2]), col_min(d[3], wb[3]))));
@@ -1653,6 +1640,30 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? (PT
                                     const floatx4 d = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, bop, acc, 0, 0, 0);
                                     best = block_min(d, wb, best);
                                 }
+                                return best;
+                            };
+                            // exhaustive FFC: one sweep over every higher robot's groups first;
+                            // the robots run one by one (each pair its own key) only where a lane
+                            // of the sweep comes within the band.  The blocks' values are the
+                            // same in both, so a sweep clear of the band clears every pair.
+                            bool near_any = true;
+                            if constexpr (KIND == 4) near_any = __ballot(blocks_min(gs, G) < e_hi) != 0ull;
+                            // MV: all higher robots in one sweep, unless ga's robot is outside the
+                            // focus set; then robot by robot, over those in it
+                            const bool sweep = kMV && a_in && !prio;
+                            const int rb_end = sweep ? ra + 2 : n;
+                            const unsigned pri = prio ? (unsigned)cload(reinterpret_cast<const int*>(tm->r_pri) + ra) : 0u;
+                            for (int rb = ra + 1; near_any && rb < rb_end; ++rb) {
+                                if (!a_in && !((focus >> rb) & 1u)) continue;
+                                if (prio && (((pri >> rb) & 1u) != 0u) != (pass == 0)) continue;
+                                const int g0 = sweep ? gs : cload(tm->r_group_off + rb);
+                                const int g1 = sweep ? G : cload(tm->r_group_off + rb + 1);
+                                if (!a_in || prio)
+                                    c_rr += (unsigned long long)ga_n *
+                                            (unsigned)(cload(tm->r_sphere_off + rb + 1) - cload(tm->r_sphere_off + rb));
+                                const unsigned key = kMV ? 0u : (unsigned)t * (unsigned)tm->P + pair_index(ra, rb, n);
+                                if (!kMV && !exhaustive && key >= flag_read(&s_key)) break;
+                                const float best = blocks_min(g0, g1);
                                 // common case first: every pair of the lane clear beyond the band
                                 bool hit = false;
                                 if (__ballot(best < e_hi)) {
