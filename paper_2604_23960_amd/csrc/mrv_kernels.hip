@@ -1642,12 +1642,13 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? (PT
                                 }
                                 return best;
                             };
-                            // exhaustive FFC: one sweep over every higher robot's groups first;
-                            // the robots run one by one (each pair its own key) only where a lane
-                            // of the sweep comes within the band.  The blocks' values are the
-                            // same in both, so a sweep clear of the band clears every pair.
+                            // FFC with two or more higher robots: one sweep over all their groups
+                            // first; the robots run one by one (each pair its own key) only where
+                            // a lane of the sweep comes within the band.  The blocks' values are
+                            // the same in both, so a sweep clear of the band clears every pair.
                             bool near_any = true;
-                            if constexpr (KIND == 4) near_any = __ballot(blocks_min(gs, G) < e_hi) != 0ull;
+                            if constexpr (!kMV)
+                                if (ra + 2 < n) near_any = __ballot(blocks_min(gs, G) < e_hi) != 0ull;
                             // MV: all higher robots in one sweep, unless ga's robot is outside the
                             // focus set; then robot by robot, over those in it
                             const bool sweep = kMV && a_in && !prio;
