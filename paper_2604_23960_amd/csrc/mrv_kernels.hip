@@ -1548,10 +1548,16 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? (PT
                                         best[i] = block_min(d, wb, best[i]);
                                     }
                                 }
+                                c_self += self_tests * (unsigned long long)min(kSI, nv - c0);
+                                // common case first: no lane within the band at any of the timesteps
+                                // (a repeated timestep's minimum equals its original's)
+                                float bmin = best[0];
+#pragma unroll
+                                for (int i = 1; i < kSI; ++i) bmin = fminf(bmin, best[i]);
+                                if (!__ballot(bmin < e_hi)) continue;
 #pragma unroll
                                 for (int i = 0; i < kSI; ++i) {
                                     if (c0 + i < nv) {
-                                        c_self += self_tests;
                                         const int t = s_t[c0 + i];
                                         const float* base = sp + (long long)(c0 + i) * TS;
                                         bool hit = false;
