@@ -1605,18 +1605,21 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? (PT
                                 const floatx4 d = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, bop, acc, 0, 0, 0);
                                 best = block_min(d, wb, best);
                             }
-                            bool hit = best < e_lo;
-                            const bool unsure = !hit && best < e_hi;
-                            if (!__ballot(hit) && __ballot(unsure) && unsure) {
-                                for (int sb = sb0; sb < sb1 && !hit; ++sb) {
-                                    const int gb = cload(tm->sblocks + 16 * sb + 1);
-                                    const unsigned long long* mk = sb_masks(tm, sb);
-                                    hit = direct_block(cd, tm, base, GSp, ga, gb, lane, mk, eps, q, t, RK_SELF, 0u, &s_hit, &s_key, true);
+                            // common case first: every pair of the lane clear beyond the band
+                            if (__ballot(best < e_hi)) {
+                                bool hit = best < e_lo;
+                                const bool unsure = !hit && best < e_hi;
+                                if (!__ballot(hit) && __ballot(unsure) && unsure) {
+                                    for (int sb = sb0; sb < sb1 && !hit; ++sb) {
+                                        const int gb = cload(tm->sblocks + 16 * sb + 1);
+                                        const unsigned long long* mk = sb_masks(tm, sb);
+                                        hit = direct_block(cd, tm, base, GSp, ga, gb, lane, mk, eps, q, t, RK_SELF, 0u, &s_hit, &s_key, true);
+                                    }
                                 }
-                            }
-                            if (__ballot(hit)) {
-                                found = true;
-                                if (lane == 0) s_hit = 1;
+                                if (__ballot(hit)) {
+                                    found = true;
+                                    if (lane == 0) s_hit = 1;
+                                }
                             }
                         }
 
@@ -1672,15 +1675,13 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? (PT
                                 if (!kMV && !exhaustive && key >= flag_read(&s_key)) break;
                                 const float best = blocks_min(g0, g1);
                                 // common case first: every pair of the lane clear beyond the band
-                                bool hit = false;
-                                if (__ballot(best < e_hi)) {
-                                    hit = best < e_lo;
-                                    const bool unsure = !hit && best < e_hi;
-                                    if (!__ballot(hit) && __ballot(unsure) && unsure) {
-                                        for (int gg = g0; gg < g1 && !hit; ++gg)
-                                            hit = direct_block(cd, tm, base, GSp, ga, gg, lane, nullptr, eps, q, t, RK_RR, key,
-                                                               &s_hit, &s_key, kMV);
-                                    }
+                                if (!__ballot(best < e_hi)) continue;
+                                bool hit = best < e_lo;
+                                const bool unsure = !hit && best < e_hi;
+                                if (!__ballot(hit) && __ballot(unsure) && unsure) {
+                                    for (int gg = g0; gg < g1 && !hit; ++gg)
+                                        hit = direct_block(cd, tm, base, GSp, ga, gg, lane, nullptr, eps, q, t, RK_RR, key,
+                                                           &s_hit, &s_key, kMV);
                                 }
                                 if (__ballot(hit)) {
                                     found = true;
