@@ -66,6 +66,22 @@ typedef const __attribute__((address_space(4))) unsigned long long CU64;
 __device__ __forceinline__ int cload(const int* p) { return *(CInt*)p; }
 __device__ __forceinline__ float cloadf(const float* p) { return *(CFloat*)p; }
 __device__ __forceinline__ unsigned long long cload64(const unsigned long long* p) { return *(CU64*)p; }
+typedef int int8v __attribute__((ext_vector_type(8)));
+typedef const __attribute__((address_space(4))) int8v CInt8;
+// Eight ints at a 32-byte aligned wave-uniform address, as one scalar load.
+__device__ __forceinline__ int8v cload8(const int* p) { return *(CInt8*)p; }
+typedef int int16v __attribute__((ext_vector_type(16)));
+typedef const __attribute__((address_space(4))) int16v CInt16;
+// Sixteen ints at a 64-byte aligned wave-uniform address, as one scalar load.
+__device__ __forceinline__ int16v cload16(const int* p) { return *(CInt16*)p; }
+typedef float float8v __attribute__((ext_vector_type(8)));
+typedef float float16v __attribute__((ext_vector_type(16)));
+typedef const __attribute__((address_space(4))) float8v CFloat8;
+typedef const __attribute__((address_space(4))) float16v CFloat16;
+__device__ __forceinline__ unsigned long long u64_of(int lo, int hi)
+{
+    return (unsigned long long)(unsigned)lo | ((unsigned long long)(unsigned)hi << 32);
+}
 
 // Descriptors read in place through the constant address space (scalar loads).
 // A phase takes its own pointer from at(): the address is opaque to the compiler,
@@ -595,7 +611,8 @@ __device__ __forceinline__ float row_max16(float v)
 
 // Squared distance from x to a box surface region (0 inside), box in the
 // precomputed row form of EnvDev::box32.
-__device__ __forceinline__ float box_val(float x, float y, float z, CFloat* B)
+template <class V>
+__device__ __forceinline__ float box_val(float x, float y, float z, const V& B)
 {
     const float p0 = fmaf(B[0], x, fmaf(B[1], y, fmaf(B[2], z, B[3])));
     const float p1 = fmaf(B[4], x, fmaf(B[5], y, fmaf(B[6], z, B[7])));
@@ -606,7 +623,8 @@ __device__ __forceinline__ float box_val(float x, float y, float z, CFloat* B)
     return fmaf(e0, e0, fmaf(e1, e1, e2 * e2));
 }
 
-__device__ __forceinline__ float cyl_val(float x, float y, float z, CFloat* Y)
+template <class V>
+__device__ __forceinline__ float cyl_val(float x, float y, float z, const V& Y)
 {
     const float vx = x - Y[0], vy = y - Y[1], vz = z - Y[2];
     const float h = fmaf(vx, Y[3], fmaf(vy, Y[4], vz * Y[5]));
@@ -1027,13 +1045,16 @@ __device__ __forceinline__ void env_tasks(const CD& cd, CTeam* tm, CEnv* env, co
             n_tested[j] += (unsigned)__popc(m);
             const int nb = min(max(env->n_box - ob, 0), 16);
             const unsigned low = (1u << nb) - 1u;
+            // each box's (cylinder's) row form in one scalar load
             for (unsigned mm = m & low; mm; mm &= mm - 1u) {
                 const int b = ob + __builtin_ctz(mm);
-                mb[j] = fminf(mb[j], box_val(x[j], y[j], z[j], (CFloat*)(env->box32 + b * 16)));
+                const float16v B = *(CFloat16*)(env->box32 + b * 16);
+                mb[j] = fminf(mb[j], box_val(x[j], y[j], z[j], B));
             }
             for (unsigned mm = m & ~low; mm; mm &= mm - 1u) {
                 const int b = ob + __builtin_ctz(mm) - env->n_box;
-                mb[j] = fminf(mb[j], cyl_val(x[j], y[j], z[j], (CFloat*)(env->cyl32 + b * 8)));
+                const float8v Y = *(CFloat8*)(env->cyl32 + b * 8);
+                mb[j] = fminf(mb[j], cyl_val(x[j], y[j], z[j], Y));
             }
         }
     }
@@ -1501,16 +1522,17 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? (PT
                 const int q4 = lane >> 4;
                 for (int k = wave; k < G; k += kWaves) {
                     if (kMV && !exhaustive && flag_read(&s_hit)) break;
-                    const int* tk = tm->gtask + 8 * k;
-                    const int ga = cload(tk + 0);
-                    const int ra = cload(tk + 1);
+                    // the task's 32-byte record in one scalar load
+                    const int8v tk = cload8(tm->gtask + 8 * k);
+                    const int ga = tk[0];
+                    const int ra = tk[1];
                     const bool a_in = fall || ((focus >> ra) & 1u);     // ga's robot in focus
-                    const int sb0 = do_self && a_in ? cload(tk + 2) : 0;
-                    const int sb1 = do_self && a_in ? cload(tk + 3) : 0;
+                    const int sb0 = do_self && a_in ? tk[2] : 0;
+                    const int sb1 = do_self && a_in ? tk[3] : 0;
                     const bool higher_in = ra + 1 < 32 && (focus >> (ra + 1)) != 0u;   // a higher robot in focus
-                    const int gs = do_rr && (a_in || higher_in) ? cload(tk + 4) : G;
-                    const unsigned long long rr_tests = do_rr && a_in && !prio ? (unsigned long long)cload(tk + 5) : 0ull;
-                    const unsigned long long self_tests = do_self && a_in ? (unsigned long long)cload(tk + 6) : 0ull;
+                    const int gs = do_rr && (a_in || higher_in) ? tk[4] : G;
+                    const unsigned long long rr_tests = do_rr && a_in && !prio ? (unsigned long long)tk[5] : 0ull;
+                    const unsigned long long self_tests = do_self && a_in ? (unsigned long long)tk[6] : 0ull;
                     // spheres of group ga, for the test counts of a robot outside the focus set
                     const int ga_n = a_in && !prio ? 0 : cload(reinterpret_cast<const int*>(tm->g_range) + 2 * ga + 1) -
                                                          cload(reinterpret_cast<const int*>(tm->g_range) + 2 * ga);
@@ -1532,10 +1554,11 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? (PT
                                     aop[i] = -2.f * sp[row[i] + q4 * GSp + ga * 16 + i16];
                                 }
                                 for (int sb = sb0; sb < sb1; ++sb) {
-                                    const int gb = cload(tm->sblocks + 16 * sb + 1);
-                                    const unsigned long long* mk = sb_masks(tm, sb);
-                                    const unsigned long long m0 = cload64(mk), m1 = cload64(mk + 1), m2 = cload64(mk + 2),
-                                                             m3 = cload64(mk + 3);
+                                    // the block's 64-byte record (column group, lane masks) in one load
+                                    const int16v rec = cload16(tm->sblocks + 16 * sb);
+                                    const int gb = rec[1];
+                                    const unsigned long long m0 = u64_of(rec[8], rec[9]), m1 = u64_of(rec[10], rec[11]),
+                                                             m2 = u64_of(rec[12], rec[13]), m3 = u64_of(rec[14], rec[15]);
 #pragma unroll
                                     for (int i = 0; i < kSI; ++i) {
                                         const float* base = sp + row[i];
@@ -1596,10 +1619,10 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? (PT
                         if (!kSelfInner && sb0 < sb1) {
                             float best = 3.0e38f;
                             for (int sb = sb0; sb < sb1; ++sb) {
-                                const int gb = cload(tm->sblocks + 16 * sb + 1);
-                                const unsigned long long* mk = sb_masks(tm, sb);
-                                const floatx4 acc = { lane_select(cload64(mk + 0), cw.x, kFar), lane_select(cload64(mk + 1), cw.y, kFar),
-                                                      lane_select(cload64(mk + 2), cw.z, kFar), lane_select(cload64(mk + 3), cw.w, kFar) };
+                                const int16v rec = cload16(tm->sblocks + 16 * sb);
+                                const int gb = rec[1];
+                                const floatx4 acc = { lane_select(u64_of(rec[8], rec[9]), cw.x, kFar), lane_select(u64_of(rec[10], rec[11]), cw.y, kFar),
+                                                      lane_select(u64_of(rec[12], rec[13]), cw.z, kFar), lane_select(u64_of(rec[14], rec[15]), cw.w, kFar) };
                                 const float bop = base[q4 * GSp + gb * 16 + i16];
                                 const float wb = base[4 * GSp + gb * 16 + i16];
                                 const floatx4 d = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, bop, acc, 0, 0, 0);
