@@ -988,11 +988,33 @@ __device__ bool point_blocks(const CD& cd, CTeam* tm, CEnv* env, int a0, float x
 // tests below the known outcome are queued for FP64 re-evaluation.  The kernel
 // passes one task at a time: with boxes and cylinders selected per task, larger
 // J only adds register pressure.
+// World boxes of obstacles ob + lane % 16 and ob + 16 + lane % 16 (empty past nbc).
+struct ObBoxes {
+    float3 lo[2], hi[2];
+};
+__device__ __forceinline__ ObBoxes ob_boxes(CEnv* env, int nbc, int ob, int lane)
+{
+    ObBoxes r;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int o = ob + 16 * k + (lane & 15);
+        r.lo[k] = make_float3(3.0e38f, 3.0e38f, 3.0e38f);
+        r.hi[k] = make_float3(-3.0e38f, -3.0e38f, -3.0e38f);
+        if (o < nbc) {
+            const float4 a = env->bc_box[2 * o], b = env->bc_box[2 * o + 1];
+            r.lo[k] = make_float3(a.x, a.y, a.z);
+            r.hi[k] = make_float3(b.x, b.y, b.z);
+        }
+    }
+    return r;
+}
+
 template <int J, bool PTS, class CD>
 __device__ __forceinline__ void env_tasks(const CD& cd, CTeam* tm, CEnv* env, const float* sp,
                                           const int* task, int nch, float ro_max, float eps, bool exhaustive, int q,
                                           unsigned focus, bool fall, const int* s_t, int* s_hit,
-                                          unsigned& c_env, unsigned long long* s_npt, int lane, float3 off)
+                                          unsigned& c_env, unsigned long long* s_npt, int lane, float3 off,
+                                          const ObBoxes& pre)
 {
     const int GS = tm->GS, GSp = tm->GSp, TS = tm->TS;
     int c[J], a[J];
@@ -1032,13 +1054,7 @@ __device__ __forceinline__ void env_tasks(const CD& cd, CTeam* tm, CEnv* env, co
         const float lz = row_min16(act[j] ? z[j] - w : 3.0e38f), hz = row_max16(act[j] ? z[j] + w : -3.0e38f);
         // lane l compares the box of its own row with obstacle ob + l % 16, so a
         // ballot covers 16 obstacles against all four rows
-        for (int ob = 0; ob < nbc; ob += 16) {
-            const int o = ob + (lane & 15);
-            float4 olo = make_float4(3.0e38f, 3.0e38f, 3.0e38f, 0.f), ohi = make_float4(-3.0e38f, -3.0e38f, -3.0e38f, 0.f);
-            if (o < nbc) {
-                olo = env->bc_box[2 * o];
-                ohi = env->bc_box[2 * o + 1];
-            }
+        auto group = [&](int ob, float3 olo, float3 ohi) {
             const unsigned long long m4 = __ballot((olo.x <= hx) & (ohi.x >= lx) & (olo.y <= hy) & (ohi.y >= ly) &
                                                    (olo.z <= hz) & (ohi.z >= lz));
             const unsigned m = (unsigned)((m4 | (m4 >> 16) | (m4 >> 32) | (m4 >> 48)) & 0xFFFFull);
@@ -1056,6 +1072,19 @@ __device__ __forceinline__ void env_tasks(const CD& cd, CTeam* tm, CEnv* env, co
                 const float8v Y = *(CFloat8*)(env->cyl32 + b * 8);
                 mb[j] = fminf(mb[j], cyl_val(x[j], y[j], z[j], Y));
             }
+        };
+        // the first 32 obstacles' world boxes come in registers (loaded once per tile;
+        // not in the point-cloud build, whose grid walk needs the registers), the rest
+        // from memory
+        int ob = 0;
+        if constexpr (!PTS) {
+            group(0, pre.lo[0], pre.hi[0]);
+            if (nbc > 16) group(16, pre.lo[1], pre.hi[1]);
+            ob = 32;
+        }
+        for (; ob < nbc; ob += 16) {
+            const ObBoxes more = ob_boxes(env, nbc, ob, lane);
+            group(ob, more.lo[0], more.hi[0]);
         }
     }
     for (int o = 0; o < env->n_sph; ++o) {
@@ -1474,11 +1503,12 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? (PT
                 for (int o = 0; o < env->n_sph; ++o) ro_max = fmaxf(ro_max, cloadf(&env->sph32[o].w));
                 // tasks wave, wave + kWaves, ... of this wave, one at a time, so that in
                 // early-terminating calls a hit stops the wave before its next task
+                const ObBoxes pre = PTS ? ObBoxes{} : ob_boxes(env, env->n_box + env->n_cyl, 0, lane);
                 int task = wave;
                 for (; task < ntask && !(!exhaustive && flag_read(&s_hit)); task += kWaves) {
                     const int tk[1] = { task };
                     env_tasks<1, PTS>(cd, tm, env, sp, tk, nch, ro_max, eps, exhaustive, q, focus, fall, s_t, &s_hit, c_env,
-                                 &s_npt, lane, off);
+                                 &s_npt, lane, off, pre);
                 }
             }
 
