@@ -9,7 +9,8 @@ over all 65,536 motions.  ``value`` = robot-states validated per second.
 Also reported (``extra``): early-exit MV on the same motions, FFC on the
 4-arm + 4-rectangle decoupled-path workload (16,384 path sets), the disk
 workload, the FP32 roofline of the validation kernel and the FP64 oracle on the
-host cores (``cpu_baseline``).
+host cores (``cpu_baseline``).  ``--cloud-exhaustive N`` and ``--ffc-only N``
+run only the profiled configurations of the point-cloud and FFC kernels.
 """
 from __future__ import annotations
 
@@ -469,6 +470,29 @@ def cloud_exhaustive(n_motions, steps, warmup, log):
     return res
 
 
+def ffc_only(n_paths, steps, warmup, log):
+    """Early-terminating and exhaustive FFC of the arm + rectangle team over n_paths
+    path sets (the profiled configuration of the FFC kernels)."""
+    import torch
+    from paper_2604_23960_amd import mrv
+    from paper_2604_23960_amd import workloads as W
+    wf = W.ffc_workload(n_paths)
+    ctx = mrv.Context(0)
+    tf = ctx.load_team(wf.team)
+    dpf = mrv.DevicePaths(wf.paths)
+    cf = torch.zeros((wf.paths.n_queries, 3), dtype=torch.int32, device="cuda")
+    res = dict(workload="arms4+rects4 FFC", path_sets=wf.paths.n_queries, steps=steps)
+    for name, flags, kname in (("early", 0, "k_validate<1, false> (early-terminating FFC)"),
+                               ("exhaustive", mrv.EXHAUSTIVE, "k_validate<4, false> (exhaustive FFC)")):
+        log(f"timing {name} FFC over {wf.paths.n_queries} path sets")
+        wall, kms, st = run_device(ctx, tf, -1, dpf, 1, flags, cf, steps, warmup)
+        res[name] = dict(ms_per_step=wall / steps * 1e3, states_evaluated=st["states_evaluated"],
+                         rr_tests=st["rr_tests"],
+                         roofline=roofline_of(wf.team, None, st, float(np.mean(kms)), kname))
+    ctx.close()
+    return res
+
+
 def cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -571,6 +595,8 @@ def main():
                     help="also write the ordering study's JSON record to this file")
     ap.add_argument("--cloud-exhaustive", type=int, default=0, metavar="MOTIONS",
                     help="only time exhaustive MV of the 16-robot point-cloud team over this many motions")
+    ap.add_argument("--ffc-only", type=int, default=0, metavar="PATH_SETS",
+                    help="only time FFC (early-terminating and exhaustive) of the arm + rectangle team")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
@@ -597,6 +623,12 @@ def main():
         if args.copy_calib_mib > 0:
             calibration_copy(args.copy_calib_mib, log)
         print(json.dumps(cloud_exhaustive(args.cloud_exhaustive, args.steps, args.warmup, log)), flush=True)
+        return
+
+    if args.ffc_only > 0:
+        if args.copy_calib_mib > 0:
+            calibration_copy(args.copy_calib_mib, log)
+        print(json.dumps(ffc_only(args.ffc_only, args.steps, args.warmup, log)), flush=True)
         return
 
     if args.copy_calib_mib > 0:
