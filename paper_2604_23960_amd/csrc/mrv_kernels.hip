@@ -1222,9 +1222,10 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? (PT
 
     for (;;) {
         // Wave priorities in exhaustive calls: the serial part of a tile (claim, FK,
-        // records; one busy wave per workgroup) issues first, then the pair phase's
-        // MFMA chains, while the obstacle phase's long VALU streams fill the gaps
-        // (early-terminating calls keep one level: their obstacle verdicts end queries).
+        // records; one busy wave per workgroup) issues first, then the obstacle
+        // phase, while the pair phase's MFMA chains, which wait on the matrix pipe
+        // anyway, fill the gaps (early-terminating calls keep one level: their
+        // obstacle verdicts end queries).
         if (exhaustive) __builtin_amdgcn_s_setprio(2);
         if (tid == 0) {
             CCall& cd = call_at();
@@ -1486,7 +1487,7 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? (PT
         // MV may run the pairs first (MRV_PAIRS_FIRST), so that their hits end a tile
         // before costly obstacle tests; exhaustive MV and FFC keep a fixed order.
         auto env_phase = [&]() {
-            if (exhaustive) __builtin_amdgcn_s_setprio(0);
+            if (exhaustive) __builtin_amdgcn_s_setprio(1);
             // --- robot-obstacle tests (MV with environment checking): one lane per
             // (timestep, slot); obstacle parameters are wave-uniform scalar loads.
             if (do_env && epu) {
@@ -1514,7 +1515,7 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? (PT
 
         };
         auto pair_phase = [&]() {
-            if (exhaustive) __builtin_amdgcn_s_setprio(1);
+            if (exhaustive) __builtin_amdgcn_s_setprio(0);
             // --- sphere-pair tests as 16 x 16 blocks on the matrix cores.  For slots a
             // (rows, group ga) and b (columns, group gb) at one timestep,
             //   D(a, b) = w_a + w_b - 2 p_a.p_b - 2 r_a r_b = |p_a - p_b|^2 - (r_a + r_b)^2,
