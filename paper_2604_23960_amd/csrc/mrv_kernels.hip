@@ -1222,10 +1222,10 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? (PT
 
     for (;;) {
         // Wave priorities in exhaustive calls: the serial part of a tile (claim, FK,
-        // records; one busy wave per workgroup) issues first, then the obstacle
-        // phase, while the pair phase's MFMA chains, which wait on the matrix pipe
-        // anyway, fill the gaps (early-terminating calls keep one level: their
-        // obstacle verdicts end queries).
+        // records; one busy wave per workgroup) and the obstacle phase issue first,
+        // then the self blocks, while the robot-robot blocks' MFMA chains, which wait
+        // on the matrix pipe anyway, fill the gaps (early-terminating calls keep one
+        // level: their obstacle verdicts end queries).
         if (exhaustive) __builtin_amdgcn_s_setprio(2);
         if (tid == 0) {
             CCall& cd = call_at();
@@ -1487,7 +1487,7 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? (PT
         // MV may run the pairs first (MRV_PAIRS_FIRST), so that their hits end a tile
         // before costly obstacle tests; exhaustive MV and FFC keep a fixed order.
         auto env_phase = [&]() {
-            if (exhaustive) __builtin_amdgcn_s_setprio(1);
+            if (exhaustive) __builtin_amdgcn_s_setprio(2);
             // --- robot-obstacle tests (MV with environment checking): one lane per
             // (timestep, slot); obstacle parameters are wave-uniform scalar loads.
             if (do_env && epu) {
@@ -1569,6 +1569,7 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? (PT
                                                          cload(reinterpret_cast<const int*>(tm->g_range) + 2 * ga);
                     if (sb0 == sb1 && gs >= G) continue;
                     if constexpr (kSelfInner) {
+                        __builtin_amdgcn_s_setprio(1);
                         // exhaustive MV: the self blocks of ga for up to kSI timesteps at a time,
                         // each block's record loaded once and its MFMAs independent
                         if (sb0 < sb1) {
@@ -1630,6 +1631,7 @@ __global__ __launch_bounds__(validate_wg(KIND), KIND <= 2 ? 2 : (KIND == 3 ? (PT
                             }
                         }
                         if (gs >= G) continue;
+                        __builtin_amdgcn_s_setprio(0);
                     }
                     for (int c = 0; c < nv; ++c) {
                         const int t = s_t[c];
