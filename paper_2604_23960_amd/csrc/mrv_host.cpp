@@ -276,6 +276,27 @@ int build_team(mrv_ctx ctx, const mrv_robot_desc* robots, int n, TeamHost& out)
                                  (g_range[2 * g + 1] - g_range[2 * g]) * (S - r_sphere_off[r + 1]), self_tests, 0 };
             gtask.insert(gtask.end(), rec, rec + 8);
         }
+        // Waves take the tasks round-robin (task k to wave k mod waves), so the tasks
+        // are dealt heaviest first in a snake order over four waves: each wave gets a
+        // like share of the blocks (a self block weighs 1.5 robot-robot blocks, a task
+        // its own set-up one more), and eight waves see pairs of such rounds.
+        std::vector<int> ord(G);
+        std::vector<double> wt(G);
+        for (int g = 0; g < G; ++g) {
+            ord[g] = g;
+            wt[g] = (G - gtask[8 * g + 4]) + 1.5 * (gtask[8 * g + 3] - gtask[8 * g + 2]) + 1.0;
+        }
+        std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return wt[a] > wt[b]; });
+        std::vector<int> dealt(gtask.size());
+        for (int i = 0; i < G; ++i) {
+            const int round = i / 4, lane = i % 4;
+            const int pos = 4 * round + ((round & 1) ? 3 - lane : lane);
+            // a last, partial round keeps its tasks in the first positions it has
+            const int last = std::min(G, 4 * round + 4) - 4 * round;
+            const int p = (round & 1) && last < 4 ? 4 * round + (last - 1 - lane) : pos;
+            std::copy(gtask.begin() + 8 * ord[i], gtask.begin() + 8 * ord[i] + 8, dealt.begin() + 8 * p);
+        }
+        gtask.swap(dealt);
     }
     float r_max = 0.f;
     for (int s2 = 0; s2 < S; ++s2) r_max = std::max(r_max, s_local32[s2 * 4 + 3]);
